@@ -269,7 +269,8 @@ int oracle_moore(uint32_t n, uint32_t k, const uint32_t *delta,
   if (rc) return rc;
   uint32_t *block = (uint32_t *)malloc(sizeof(uint32_t) * n);
   if (!block) return -2;
-  for (uint32_t q = 0; q < n; ++q) block[q] = ACC(accept, q) ? 0u : 1u;
+  /* {F, Q\F}; labels must stay below n, so a lone state is labelled 0 */
+  for (uint32_t q = 0; q < n; ++q) block[q] = (ACC(accept, q) || n == 1) ? 0u : 1u;
   rc = moore_core(n, k, delta, block, max_rounds, 0, out, num_blocks, refine_rounds);
   free(block);
   return rc;
@@ -282,7 +283,7 @@ int oracle_moore_partial(uint32_t n, uint32_t k, const uint32_t *delta,
   if (rc) return rc;
   uint32_t *block = (uint32_t *)malloc(sizeof(uint32_t) * n);
   if (!block) return -2;
-  for (uint32_t q = 0; q < n; ++q) block[q] = ACC(accept, q) ? 0u : 1u;
+  for (uint32_t q = 0; q < n; ++q) block[q] = (ACC(accept, q) || n == 1) ? 0u : 1u;
   if (rounds == 0) {
     uint32_t c = oracle_canonicalize(n, block, out);
     if (num_blocks) *num_blocks = c;

@@ -36,8 +36,8 @@ uint64_t oracle_exhaustive_check(uint32_t n, uint32_t k, uint64_t *mismatches) {
       int ok = !e1 && !e2 && !e3 && c1 == c2 && c2 == c3 &&
                !memcmp(o1, o2, n * sizeof(uint32_t)) &&
                !memcmp(o2, o3, n * sizeof(uint32_t));
-      /* Moore refines at most n-2 times (n >= 2). */
-      if (n >= 2 && r > n - 2) ok = 0;
+      /* Moore refines at most n-2 times for n >= 2, never for n = 1. */
+      if (r > (n >= 2 ? n - 2 : 0)) ok = 0;
       if (n <= 4) {
         int e4 = oracle_word_equivalence(n, k, delta, acc, o4, &c4);
         ok = ok && !e4 && c4 == c1 && !memcmp(o1, o4, n * sizeof(uint32_t));

@@ -325,11 +325,13 @@ def test_invariants(seed):
 
 @pytest.mark.parametrize("n", [1, 2, 7, 64])
 def test_degenerate_accepting_sets(n):
+    """F empty or F = Q (and any single state): one class, no refining round."""
     for acc in (np.zeros(n, bool), np.ones(n, bool)):
         d = W.random_dfa(n, 3, n)
         d.accept = W.pack_accept(acc)
         out, nb = _all_algorithms(d)
         assert nb == 1 and not out.any()
+        assert oracle.moore(d.n, d.k, d.delta, d.accept)[2] == 0
 
 
 def test_reachability_of_random_dfa():
