@@ -1,0 +1,335 @@
+// capi.hip -- the extern "C" boundary of libdfamin (declared in dfamin.h).
+//
+// Argument checks happen here on the host; everything the method computes
+// happens in the kernels driven by Engine.  No exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/dfamin.h"
+#include "engine.h"
+#include "serving.h"
+
+struct dfamin_ctx {
+  dfamin::Context c;
+};
+
+namespace {
+
+using dfamin::Context;
+using dfamin::InstInput;
+using dfamin::InstOutcome;
+
+int check_dfa_shape(const dfamin_dfa* d) {
+  if (!d || !d->delta || !d->accept) return DFAMIN_E_INVAL;
+  if (d->n == 0 || d->k == 0 || d->q0 >= d->n) return DFAMIN_E_INVAL;
+  if ((uint64_t)d->n * d->k > (1ull << 40)) return DFAMIN_E_INVAL;
+  return DFAMIN_OK;
+}
+
+int check_opts(const dfamin_opts* o) {
+  if (o && o->closure > DFAMIN_CLOSURE_AUTO) return DFAMIN_E_INVAL;
+  return DFAMIN_OK;
+}
+
+dfamin_opts opts_or_default(const dfamin_opts* o) {
+  dfamin_opts d{};
+  if (o) d = *o;
+  return d;
+}
+
+void to_result(const InstOutcome& o, dfamin_result* r) {
+  if (!r) return;
+  r->num_blocks = o.num_blocks;
+  r->initial_block = o.initial_block;
+  r->refine_rounds = o.refine_rounds;
+  r->rounds_executed = o.rounds_executed;
+  r->closure_levels = o.closure_levels;
+  r->closure_letters = o.closure_letters;
+  r->status = o.status;
+  r->reserved = 0;
+}
+
+int set_device(Context& c) {
+  if (c.device_lost) return DFAMIN_E_DEVICE;
+  return hipSetDevice(c.device) == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
+}
+
+int ensure(Context& c, dfamin::DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return DFAMIN_OK;
+  if (b.p) {
+    (void)hipFree(b.p);
+    c.used -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t want = (bytes + bytes / 8 + 4095) & ~size_t(4095);
+  if (c.used + want > c.budget) {
+    want = (bytes + 4095) & ~size_t(4095);
+    if (c.used + want > c.budget) return DFAMIN_E_NOMEM;
+  }
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return DFAMIN_E_NOMEM;
+  }
+  b.cap = want;
+  c.used += want;
+  return DFAMIN_OK;
+}
+
+int ensure_host(dfamin::HostBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 64;
+  if (b.cap >= bytes) return DFAMIN_OK;
+  if (b.p) (void)hipHostFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  size_t want = bytes + bytes / 8 + 64;
+  if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+    b.p = nullptr;
+    return DFAMIN_E_NOMEM;
+  }
+  b.cap = want;
+  return DFAMIN_OK;
+}
+
+inline size_t accept_bytes(uint32_t n) { return ((size_t)n + 7) / 8; }
+inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// Host-input batch: pack every instance into pinned staging, one H2D copy,
+// run, one D2H copy, scatter into the caller's buffers.
+int run_host_batch(Context& c, uint32_t count, const dfamin_dfa* dfas, const dfamin_opts& o,
+                   uint32_t* const* outs, dfamin_result* results) {
+  std::vector<size_t> d_off(count), a_off(count), o_off(count);
+  size_t in_bytes = 0, out_bytes = 0;
+  for (uint32_t i = 0; i < count; ++i) {
+    d_off[i] = in_bytes;
+    in_bytes = align16(in_bytes + 4ull * dfas[i].n * dfas[i].k);
+    a_off[i] = in_bytes;
+    in_bytes = align16(in_bytes + accept_bytes(dfas[i].n));
+    o_off[i] = out_bytes;
+    out_bytes = align16(out_bytes + 4ull * dfas[i].n);
+  }
+  int rc;
+  if ((rc = ensure_host(c.h_in, in_bytes)) != DFAMIN_OK) return rc;
+  if ((rc = ensure_host(c.h_out, out_bytes)) != DFAMIN_OK) return rc;
+  if ((rc = ensure(c, c.in_delta, in_bytes)) != DFAMIN_OK) return rc;
+  if ((rc = ensure(c, c.in_out, out_bytes)) != DFAMIN_OK) return rc;
+  char* hin = c.h_in.as<char>();
+  for (uint32_t i = 0; i < count; ++i) {
+    std::memcpy(hin + d_off[i], dfas[i].delta, 4ull * dfas[i].n * dfas[i].k);
+    std::memcpy(hin + a_off[i], dfas[i].accept, accept_bytes(dfas[i].n));
+  }
+  if (hipMemcpyAsync(c.in_delta.p, hin, in_bytes, hipMemcpyHostToDevice, c.stream) != hipSuccess)
+    return DFAMIN_E_DEVICE;
+  std::vector<InstInput> in(count);
+  char* dbase = c.in_delta.as<char>();
+  char* obase = c.in_out.as<char>();
+  for (uint32_t i = 0; i < count; ++i) {
+    in[i].n = dfas[i].n;
+    in[i].k = dfas[i].k;
+    in[i].q0 = dfas[i].q0;
+    in[i].closure = o.closure;
+    in[i].delta = reinterpret_cast<const uint32_t*>(dbase + d_off[i]);
+    in[i].accept = reinterpret_cast<const uint8_t*>(dbase + a_off[i]);
+    in[i].out = reinterpret_cast<uint32_t*>(obase + o_off[i]);
+  }
+  std::vector<InstOutcome> res;
+  rc = c.engine.run(in, o, c.stream, res);
+  if (rc == DFAMIN_E_BAD_DFA) {
+    for (uint32_t i = 0; i < count; ++i) to_result(res[i], results ? &results[i] : nullptr);
+    return rc;
+  }
+  if (rc != DFAMIN_OK) return rc;
+  if (hipMemcpyAsync(c.h_out.p, obase, out_bytes, hipMemcpyDeviceToHost, c.stream) != hipSuccess)
+    return DFAMIN_E_DEVICE;
+  if (hipStreamSynchronize(c.stream) != hipSuccess) return DFAMIN_E_DEVICE;
+  const char* hout = c.h_out.as<char>();
+  for (uint32_t i = 0; i < count; ++i) {
+    std::memcpy(outs[i], hout + o_off[i], 4ull * dfas[i].n);
+    to_result(res[i], results ? &results[i] : nullptr);
+  }
+  return DFAMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dfamin_create(int hip_device, uint64_t hbm_budget_bytes, dfamin_ctx** out) {
+  if (!out) return DFAMIN_E_INVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    return DFAMIN_E_DEVICE;
+  }
+  if (hip_device < 0 || hip_device >= count) return DFAMIN_E_INVAL;
+  if (hipSetDevice(hip_device) != hipSuccess) return DFAMIN_E_DEVICE;
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return DFAMIN_E_DEVICE;
+  dfamin_ctx* ctx = new (std::nothrow) dfamin_ctx;
+  if (!ctx) return DFAMIN_E_NOMEM;
+  ctx->c.device = hip_device;
+  ctx->c.budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+  if (hipStreamCreateWithFlags(&ctx->c.stream, hipStreamNonBlocking) != hipSuccess) {
+    delete ctx;
+    return DFAMIN_E_DEVICE;
+  }
+  *out = ctx;
+  return DFAMIN_OK;
+}
+
+void dfamin_destroy(dfamin_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->c.device);
+  if (ctx->c.serving) {
+    delete ctx->c.serving;
+    ctx->c.serving = nullptr;
+  }
+  dfamin::DevBuf* bufs[] = {&ctx->c.in_delta, &ctx->c.in_accept, &ctx->c.in_out};
+  for (auto* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (ctx->c.h_in.p) (void)hipHostFree(ctx->c.h_in.p);
+  if (ctx->c.h_out.p) (void)hipHostFree(ctx->c.h_out.p);
+  if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  hipStream_t s = ctx->c.stream;
+  delete ctx;
+  if (s) (void)hipStreamDestroy(s);
+}
+
+int dfamin_minimize(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin_opts* opts,
+                    uint32_t* out, dfamin_result* result) {
+  if (!ctx || !out) return DFAMIN_E_INVAL;
+  int rc = check_dfa_shape(host_dfa);
+  if (rc == DFAMIN_OK) rc = check_opts(opts);
+  if (rc != DFAMIN_OK) return rc;
+  if ((rc = set_device(ctx->c)) != DFAMIN_OK) return rc;
+  uint32_t* outs[1] = {out};
+  dfamin_result tmp{};
+  rc = run_host_batch(ctx->c, 1, host_dfa, opts_or_default(opts), outs, &tmp);
+  if (result && (rc == DFAMIN_OK || rc == DFAMIN_E_BAD_DFA)) *result = tmp;
+  return rc;
+}
+
+int dfamin_minimize_device(dfamin_ctx* ctx, const dfamin_dfa* dev_dfa, const dfamin_opts* opts,
+                           uint32_t* dev_out, dfamin_result* result, void* hip_stream) {
+  if (!ctx || !dev_out) return DFAMIN_E_INVAL;
+  int rc = check_dfa_shape(dev_dfa);
+  if (rc == DFAMIN_OK) rc = check_opts(opts);
+  if (rc != DFAMIN_OK) return rc;
+  if ((rc = set_device(ctx->c)) != DFAMIN_OK) return rc;
+  const dfamin_opts o = opts_or_default(opts);
+  std::vector<InstInput> in(1);
+  in[0].n = dev_dfa->n;
+  in[0].k = dev_dfa->k;
+  in[0].q0 = dev_dfa->q0;
+  in[0].closure = o.closure;
+  in[0].delta = dev_dfa->delta;
+  in[0].accept = dev_dfa->accept;
+  in[0].out = dev_out;
+  std::vector<InstOutcome> res;
+  rc = ctx->c.engine.run(in, o, static_cast<hipStream_t>(hip_stream), res);
+  if (rc == DFAMIN_OK || rc == DFAMIN_E_BAD_DFA) to_result(res[0], result);
+  return rc;
+}
+
+int dfamin_minimize_batch(dfamin_ctx* ctx, uint32_t count, const dfamin_dfa* dfas,
+                          const dfamin_opts* opts, uint32_t* const* outs, dfamin_result* results) {
+  if (!ctx || (count && (!dfas || !outs))) return DFAMIN_E_INVAL;
+  int rc = check_opts(opts);
+  if (rc != DFAMIN_OK) return rc;
+  for (uint32_t i = 0; i < count; ++i) {
+    if ((rc = check_dfa_shape(&dfas[i])) != DFAMIN_OK) return rc;
+    if (!outs[i]) return DFAMIN_E_INVAL;
+  }
+  if (count == 0) return DFAMIN_OK;
+  if ((rc = set_device(ctx->c)) != DFAMIN_OK) return rc;
+  return run_host_batch(ctx->c, count, dfas, opts_or_default(opts), outs, results);
+}
+
+int dfamin_minimize_batch_device(dfamin_ctx* ctx, uint32_t count, const dfamin_dfa* dev_dfas,
+                                 const dfamin_opts* opts, uint32_t* const* dev_outs,
+                                 dfamin_result* results, void* hip_stream) {
+  if (!ctx || (count && (!dev_dfas || !dev_outs))) return DFAMIN_E_INVAL;
+  int rc = check_opts(opts);
+  if (rc != DFAMIN_OK) return rc;
+  for (uint32_t i = 0; i < count; ++i) {
+    if ((rc = check_dfa_shape(&dev_dfas[i])) != DFAMIN_OK) return rc;
+    if (!dev_outs[i]) return DFAMIN_E_INVAL;
+  }
+  if (count == 0) return DFAMIN_OK;
+  if ((rc = set_device(ctx->c)) != DFAMIN_OK) return rc;
+  const dfamin_opts o = opts_or_default(opts);
+  std::vector<InstInput> in(count);
+  for (uint32_t i = 0; i < count; ++i) {
+    in[i].n = dev_dfas[i].n;
+    in[i].k = dev_dfas[i].k;
+    in[i].q0 = dev_dfas[i].q0;
+    in[i].closure = o.closure;
+    in[i].delta = dev_dfas[i].delta;
+    in[i].accept = dev_dfas[i].accept;
+    in[i].out = dev_outs[i];
+  }
+  std::vector<InstOutcome> res;
+  rc = ctx->c.engine.run(in, o, static_cast<hipStream_t>(hip_stream), res);
+  if ((rc == DFAMIN_OK || rc == DFAMIN_E_BAD_DFA) && results)
+    for (uint32_t i = 0; i < count; ++i) to_result(res[i], &results[i]);
+  return rc;
+}
+
+int dfamin_submit(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin_opts* opts,
+                  uint64_t* ticket) {
+  if (!ctx || !ticket) return DFAMIN_E_INVAL;
+  int rc = check_dfa_shape(host_dfa);
+  if (rc == DFAMIN_OK) rc = check_opts(opts);
+  if (rc != DFAMIN_OK) return rc;
+  if (!ctx->c.serving) {
+    ctx->c.serving = new (std::nothrow) dfamin::Serving(&ctx->c);
+    if (!ctx->c.serving) return DFAMIN_E_NOMEM;
+  }
+  return ctx->c.serving->submit(*host_dfa, opts_or_default(opts), ticket);
+}
+
+int dfamin_wait(dfamin_ctx* ctx, uint64_t ticket, int64_t timeout_us, uint32_t* out,
+                dfamin_result* result) {
+  if (!ctx || !out) return DFAMIN_E_INVAL;
+  if (!ctx->c.serving) return DFAMIN_E_INVAL;
+  return ctx->c.serving->wait(ticket, timeout_us, out, result);
+}
+
+int dfamin_cancel(dfamin_ctx* ctx, uint64_t ticket) {
+  if (!ctx || !ctx->c.serving) return DFAMIN_E_INVAL;
+  return ctx->c.serving->cancel(ticket);
+}
+
+const char* dfamin_status_str(int status) {
+  switch (status) {
+    case DFAMIN_OK: return "ok";
+    case DFAMIN_E_INVAL: return "invalid argument";
+    case DFAMIN_E_BAD_DFA: return "transition target out of range";
+    case DFAMIN_E_NOMEM: return "out of device memory budget";
+    case DFAMIN_E_DEVICE: return "HIP device error";
+    case DFAMIN_E_TIMEOUT: return "timed out";
+    case DFAMIN_E_CANCELLED: return "cancelled";
+    case DFAMIN_E_BUSY: return "queue full";
+    case DFAMIN_E_INTERNAL: return "internal limit exceeded";
+    default: return "unknown status";
+  }
+}
+
+int dfamin_set_profiling(dfamin_ctx* ctx, int on) {
+  if (!ctx) return DFAMIN_E_INVAL;
+  ctx->c.prof.set_enabled(on != 0);
+  return DFAMIN_OK;
+}
+
+int dfamin_get_kernel_stats(dfamin_ctx* ctx, dfamin_kernel_stat* stats, int cap) {
+  if (!ctx || (cap > 0 && !stats)) return DFAMIN_E_INVAL;
+  return ctx->c.prof.copy_stats(stats, cap);
+}
+
+}  // extern "C"

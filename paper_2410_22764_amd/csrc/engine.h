@@ -1,0 +1,125 @@
+// engine.h -- host-side driver of the refinement kernels (one context).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dfamin.h"
+#include "internal.h"
+
+namespace dfamin {
+
+// A device buffer that only grows; its bytes count against the context budget.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Host staging buffer in pinned memory (grow-only).
+struct HostBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Per-kernel HIP-event timing.
+class Profiler {
+ public:
+  ~Profiler();
+  void set_enabled(bool on);
+  bool enabled() const { return on_; }
+  // Record a start event for kernel `name`; `alg_bytes` is what it must move.
+  void begin(hipStream_t s, const char* name, double alg_bytes);
+  void end(hipStream_t s);
+  // Accumulate every finished pair (call after a stream synchronisation).
+  void collect();
+  int copy_stats(dfamin_kernel_stat* out, int cap) const;
+
+ private:
+  struct Pending {
+    int stat;
+    hipEvent_t a, b;
+  };
+  int stat_index(const char* name);
+  hipEvent_t get_event();
+  bool on_ = false;
+  std::vector<dfamin_kernel_stat> stats_;
+  std::vector<Pending> pending_;
+  std::vector<hipEvent_t> free_events_;
+  Pending cur_{};
+};
+
+struct InstInput {
+  uint32_t n, k, q0;
+  uint32_t closure;      // DFAMIN_CLOSURE_*
+  const uint32_t* delta; // device, letter-major
+  const uint8_t* accept; // device bitmap
+  uint32_t* out;         // device, n entries
+};
+
+struct InstOutcome {
+  uint32_t num_blocks = 0, initial_block = 0, refine_rounds = 0, rounds_executed = 0;
+  uint32_t closure_levels = 0, closure_letters = 0;
+  int32_t status = 0;
+};
+
+class Context;
+
+// Runs the whole path for a set of instances that live in device memory.
+class Engine {
+ public:
+  explicit Engine(Context* ctx) : ctx_(ctx) {}
+  ~Engine();
+  int run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+          std::vector<InstOutcome>& res);
+  uint64_t device_bytes() const;
+
+ private:
+  int ensure(DevBuf& b, size_t bytes);
+  int ensure_host(HostBuf& b, size_t bytes);
+  int build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts, hipStream_t s);
+  int upload_layout(hipStream_t s);
+  int check_hip(hipError_t e);
+
+  Context* ctx_;
+  // host-side layout
+  std::vector<InstInput> in_;
+  std::vector<InstDesc> desc_;
+  std::vector<uint64_t> rows_;                   // signature row pointers
+  std::vector<std::vector<uint64_t>> inst_rows_;  // per instance
+  std::vector<std::vector<uint32_t>> nonid_;      // per instance: non-identity letters
+  std::vector<uint32_t> levels_;                  // closure levels built per instance
+  std::vector<uint8_t> has_closure_;
+  uint64_t N_ = 0;
+  uint64_t closure_used_ = 0;
+  // device buffers
+  DevBuf d_desc_, d_rows_, d_jobs_, d_joboff_, d_flags_, d_inst_off_, d_minF_, d_minN_;
+  DevBuf d_inst_of_, d_block_, d_act_, d_act2_, d_slot_of_, d_nb_, d_keep_, d_rank_;
+  DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_, d_closure_;
+  HostBuf h_ctrl_, h_flags_, h_results_;
+};
+
+// The object behind dfamin_ctx.
+class Serving;
+class Context {
+ public:
+  int device = 0;
+  uint64_t budget = 0;
+  uint64_t used = 0;
+  hipStream_t stream = nullptr;  // internal stream for host-input calls
+  Profiler prof;
+  Engine engine{this};
+  // staging for host-input calls
+  DevBuf in_delta, in_accept, in_out;
+  HostBuf h_in, h_out;
+  Serving* serving = nullptr;
+  bool device_lost = false;
+};
+
+}  // namespace dfamin

@@ -1,0 +1,590 @@
+// engine.hip -- host driver of one minimization call (single or batched).
+//
+// Order of work (each step cites the paper passage it implements):
+//   1. validate delta and find identity letters (one pass over delta);
+//   2. signature letters: the non-identity letters of Sigma, or the levels of
+//      Sigma^T (Section 3.4, Algorithm 5) when the closure is on; an identity
+//      letter or a level equal to the previous one adds a component already
+//      in every signature, so dropping it leaves every round's partition as
+//      it is;
+//   3. initial partition {F, Q\F} (Algorithm 4 initialisation);
+//   4. rounds until no instance splits a block (Algorithm 4 loop);
+//   5. canonical numbering by least member and emission.
+#include "engine.h"
+
+#include <algorithm>
+#include <cstring>
+
+namespace dfamin {
+
+namespace {
+
+inline uint32_t floor_log2_u32(uint32_t n) {
+  uint32_t L = 0;
+  while (n >> 1) { n >>= 1; ++L; }
+  return L;
+}
+
+inline uint32_t ceil_log2_u64(uint64_t x) {
+  uint32_t b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+inline uint64_t mix64(uint64_t z) {
+  z ^= z >> 30; z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27; z *= 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+constexpr uint32_t kDefaultAutoRounds = 8;
+constexpr int kMaxSaltRetries = 8;
+
+}  // namespace
+
+// ------------------------------------------------------------------ Profiler
+Profiler::~Profiler() {
+  for (auto& p : pending_) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (auto e : free_events_) (void)hipEventDestroy(e);
+}
+
+void Profiler::set_enabled(bool on) {
+  on_ = on;
+  if (on) stats_.clear();
+}
+
+int Profiler::stat_index(const char* name) {
+  for (size_t i = 0; i < stats_.size(); ++i)
+    if (!std::strncmp(stats_[i].name, name, sizeof(stats_[i].name))) return (int)i;
+  dfamin_kernel_stat st{};
+  std::strncpy(st.name, name, sizeof(st.name) - 1);
+  stats_.push_back(st);
+  return (int)stats_.size() - 1;
+}
+
+hipEvent_t Profiler::get_event() {
+  if (!free_events_.empty()) {
+    hipEvent_t e = free_events_.back();
+    free_events_.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void Profiler::begin(hipStream_t s, const char* name, double alg_bytes) {
+  if (!on_) return;
+  cur_.stat = stat_index(name);
+  stats_[cur_.stat].alg_bytes += alg_bytes;
+  stats_[cur_.stat].launches += 1;
+  cur_.a = get_event();
+  cur_.b = get_event();
+  if (cur_.a) (void)hipEventRecord(cur_.a, s);
+}
+
+void Profiler::end(hipStream_t s) {
+  if (!on_) return;
+  if (cur_.b) (void)hipEventRecord(cur_.b, s);
+  pending_.push_back(cur_);
+}
+
+void Profiler::collect() {
+  for (auto& p : pending_) {
+    float ms = 0.f;
+    if (p.a && p.b && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) stats_[p.stat].total_ms += ms;
+    if (p.a) free_events_.push_back(p.a);
+    if (p.b) free_events_.push_back(p.b);
+  }
+  pending_.clear();
+}
+
+int Profiler::copy_stats(dfamin_kernel_stat* out, int cap) const {
+  int n = (int)stats_.size();
+  for (int i = 0; i < n && i < cap; ++i) out[i] = stats_[i];
+  return n;
+}
+
+// ------------------------------------------------------------------ Engine
+Engine::~Engine() {
+  DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
+                    &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
+                    &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
+                    &d_results_, &d_ctrl_, &d_closure_};
+  for (DevBuf* b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_};
+  for (HostBuf* b : hb)
+    if (b->p) (void)hipHostFree(b->p);
+}
+
+uint64_t Engine::device_bytes() const {
+  const DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
+                          &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
+                          &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
+                          &d_results_, &d_ctrl_, &d_closure_};
+  uint64_t t = 0;
+  for (const DevBuf* b : bufs) t += b->cap;
+  return t;
+}
+
+int Engine::check_hip(hipError_t e) {
+  if (e == hipSuccess) return DFAMIN_OK;
+  if (e == hipErrorOutOfMemory) return DFAMIN_E_NOMEM;
+  ctx_->device_lost = true;
+  return DFAMIN_E_DEVICE;
+}
+
+int Engine::ensure(DevBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b.cap >= bytes) return DFAMIN_OK;
+  size_t want = bytes + bytes / 8;  // head-room for the next, slightly larger call
+  want = (want + 4095) & ~size_t(4095);
+  if (b.p) {
+    (void)hipFree(b.p);
+    ctx_->used -= b.cap;
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  if (ctx_->used + want > ctx_->budget) {
+    want = (bytes + 4095) & ~size_t(4095);
+    if (ctx_->used + want > ctx_->budget) return DFAMIN_E_NOMEM;
+  }
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    (void)hipGetLastError();
+    return e == hipErrorOutOfMemory ? DFAMIN_E_NOMEM : check_hip(e);
+  }
+  b.cap = want;
+  ctx_->used += want;
+  return DFAMIN_OK;
+}
+
+int Engine::ensure_host(HostBuf& b, size_t bytes) {
+  if (bytes == 0) bytes = 64;
+  if (b.cap >= bytes) return DFAMIN_OK;
+  if (b.p) (void)hipHostFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+  size_t want = bytes + bytes / 8 + 64;
+  if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+    b.p = nullptr;
+    return DFAMIN_E_NOMEM;
+  }
+  b.cap = want;
+  return DFAMIN_OK;
+}
+
+#define TRY(x)                    \
+  do {                            \
+    int _rc = (x);                \
+    if (_rc != DFAMIN_OK) return _rc; \
+  } while (0)
+#define HIP(x) TRY(check_hip(x))
+
+// Rebuild descriptors, row pointers and signature-record offsets from the
+// per-instance row lists and upload them.
+int Engine::upload_layout(hipStream_t s) {
+  const size_t I = in_.size();
+  rows_.clear();
+  uint64_t sig_words = 0;
+  for (size_t i = 0; i < I; ++i) {
+    desc_[i].rows_off = (uint32_t)rows_.size();
+    desc_[i].kp = (uint32_t)inst_rows_[i].size();
+    rows_.insert(rows_.end(), inst_rows_[i].begin(), inst_rows_[i].end());
+    desc_[i].sig_off = sig_words;
+    sig_words += (uint64_t)desc_[i].n * (desc_[i].kp + 1);
+  }
+  TRY(ensure(d_sig_, sig_words * 4));
+  TRY(ensure(d_desc_, I * sizeof(InstDesc)));
+  TRY(ensure(d_rows_, std::max<size_t>(rows_.size(), 1) * 8));
+  HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+  if (!rows_.empty())
+    HIP(hipMemcpyAsync(d_rows_.p, rows_.data(), rows_.size() * 8, hipMemcpyHostToDevice, s));
+  return DFAMIN_OK;
+}
+
+// Partial transitive closure (Algorithm 5) for the listed instances: levels
+// 1..L of every non-identity letter by pointer jumping, one launch per
+// level for all of them; then the row list keeps, per letter, the levels up
+// to (excluding) the first one that equals its predecessor or is the
+// identity -- all later levels would equal it.
+int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts,
+                          hipStream_t s) {
+  struct LJob { uint32_t inst, letter, level; };
+  std::vector<uint32_t> L(which.size());
+  uint64_t words = 0;
+  uint32_t Lmax = 0;
+  for (size_t w = 0; w < which.size(); ++w) {
+    const uint32_t i = which[w];
+    uint32_t l = floor_log2_u32(in_[i].n);
+    if (opts.max_levels && opts.max_levels < l) l = opts.max_levels;
+    L[w] = l;
+    Lmax = std::max(Lmax, l);
+    words += (uint64_t)nonid_[i].size() * l * in_[i].n;
+  }
+  // storage: appended after what earlier closures of this call use
+  const uint64_t base = closure_used_;
+  if (words) {
+    // grow keeping old contents is not needed: earlier closures belong to
+    // instances that are already converged or are rebuilt here.
+    if (d_closure_.cap < (base + words) * 4) {
+      if (base != 0) {
+        // keep rows of earlier instances valid: copy into a new buffer
+        DevBuf nb;
+        TRY(ensure(nb, (base + words) * 4));
+        HIP(hipMemcpyAsync(nb.p, d_closure_.p, base * 4, hipMemcpyDeviceToDevice, s));
+        HIP(hipStreamSynchronize(s));
+        const uint64_t old = reinterpret_cast<uint64_t>(d_closure_.p);
+        const uint64_t nw = reinterpret_cast<uint64_t>(nb.p);
+        for (auto& rl : inst_rows_)
+          for (auto& r : rl)
+            if (r >= old && r < old + base * 4) r = r - old + nw;
+        (void)hipFree(d_closure_.p);
+        ctx_->used -= d_closure_.cap;
+        d_closure_ = nb;
+      } else {
+        TRY(ensure(d_closure_, words * 4));
+      }
+    }
+  }
+  const uint64_t cbase = reinterpret_cast<uint64_t>(d_closure_.p);
+  // level l of letter index x of instance w lives at row_ptr(w, x, l)
+  std::vector<uint64_t> first_row(which.size());
+  {
+    uint64_t off = base;
+    for (size_t w = 0; w < which.size(); ++w) {
+      first_row[w] = off;
+      off += (uint64_t)nonid_[which[w]].size() * L[w] * in_[which[w]].n;
+    }
+  }
+  auto row_ptr = [&](size_t w, size_t x, uint32_t l) -> uint64_t {
+    const uint32_t i = which[w];
+    if (l == 0) return reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * nonid_[i][x] * in_[i].n;
+    return cbase + 4ull * (first_row[w] + ((uint64_t)x * L[w] + (l - 1)) * in_[i].n);
+  };
+  // jobs for all levels, grouped by level
+  std::vector<RowJob> jobs;
+  std::vector<uint32_t> joboff;
+  std::vector<LJob> meta;
+  std::vector<uint32_t> lvl_job_begin(Lmax + 2, 0), lvl_wg_total(Lmax + 2, 0);
+  for (uint32_t l = 1; l <= Lmax; ++l) {
+    lvl_job_begin[l] = (uint32_t)jobs.size();
+    uint32_t wgs = 0;
+    for (size_t w = 0; w < which.size(); ++w) {
+      if (L[w] < l) continue;
+      const uint32_t i = which[w];
+      for (size_t x = 0; x < nonid_[i].size(); ++x) {
+        RowJob J;
+        J.src = row_ptr(w, x, l - 1);
+        J.dst = row_ptr(w, x, l);
+        J.n = in_[i].n;
+        J.flag_idx = (uint32_t)jobs.size();
+        joboff.push_back(wgs);
+        wgs += (J.n + kRowTile - 1) / kRowTile;
+        jobs.push_back(J);
+        meta.push_back({(uint32_t)w, (uint32_t)x, l});
+      }
+    }
+    lvl_wg_total[l] = wgs;
+  }
+  lvl_job_begin[Lmax + 1] = (uint32_t)jobs.size();
+  if (!jobs.empty()) {
+    TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
+    TRY(ensure(d_joboff_, joboff.size() * 4));
+    TRY(ensure(d_flags_, jobs.size() * 4));
+    HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
+    HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
+    HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
+    for (uint32_t l = 1; l <= Lmax; ++l) {
+      const uint32_t b = lvl_job_begin[l], e = lvl_job_begin[l + 1];
+      if (b == e) continue;
+      double bytes = 0;
+      for (uint32_t j = b; j < e; ++j) bytes += 12.0 * jobs[j].n;
+      ctx_->prof.begin(s, "closure_level", bytes);
+      launch_closure_level(d_jobs_.as<RowJob>() + b, d_joboff_.as<uint32_t>() + b, e - b,
+                           lvl_wg_total[l], d_flags_.as<uint32_t>(), s);
+      ctx_->prof.end(s);
+      HIP(hipGetLastError());
+    }
+    TRY(ensure_host(h_flags_, jobs.size() * 4));
+    HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
+    HIP(hipStreamSynchronize(s));
+    ctx_->prof.collect();
+  }
+  const uint32_t* flags = h_flags_.as<uint32_t>();
+  // per (w, x): highest level kept
+  for (size_t w = 0; w < which.size(); ++w) {
+    const uint32_t i = which[w];
+    inst_rows_[i].clear();
+    for (size_t x = 0; x < nonid_[i].size(); ++x) {
+      inst_rows_[i].push_back(row_ptr(w, x, 0));
+      for (uint32_t l = 1; l <= L[w]; ++l) {
+        // find job of (w, x, l)
+        uint32_t jb = lvl_job_begin[l], je = lvl_job_begin[l + 1], found = UINT32_MAX;
+        for (uint32_t j = jb; j < je; ++j)
+          if (meta[j].inst == w && meta[j].letter == x) { found = j; break; }
+        if (found == UINT32_MAX) break;
+        const uint32_t f = flags[found];
+        if (!(f & kFlagDiffers) || !(f & kFlagNonId)) break;
+        inst_rows_[i].push_back(row_ptr(w, x, l));
+      }
+    }
+    levels_[i] = L[w];
+    has_closure_[i] = 1;
+  }
+  closure_used_ = base + words;
+  return DFAMIN_OK;
+}
+
+int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+                std::vector<InstOutcome>& res) {
+  in_ = in;
+  const size_t I = in_.size();
+  res.assign(I, InstOutcome{});
+  if (I == 0) return DFAMIN_OK;
+  const bool batch = I > 1;
+  uint64_t N = 0;
+  uint32_t nmax = 0;
+  for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
+  if (N >= 0xFFFFFF00ull) return DFAMIN_E_INVAL;
+  N_ = N;
+  closure_used_ = 0;
+  Profiler& prof = ctx_->prof;
+
+  // ---- 1. validation + identity letters: one row job per (instance, letter)
+  std::vector<RowJob> jobs;
+  std::vector<uint32_t> joboff, job_inst;
+  uint32_t wgs = 0;
+  for (size_t i = 0; i < I; ++i)
+    for (uint32_t a = 0; a < in_[i].k; ++a) {
+      RowJob J;
+      J.src = reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n;
+      J.dst = 0;
+      J.n = in_[i].n;
+      J.flag_idx = (uint32_t)jobs.size();
+      joboff.push_back(wgs);
+      wgs += (J.n + kRowTile - 1) / kRowTile;
+      jobs.push_back(J);
+      job_inst.push_back((uint32_t)i);
+    }
+  TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
+  TRY(ensure(d_joboff_, joboff.size() * 4));
+  TRY(ensure(d_flags_, jobs.size() * 4));
+  TRY(ensure_host(h_flags_, jobs.size() * 4));
+  HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
+  HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
+  HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
+  {
+    double bytes = 0;
+    for (auto& x : in_) bytes += 4.0 * x.n * x.k;
+    prof.begin(s, "validate", bytes);
+    launch_row_check(d_jobs_.as<RowJob>(), d_joboff_.as<uint32_t>(), (uint32_t)jobs.size(), wgs,
+                     d_flags_.as<uint32_t>(), s);
+    prof.end(s);
+    HIP(hipGetLastError());
+  }
+  HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP(hipStreamSynchronize(s));
+  prof.collect();
+  bool any_bad = false;
+  nonid_.assign(I, {});
+  {
+    const uint32_t* f = h_flags_.as<uint32_t>();
+    for (size_t j = 0; j < jobs.size(); ++j)
+      if (f[j] & kFlagBad) { res[job_inst[j]].status = DFAMIN_E_BAD_DFA; any_bad = true; }
+    // jobs are ordered (instance, letter): job j of instance i is letter j - first(i)
+    size_t j = 0;
+    for (size_t i = 0; i < I; ++i) {
+      std::vector<uint32_t> letters;
+      for (uint32_t a = 0; a < in_[i].k; ++a, ++j)
+        if (f[j] & kFlagNonId) letters.push_back(a);
+      nonid_[i] = letters;
+    }
+  }
+  if (any_bad) return DFAMIN_E_BAD_DFA;
+
+  // ---- 2. descriptors and signature letters
+  desc_.assign(I, InstDesc{});
+  inst_rows_.assign(I, {});
+  levels_.assign(I, 0);
+  has_closure_.assign(I, 0);
+  {
+    uint64_t off = 0;
+    for (size_t i = 0; i < I; ++i) {
+      InstDesc& D = desc_[i];
+      D.state_off = (uint32_t)off;
+      D.n = in_[i].n;
+      D.k = in_[i].k;
+      D.q0 = in_[i].q0;
+      D.accept = reinterpret_cast<uint64_t>(in_[i].accept);
+      D.out = reinterpret_cast<uint64_t>(in_[i].out);
+      off += in_[i].n;
+      for (uint32_t a : nonid_[i])
+        inst_rows_[i].push_back(reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n);
+    }
+  }
+  {
+    std::vector<uint32_t> on;
+    for (size_t i = 0; i < I; ++i)
+      if (in_[i].closure == DFAMIN_CLOSURE_ON) on.push_back((uint32_t)i);
+    if (!on.empty()) TRY(build_closure(on, opts, s));
+  }
+
+  // ---- 3. buffers sized for N
+  TRY(ensure(d_block_, N * 4));
+  TRY(ensure(d_act_, N * 4));
+  TRY(ensure(d_act2_, N * 4));
+  TRY(ensure(d_slot_of_, N * 4));
+  TRY(ensure(d_nb_, N * 4));
+  TRY(ensure(d_keep_, N));
+  TRY(ensure(d_rank_, (N + 1) * 4));
+  const uint64_t max_tiles = (N + kScanTile - 1) / kScanTile + 1;
+  TRY(ensure(d_status_, max_tiles * 8));
+  TRY(ensure(d_changed_, I * 4));
+  TRY(ensure(d_refine_, I * 4));
+  TRY(ensure(d_minF_, I * 4));
+  TRY(ensure(d_minN_, I * 4));
+  TRY(ensure(d_results_, I * sizeof(ResultDev)));
+  TRY(ensure(d_ctrl_, sizeof(Ctrl)));
+  TRY(ensure(d_inst_off_, I * 4));
+  if (batch) TRY(ensure(d_inst_of_, N * 4));
+  TRY(ensure_host(h_ctrl_, sizeof(Ctrl)));
+  TRY(ensure_host(h_results_, I * sizeof(ResultDev)));
+  TRY(upload_layout(s));
+  // workgroup offsets of the per-instance init jobs
+  std::vector<uint32_t> inst_off(I);
+  uint32_t init_wgs = 0;
+  for (size_t i = 0; i < I; ++i) {
+    inst_off[i] = init_wgs;
+    init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
+  }
+  HIP(hipMemcpyAsync(d_inst_off_.p, inst_off.data(), I * 4, hipMemcpyHostToDevice, s));
+  HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
+  HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
+  HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
+
+  // ---- 4. initial partition {F, Q\F}
+  prof.begin(s, "init_minmax", 0.0);
+  launch_init_minmax(d_desc_.as<InstDesc>(), (uint32_t)I, d_minF_.as<uint32_t>(),
+                     d_minN_.as<uint32_t>(), s);
+  prof.end(s);
+  prof.begin(s, "init_block", (8.125 + (batch ? 4.0 : 0.0)) * (double)N);
+  launch_init_block(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
+                    d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(),
+                    batch ? d_inst_of_.as<uint32_t>() : nullptr, d_block_.as<uint32_t>(),
+                    d_act_.as<uint32_t>(), s);
+  prof.end(s);
+  HIP(hipGetLastError());
+
+  // ---- 5. rounds
+  const uint32_t auto_rounds = opts.auto_rounds ? opts.auto_rounds : kDefaultAutoRounds;
+  const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
+  bool any_auto = false;
+  for (auto& x : in_) any_auto |= (x.closure == DFAMIN_CLOSURE_AUTO);
+  uint64_t m = N;
+  uint32_t* cur = d_act_.as<uint32_t>();
+  uint32_t* nxt = d_act2_.as<uint32_t>();
+  uint64_t salt = 0x5DEECE66Dull;
+  int retries = 0;
+  uint64_t rounds = 0;
+  auto avg_kp = [&]() {
+    // average signature letters per state, weighted by n (for byte counts)
+    double w = 0;
+    for (size_t i = 0; i < I; ++i) w += (double)desc_[i].n * desc_[i].kp;
+    return N ? w / (double)N : 0.0;
+  };
+  double kpbar = avg_kp();
+  while (m > 0) {
+    if (any_auto && rounds == auto_rounds) {
+      // instances still refining after auto_rounds rounds get the closure
+      HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
+      HIP(hipStreamSynchronize(s));
+      const uint32_t* rc = h_results_.as<uint32_t>();
+      std::vector<uint32_t> which;
+      for (size_t i = 0; i < I; ++i)
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && rc[i] == rounds) which.push_back((uint32_t)i);
+      if (!which.empty()) {
+        TRY(build_closure(which, opts, s));
+        TRY(upload_layout(s));
+        kpbar = avg_kp();
+      }
+    }
+    if (rounds >= max_rounds) return DFAMIN_E_INTERNAL;
+    const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * m));
+    const uint64_t tsize = 1ull << tbits;
+    TRY(ensure(d_table_, tsize * sizeof(Slot)));
+    const uint32_t ntiles = (uint32_t)((m + kScanTile - 1) / kScanTile);
+    const double md = (double)m;
+    const double inst_b = batch ? 4.0 : 0.0;
+
+    prof.begin(s, "clear_table", 16.0 * (double)tsize);
+    launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+    prof.end(s);
+    prof.begin(s, "signature", md * (4 + inst_b + 4 + 8 * kpbar + 4 * (kpbar + 1) + 4 + 16));
+    launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_sig_.as<uint32_t>(),
+                     d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, s);
+    prof.end(s);
+    prof.begin(s, "resolve", md * (4 + inst_b + 4 + 16 + 4 + 4 + 1));
+    launch_resolve(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                   d_sig_.as<uint32_t>(), d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
+                   d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(), d_keep_.as<uint8_t>(),
+                   d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                   d_status_.as<unsigned long long>(), ntiles, s);
+    prof.end(s);
+    prof.begin(s, "compact", md * (4 + inst_b + 4 + 1 + 4));
+    launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
+                   d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), d_block_.as<uint32_t>(), nxt,
+                   d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), s);
+    prof.end(s);
+    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(),
+                     d_ctrl_.as<Ctrl>(), s);
+    HIP(hipGetLastError());
+    HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP(hipStreamSynchronize(s));
+    prof.collect();
+    const Ctrl c = *h_ctrl_.as<Ctrl>();
+    if (c.collision) {
+      if (++retries > kMaxSaltRetries) return DFAMIN_E_INTERNAL;
+      salt = mix64(salt + 0x9E3779B97F4A7C15ull);
+      continue;
+    }
+    ++rounds;
+    std::swap(cur, nxt);
+    m = c.m_next;
+    if (!c.any_changed) break;
+  }
+
+  // ---- 6. canonical numbering and emission
+  const uint32_t ntilesN = (uint32_t)((N + kScanTile - 1) / kScanTile);
+  launch_prep_scan(d_status_.as<unsigned long long>(), ntilesN, d_ctrl_.as<Ctrl>(), s);
+  prof.begin(s, "scan_reps", 8.0 * (double)N);
+  launch_scan_reps(d_block_.as<uint32_t>(), (uint32_t)N, d_rank_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                   d_status_.as<unsigned long long>(), s);
+  prof.end(s);
+  prof.begin(s, "emit", (12.0 + (batch ? 4.0 : 0.0)) * (double)N);
+  launch_emit(batch, (uint32_t)N, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+              d_block_.as<uint32_t>(), d_rank_.as<uint32_t>(), s);
+  prof.end(s);
+  launch_results((uint32_t)I, d_desc_.as<InstDesc>(), d_rank_.as<uint32_t>(),
+                 d_refine_.as<uint32_t>(), d_results_.as<ResultDev>(), s);
+  HIP(hipGetLastError());
+  HIP(hipMemcpyAsync(h_results_.p, d_results_.p, I * sizeof(ResultDev), hipMemcpyDeviceToHost, s));
+  HIP(hipStreamSynchronize(s));
+  prof.collect();
+  const ResultDev* r = h_results_.as<ResultDev>();
+  for (size_t i = 0; i < I; ++i) {
+    res[i].num_blocks = r[i].num_blocks;
+    res[i].initial_block = r[i].initial_block;
+    res[i].refine_rounds = r[i].refine_rounds;
+    res[i].rounds_executed = r[i].refine_rounds + 1;
+    res[i].closure_levels = has_closure_[i] ? levels_[i] : 0;
+    res[i].closure_letters = has_closure_[i] ? (uint32_t)inst_rows_[i].size() : 0;
+    res[i].status = DFAMIN_OK;
+  }
+  return DFAMIN_OK;
+}
+
+}  // namespace dfamin

@@ -1,0 +1,115 @@
+// internal.h -- device data layout and kernel launchers of libdfamin.
+//
+// Layout (all in HBM of one device):
+//   * Instances are laid side by side in one global state space: instance i
+//     owns global state ids [state_off, state_off + n).  Block ids are global
+//     state ids too: the id of a block is its least member state.  Two
+//     instances therefore never share a block id, which keeps every
+//     instance's signatures apart when many are refined by one launch.
+//   * delta stays in the caller's letter-major layout (Section 2,
+//     "Representation"); each signature letter is a pointer to one row of n
+//     local successor ids (an input row, or a closure level).
+//   * act[] lists the global ids of the states still in non-singleton blocks
+//     of instances still refining, in increasing order within each instance.
+//     A singleton block can never split again, so its states leave the list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dfamin {
+
+constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
+constexpr int kScanItems = 4;         // items per thread in scan / compaction tiles
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kLocalSlots = 512;      // LDS hash slots per signature workgroup
+constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
+
+// Per-instance descriptor (device copy).  48 bytes.
+struct InstDesc {
+  uint32_t state_off;   // first global state id
+  uint32_t n;           // states
+  uint32_t kp;          // signature letters in use (rows)
+  uint32_t rows_off;    // index of the first row pointer in rows[]
+  uint64_t sig_off;     // word offset of the signature records: n * (kp + 1) words
+  uint64_t accept;      // device address of the accept bitmap
+  uint64_t out;         // device address of the output (n uint32)
+  uint32_t q0;
+  uint32_t k;           // original alphabet size
+};
+
+// Global hash-table slot: 16 bytes.  key == 0 marks an empty slot.
+struct Slot {
+  unsigned long long key;  // 64-bit signature hash (never 0)
+  uint32_t jmin;           // least active index with this hash
+  uint32_t cnt;            // number of active states with this hash
+};
+
+// Control block shared by the round kernels and read by the host.
+struct Ctrl {
+  uint32_t any_changed;   // some block split this round
+  uint32_t collision;     // two different signatures shared a hash this round
+  uint32_t m_next;        // active states for the next round
+  uint32_t tile_counter;  // dynamic tile ids for the look-back scans
+  uint32_t bad;           // a delta entry >= n was seen
+  uint32_t pad[3];
+};
+
+// One row of n entries handled by a row job (validation, closure level).
+struct RowJob {
+  uint64_t src;        // device address of a uint32[n] row
+  uint64_t dst;        // destination row (closure level) or 0
+  uint32_t n;
+  uint32_t flag_idx;   // which flag word this job reports into
+};
+
+// Per-instance results written on the device.
+struct ResultDev {
+  uint32_t num_blocks;
+  uint32_t initial_block;
+  uint32_t refine_rounds;
+  uint32_t pad;
+};
+
+// Row-check flag bits.
+constexpr uint32_t kFlagBad = 1u;      // entry >= n
+constexpr uint32_t kFlagNonId = 2u;    // entry != its own index
+constexpr uint32_t kFlagDiffers = 4u;  // closure level differs from the previous level
+
+// Kernel launchers (kernels.hip).  All are asynchronous on `s`.
+// Jobs: a list of work units each covering `len` elements; job_wg_off[j] is
+// the first workgroup of job j (exclusive prefix over ceil(len/tile)).
+void launch_row_check(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
+                      uint32_t total_wgs, uint32_t* flags, hipStream_t s);
+void launch_closure_level(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
+                          uint32_t total_wgs, uint32_t* flags, hipStream_t s);
+void launch_init_minmax(const InstDesc* desc, uint32_t ninst, uint32_t* minF, uint32_t* minN,
+                        hipStream_t s);
+void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
+                       uint32_t total_wgs, const uint32_t* minF, const uint32_t* minN,
+                       uint32_t* inst_of, uint32_t* block, uint32_t* act, hipStream_t s);
+void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s);
+void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                      const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
+                      uint32_t* sig, Slot* table, uint32_t tbits, uint32_t* slot_of,
+                      uint64_t salt, hipStream_t s);
+void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                    const InstDesc* desc, const uint32_t* sig, const Slot* table,
+                    const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
+                    uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
+                    uint32_t ntiles, hipStream_t s);
+void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                    const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
+                    uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
+                    unsigned long long* scan_status, hipStream_t s);
+void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt,
+                      const Ctrl* ctrl, hipStream_t s);
+void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s);
+void launch_scan_reps(const uint32_t* block, uint32_t N, uint32_t* rank, Ctrl* ctrl,
+                      unsigned long long* scan_status, hipStream_t s);
+void launch_emit(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
+                 const uint32_t* block, const uint32_t* rank, hipStream_t s);
+void launch_results(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
+                    const uint32_t* refine_cnt, ResultDev* res, hipStream_t s);
+
+}  // namespace dfamin

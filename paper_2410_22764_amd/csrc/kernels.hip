@@ -1,0 +1,640 @@
+// kernels.hip -- HIP kernels for gfx950 (CDNA4, wave64) of libdfamin.
+//
+// One refinement round (the loop body of the paper's Algorithm 4, Section
+// 3.3) is four kernels over the active list:
+//   k_signature  gather: sig(q) = (block[q], block[delta'(q,a)] for a in
+//                Sigma'), a 64-bit hash of it, workgroup-local grouping of
+//                equal hashes in LDS and one global hash-table insert per
+//                local group (hash grouping, the alternative to sorting that
+//                the paper attributes to Tewari et al.);
+//   k_resolve    every state learns its group's least member (the new block
+//                id) and checks its full signature against that member's,
+//                so grouping is exact and never trusts a hash alone;
+//   k_compact    applies the new ids and compacts the active list with a
+//                wave64 ballot/popcount scan and decoupled look-back (the
+//                adjacent-difference + inclusive-scan step of Algorithm 4);
+//   k_round_end  per-instance round counters.
+// The closure of Algorithm 5 (Section 3.4) is k_closure_level, one launch per
+// level: T_i[q] = T_{i-1}[T_{i-1}[q]] (pointer jumping).
+//
+// Cross-workgroup communication inside a kernel happens only through device
+// atomics (hash slots, look-back status words); everything else is handed
+// from one kernel to the next.
+#include "internal.h"
+
+namespace dfamin {
+
+namespace {
+
+constexpr unsigned long long kFlagAgg = 1ull << 62;
+constexpr unsigned long long kFlagPrefix = 2ull << 62;
+
+__device__ __forceinline__ uint64_t hash_step(uint64_t h, uint32_t w) {
+  h ^= w;
+  h *= 0x9E3779B97F4A7C15ull;
+  h ^= h >> 29;
+  return h;
+}
+
+__device__ __forceinline__ uint64_t hash_final(uint64_t h) {
+  h ^= h >> 32;
+  h *= 0xD6E8FEB86659FD93ull;
+  h ^= h >> 32;
+  return h ? h : 1ull;  // 0 marks an empty slot
+}
+
+__device__ __forceinline__ unsigned long long load_status(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void store_status(unsigned long long* p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Decoupled look-back (one thread): publishes this tile's aggregate, sums the
+// predecessors' values back to the first inclusive prefix, publishes its own
+// inclusive prefix and returns the exclusive one.  Tiles are numbered in the
+// order workgroups obtained them, so every predecessor is running or done.
+__device__ uint32_t lookback(unsigned long long* status, uint32_t tile, uint32_t total) {
+  if (tile == 0) {
+    store_status(&status[0], kFlagPrefix | total);
+    return 0;
+  }
+  store_status(&status[tile], kFlagAgg | total);
+  uint32_t excl = 0;
+  int t = (int)tile - 1;
+  while (true) {
+    unsigned long long v = load_status(&status[t]);
+    unsigned long long flag = v >> 62;
+    if (flag == 0) {
+      __builtin_amdgcn_s_sleep(1);
+      continue;
+    }
+    excl += (uint32_t)v;
+    if (flag == 2) break;
+    --t;
+  }
+  store_status(&status[tile], kFlagPrefix | (unsigned long long)(excl + total));
+  return excl;
+}
+
+// Exclusive rank of each flagged item inside a tile of kScanItems sub-tiles of
+// kBlock items (item e of thread t is element e*kBlock + t of the tile), via
+// one 64-lane ballot per sub-tile and wave.  s_cnt: LDS of kScanItems*4 words.
+__device__ __forceinline__ uint32_t tile_ballot_scan(const bool (&f)[kScanItems],
+                                                     uint32_t (&rank)[kScanItems],
+                                                     uint32_t* s_cnt) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t within[kScanItems];
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    unsigned long long mask = __ballot(f[e]);
+    within[e] = __popcll(mask & lt);
+    if (lane == 0) s_cnt[e * 4 + wave] = __popcll(mask);
+  }
+  __syncthreads();
+  uint32_t acc = 0;
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+#pragma unroll
+    for (uint32_t w = 0; w < 4; ++w) {
+      if (w == wave) rank[e] = acc + within[e];
+      acc += s_cnt[e * 4 + w];
+    }
+  }
+  return acc;
+}
+
+// Workgroup -> job by binary search over the exclusive workgroup prefix.
+__device__ __forceinline__ uint32_t find_job(const uint32_t* job_wg_off, uint32_t njobs,
+                                             uint32_t* s_job) {
+  if (threadIdx.x == 0) {
+    uint32_t lo = 0, hi = njobs;  // largest j with job_wg_off[j] <= blockIdx.x
+    while (hi - lo > 1) {
+      uint32_t mid = (lo + hi) >> 1;
+      if (job_wg_off[mid] <= blockIdx.x) lo = mid; else hi = mid;
+    }
+    *s_job = lo;
+  }
+  __syncthreads();
+  return *s_job;
+}
+
+// ---------------------------------------------------------------- row jobs
+// Algorithmic bytes: 4 per element read.
+__global__ __launch_bounds__(kBlock) void k_row_check(const RowJob* __restrict__ jobs,
+                                                      const uint32_t* __restrict__ job_wg_off,
+                                                      uint32_t njobs, uint32_t* __restrict__ flags) {
+  __shared__ uint32_t s_job;
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const RowJob J = jobs[j];
+  const uint32_t* __restrict__ row = reinterpret_cast<const uint32_t*>(J.src);
+  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+  uint32_t bits = 0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < J.n) {
+      uint32_t v = row[q];
+      if (v >= J.n) bits |= kFlagBad;
+      if (v != q) bits |= kFlagNonId;
+    }
+  }
+  // wave-aggregate before touching the flag word
+  bool any_bad = __any(bits & kFlagBad), any_nonid = __any(bits & kFlagNonId);
+  if ((threadIdx.x & 63u) == 0 && (any_bad || any_nonid))
+    atomicOr(&flags[J.flag_idx], (any_bad ? kFlagBad : 0u) | (any_nonid ? kFlagNonId : 0u));
+}
+
+// One closure level for every job: dst[q] = src[src[q]] (Algorithm 5).
+// Algorithmic bytes: 12 per element (coalesced read, gathered read, write).
+__global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restrict__ jobs,
+                                                          const uint32_t* __restrict__ job_wg_off,
+                                                          uint32_t njobs,
+                                                          uint32_t* __restrict__ flags) {
+  __shared__ uint32_t s_job;
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const RowJob J = jobs[j];
+  const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(J.src);
+  uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(J.dst);
+  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+  uint32_t s1[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t q = base + e * kBlock + threadIdx.x;
+    s1[e] = (q < J.n) ? src[q] : 0u;
+  }
+  bool differs = false, nonid = false;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < J.n) {
+      uint32_t s2 = src[s1[e]];
+      dst[q] = s2;
+      differs |= (s2 != s1[e]);
+      nonid |= (s2 != q);
+    }
+  }
+  bool d = __any(differs), ni = __any(nonid);
+  if ((threadIdx.x & 63u) == 0 && (d || ni))
+    atomicOr(&flags[J.flag_idx], (d ? kFlagDiffers : 0u) | (ni ? kFlagNonId : 0u));
+}
+
+// ---------------------------------------------------------------- init
+// Least accepting and least non-accepting state of each instance (the two
+// initial blocks {F, Q\F} of Algorithm 4, named by their least members).
+// One workgroup per instance scans the bitmap from the front and stops as
+// soon as both are found.
+__global__ __launch_bounds__(kBlock) void k_init_minmax(const InstDesc* __restrict__ desc,
+                                                        uint32_t* __restrict__ minF,
+                                                        uint32_t* __restrict__ minN) {
+  __shared__ uint32_t sF, sN;
+  const InstDesc D = desc[blockIdx.x];
+  const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
+  if (threadIdx.x == 0) { sF = 0xffffffffu; sN = 0xffffffffu; }
+  __syncthreads();
+  const uint32_t nbytes = (D.n + 7) >> 3;
+  for (uint32_t b0 = 0; b0 < nbytes; b0 += kBlock) {
+    uint32_t b = b0 + threadIdx.x;
+    if (b < nbytes) {
+      uint32_t valid = D.n - b * 8;
+      uint32_t vmask = valid >= 8 ? 0xffu : ((1u << valid) - 1u);
+      uint32_t v = acc[b];
+      uint32_t f = v & vmask, nf = ~v & vmask;
+      if (f) atomicMin(&sF, b * 8 + __builtin_ctz(f));
+      if (nf) atomicMin(&sN, b * 8 + __builtin_ctz(nf));
+    }
+    __syncthreads();
+    bool done = (sF != 0xffffffffu) && (sN != 0xffffffffu);
+    __syncthreads();
+    if (done) break;
+  }
+  if (threadIdx.x == 0) { minF[blockIdx.x] = sF; minN[blockIdx.x] = sN; }
+}
+
+// block[g] = least member of g's initial block; act = all states.
+// Algorithmic bytes: 8.125 per state (bit read, block + act writes; +4 with inst_of).
+__global__ __launch_bounds__(kBlock) void k_init_block(const InstDesc* __restrict__ desc,
+                                                       const uint32_t* __restrict__ job_wg_off,
+                                                       uint32_t ninst,
+                                                       const uint32_t* __restrict__ minF,
+                                                       const uint32_t* __restrict__ minN,
+                                                       uint32_t* __restrict__ inst_of,
+                                                       uint32_t* __restrict__ block,
+                                                       uint32_t* __restrict__ act) {
+  __shared__ uint32_t s_job;
+  const uint32_t i = find_job(job_wg_off, ninst, &s_job);
+  const InstDesc D = desc[i];
+  const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
+  const uint32_t base = (blockIdx.x - job_wg_off[i]) * kRowTile;
+  const uint32_t f = D.state_off + minF[i], nf = D.state_off + minN[i];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < D.n) {
+      uint32_t g = D.state_off + q;
+      bool a = (acc[q >> 3] >> (q & 7)) & 1u;
+      block[g] = a ? f : nf;
+      act[g] = g;
+      if (inst_of) inst_of[g] = i;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- round
+__global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table, uint64_t tsize,
+                                                        Ctrl* __restrict__ ctrl) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl->any_changed = 0;
+    ctrl->collision = 0;
+  }
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x; s < tsize; s += stride) {
+    Slot e;
+    e.key = 0ull;
+    e.jmin = 0xffffffffu;
+    e.cnt = 0u;
+    table[s] = e;
+  }
+}
+
+// Signature gather + grouping by hash.  Algorithmic bytes per active state:
+// 4 (act) [+4 inst_of] + 4 (own block) + 8*kp (delta' row entry and the
+// gathered successor block per letter) + 4*(kp+1) (signature record) + 4
+// (slot id) + 16 (one hash-slot update per local group, upper bound).
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_signature(
+    const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
+    const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
+    const uint32_t* __restrict__ block, uint32_t* __restrict__ sig, Slot* __restrict__ table,
+    uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt) {
+  __shared__ unsigned long long lkey[kLocalSlots];
+  __shared__ uint32_t lmin[kLocalSlots], lcnt[kLocalSlots], lslot[kLocalSlots];
+  for (uint32_t s = threadIdx.x; s < kLocalSlots; s += kBlock) {
+    lkey[s] = 0ull;
+    lmin[s] = 0xffffffffu;
+    lcnt[s] = 0u;
+  }
+  __syncthreads();
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = j < m;
+  uint64_t h = 0;
+  uint32_t lp = 0;
+  if (valid) {
+    const uint32_t g = act[j];
+    const uint32_t i = BATCH ? inst_of[g] : 0u;
+    const InstDesc D = desc[i];
+    const uint32_t q = g - D.state_off;
+    const uint32_t kp = D.kp;
+    uint32_t* __restrict__ rec = sig + D.sig_off + (uint64_t)q * (kp + 1);
+    const uint32_t own = block[g];
+    rec[0] = own;
+    h = hash_step(salt ^ 0x243F6A8885A308D3ull, own);
+    const uint64_t* __restrict__ R = rows + D.rows_off;
+    for (uint32_t r0 = 0; r0 < kp; r0 += 8) {
+      const uint32_t cnt = (kp - r0) < 8u ? (kp - r0) : 8u;
+      uint32_t s[8], b[8];
+#pragma unroll
+      for (uint32_t t = 0; t < 8; ++t)
+        if (t < cnt) s[t] = reinterpret_cast<const uint32_t*>(R[r0 + t])[q];
+#pragma unroll
+      for (uint32_t t = 0; t < 8; ++t)
+        if (t < cnt) b[t] = block[D.state_off + s[t]];
+#pragma unroll
+      for (uint32_t t = 0; t < 8; ++t)
+        if (t < cnt) {
+          rec[1 + r0 + t] = b[t];
+          h = hash_step(h, b[t]);
+        }
+    }
+    h = hash_final(h);
+    uint32_t p = (uint32_t)h & (kLocalSlots - 1);
+    while (true) {
+      unsigned long long prev = atomicCAS(&lkey[p], 0ull, (unsigned long long)h);
+      if (prev == 0ull || prev == h) break;
+      p = (p + 1) & (kLocalSlots - 1);
+    }
+    lp = p;
+    atomicMin(&lmin[p], j);
+    atomicAdd(&lcnt[p], 1u);
+  }
+  __syncthreads();
+  if (valid && lmin[lp] == j) {
+    const uint64_t mask = (tbits >= 64) ? ~0ull : ((1ull << tbits) - 1ull);
+    uint64_t p = h >> (64 - tbits);
+    while (true) {
+      unsigned long long prev = atomicCAS(&table[p].key, 0ull, (unsigned long long)h);
+      if (prev == 0ull || prev == h) break;
+      p = (p + 1) & mask;
+    }
+    atomicMin(&table[p].jmin, j);
+    atomicAdd(&table[p].cnt, lcnt[lp]);
+    lslot[lp] = (uint32_t)p;
+  }
+  __syncthreads();
+  if (valid) slot_of[j] = lslot[lp];
+}
+
+// New block id = least member of the state's hash group; exact check of the
+// full signature against that member's.  Algorithmic bytes per active state:
+// 4 (act) [+4 inst_of] + 4 (slot id) + 16 (slot) + 4 (old block) + 4 (new
+// id) + 1 (keep flag), plus 4 + 8*(kp+1) when the state is not the least
+// member of its group (its record and the least member's).
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_resolve(
+    const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
+    const InstDesc* __restrict__ desc, const uint32_t* __restrict__ sig,
+    const Slot* __restrict__ table, const uint32_t* __restrict__ slot_of,
+    const uint32_t* __restrict__ block, uint32_t* __restrict__ nb, uint8_t* __restrict__ keep,
+    uint32_t* __restrict__ changed_inst, Ctrl* __restrict__ ctrl,
+    unsigned long long* __restrict__ scan_status, uint32_t ntiles) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < ntiles) scan_status[j] = 0ull;
+  if (j == 0) ctrl->tile_counter = 0u;
+  bool changed = false, coll = false;
+  if (j < m) {
+    const uint32_t g = act[j];
+    const uint32_t i = BATCH ? inst_of[g] : 0u;
+    const Slot e = table[slot_of[j]];
+    uint32_t rep = g;
+    if (e.jmin != j) {
+      const InstDesc D = desc[i];
+      const uint32_t gc = act[e.jmin];
+      rep = gc;
+      const uint32_t w = D.kp + 1;
+      const uint32_t* __restrict__ r1 = sig + D.sig_off + (uint64_t)(g - D.state_off) * w;
+      const uint32_t* __restrict__ r2 = sig + D.sig_off + (uint64_t)(gc - D.state_off) * w;
+      if (gc < D.state_off || gc - D.state_off >= D.n) {
+        coll = true;  // the group's least member belongs to another instance
+      } else {
+        for (uint32_t t = 0; t < w; ++t) coll |= (r1[t] != r2[t]);
+      }
+    }
+    if (rep != block[g]) {
+      changed = true;
+      changed_inst[i] = 1u;
+    }
+    nb[j] = rep;
+    keep[j] = e.cnt > 1u ? 1 : 0;
+  }
+  const bool any_changed = __any(changed), any_coll = __any(coll);
+  if ((threadIdx.x & 63u) == 0) {
+    if (any_changed) ctrl->any_changed = 1u;
+    if (any_coll) ctrl->collision = 1u;
+  }
+}
+
+// Apply the new ids and keep the states whose block is still shared and whose
+// instance split this round.  Algorithmic bytes per active state: 4 (act)
+// [+4 inst_of] + 4 (new id) + 1 (keep) + 4 (changed flag, cached) + 4 (block
+// write) + 4 per kept state (next active list).
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_compact(
+    const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
+    const uint32_t* __restrict__ nb, const uint8_t* __restrict__ keep,
+    const uint32_t* __restrict__ changed_inst, uint32_t* __restrict__ block,
+    uint32_t* __restrict__ act_next, Ctrl* __restrict__ ctrl,
+    unsigned long long* __restrict__ scan_status) {
+  if (ctrl->collision) return;  // the round is redone with another salt
+  __shared__ uint32_t s_tile, s_prefix;
+  __shared__ uint32_t s_cnt[kScanItems * 4];
+  if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tile_counter, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint32_t base = tile * kScanTile;
+  bool f[kScanItems];
+  uint32_t gs[kScanItems];
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    const uint32_t j = base + e * kBlock + threadIdx.x;
+    f[e] = false;
+    gs[e] = 0;
+    if (j < m) {
+      const uint32_t g = act[j];
+      gs[e] = g;
+      block[g] = nb[j];
+      const uint32_t i = BATCH ? inst_of[g] : 0u;
+      f[e] = keep[j] && changed_inst[i];
+    }
+  }
+  uint32_t rank[kScanItems];
+  const uint32_t total = tile_ballot_scan(f, rank, s_cnt);
+  if (threadIdx.x == 0) {
+    const uint32_t excl = lookback(scan_status, tile, total);
+    s_prefix = excl;
+    if (base + kScanTile >= m) ctrl->m_next = excl + total;
+  }
+  __syncthreads();
+  const uint32_t pre = s_prefix;
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e)
+    if (f[e]) act_next[pre + rank[e]] = gs[e];
+}
+
+__global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
+                                                      uint32_t* __restrict__ changed_inst,
+                                                      uint32_t* __restrict__ refine_cnt,
+                                                      const Ctrl* __restrict__ ctrl) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ninst) return;
+  if (changed_inst[i]) {
+    if (!ctrl->collision) refine_cnt[i] += 1u;
+    changed_inst[i] = 0u;
+  }
+}
+
+// ---------------------------------------------------------------- finalize
+__global__ __launch_bounds__(kBlock) void k_prep_scan(unsigned long long* __restrict__ scan_status,
+                                                      uint32_t ntiles, Ctrl* __restrict__ ctrl) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j < ntiles) scan_status[j] = 0ull;
+  if (j == 0) ctrl->tile_counter = 0u;
+}
+
+// rank[g] = number of block representatives (block[x] == x) with x < g;
+// rank[N] = their total.  Algorithmic bytes: 8 per state.
+__global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict__ block,
+                                                      uint32_t N, uint32_t* __restrict__ rank,
+                                                      Ctrl* __restrict__ ctrl,
+                                                      unsigned long long* __restrict__ scan_status) {
+  __shared__ uint32_t s_tile, s_prefix;
+  __shared__ uint32_t s_cnt[kScanItems * 4];
+  if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tile_counter, 1u);
+  __syncthreads();
+  const uint32_t tile = s_tile;
+  const uint32_t base = tile * kScanTile;
+  bool f[kScanItems];
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    const uint32_t g = base + e * kBlock + threadIdx.x;
+    f[e] = (g < N) && (block[g] == g);
+  }
+  uint32_t r[kScanItems];
+  const uint32_t total = tile_ballot_scan(f, r, s_cnt);
+  if (threadIdx.x == 0) {
+    const uint32_t excl = lookback(scan_status, tile, total);
+    s_prefix = excl;
+    if (base + kScanTile >= N) rank[N] = excl + total;
+  }
+  __syncthreads();
+  const uint32_t pre = s_prefix;
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    const uint32_t g = base + e * kBlock + threadIdx.x;
+    if (g < N) rank[g] = pre + r[e];
+  }
+}
+
+// out[q] = rank[block[g]] - rank[state_off]: canonical ids by least member.
+// Algorithmic bytes: 16 per state (block, gathered rank, out write; +4 inst_of).
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, const uint32_t* __restrict__ inst_of,
+                                                 const InstDesc* __restrict__ desc,
+                                                 const uint32_t* __restrict__ block,
+                                                 const uint32_t* __restrict__ rank) {
+  const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= N) return;
+  const uint32_t i = BATCH ? inst_of[g] : 0u;
+  const uint32_t off = desc[i].state_off;
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(desc[i].out);
+  out[g - off] = rank[block[g]] - rank[off];
+}
+
+__global__ __launch_bounds__(kBlock) void k_results(uint32_t ninst, const InstDesc* __restrict__ desc,
+                                                    const uint32_t* __restrict__ rank,
+                                                    const uint32_t* __restrict__ refine_cnt,
+                                                    ResultDev* __restrict__ res) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ninst) return;
+  const InstDesc D = desc[i];
+  ResultDev r;
+  r.num_blocks = rank[D.state_off + D.n] - rank[D.state_off];
+  r.initial_block = reinterpret_cast<const uint32_t*>(D.out)[D.q0];
+  r.refine_rounds = refine_cnt[i];
+  r.pad = 0;
+  res[i] = r;
+}
+
+inline uint32_t grid_for(uint64_t items, uint64_t per_wg) {
+  return (uint32_t)((items + per_wg - 1) / per_wg);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void launch_row_check(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
+                      uint32_t total_wgs, uint32_t* flags, hipStream_t s) {
+  if (!total_wgs) return;
+  hipLaunchKernelGGL(k_row_check, dim3(total_wgs), dim3(kBlock), 0, s, jobs, job_wg_off, njobs, flags);
+}
+
+void launch_closure_level(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
+                          uint32_t total_wgs, uint32_t* flags, hipStream_t s) {
+  if (!total_wgs) return;
+  hipLaunchKernelGGL(k_closure_level, dim3(total_wgs), dim3(kBlock), 0, s, jobs, job_wg_off, njobs,
+                     flags);
+}
+
+void launch_init_minmax(const InstDesc* desc, uint32_t ninst, uint32_t* minF, uint32_t* minN,
+                        hipStream_t s) {
+  if (!ninst) return;
+  hipLaunchKernelGGL(k_init_minmax, dim3(ninst), dim3(kBlock), 0, s, desc, minF, minN);
+}
+
+void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
+                       uint32_t total_wgs, const uint32_t* minF, const uint32_t* minN,
+                       uint32_t* inst_of, uint32_t* block, uint32_t* act, hipStream_t s) {
+  if (!total_wgs) return;
+  hipLaunchKernelGGL(k_init_block, dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, minF,
+                     minN, inst_of, block, act);
+}
+
+void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) {
+  uint32_t grid = grid_for(tsize, kBlock);
+  if (grid > 65536u) grid = 65536u;
+  if (grid == 0) grid = 1;
+  hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl);
+}
+
+void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                      const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
+                      uint32_t* sig, Slot* table, uint32_t tbits, uint32_t* slot_of,
+                      uint64_t salt, hipStream_t s) {
+  if (!m) return;
+  const uint32_t grid = grid_for(m, kBlock);
+  if (batch)
+    hipLaunchKernelGGL(k_signature<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+                       block, sig, table, tbits, slot_of, salt);
+  else
+    hipLaunchKernelGGL(k_signature<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+                       block, sig, table, tbits, slot_of, salt);
+}
+
+void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                    const InstDesc* desc, const uint32_t* sig, const Slot* table,
+                    const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
+                    uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
+                    uint32_t ntiles, hipStream_t s) {
+  if (!m) return;
+  const uint32_t grid = grid_for(m, kBlock);
+  if (batch)
+    hipLaunchKernelGGL(k_resolve<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, sig, table,
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles);
+  else
+    hipLaunchKernelGGL(k_resolve<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, sig, table,
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles);
+}
+
+void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                    const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
+                    uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
+                    unsigned long long* scan_status, hipStream_t s) {
+  if (!m) return;
+  const uint32_t grid = grid_for(m, kScanTile);
+  if (batch)
+    hipLaunchKernelGGL(k_compact<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, nb, keep,
+                       changed_inst, block, act_next, ctrl, scan_status);
+  else
+    hipLaunchKernelGGL(k_compact<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, nb, keep,
+                       changed_inst, block, act_next, ctrl, scan_status);
+}
+
+void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt,
+                      const Ctrl* ctrl, hipStream_t s) {
+  if (!ninst) return;
+  hipLaunchKernelGGL(k_round_end, dim3(grid_for(ninst, kBlock)), dim3(kBlock), 0, s, ninst,
+                     changed_inst, refine_cnt, ctrl);
+}
+
+void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s) {
+  uint32_t grid = grid_for(ntiles ? ntiles : 1, kBlock);
+  hipLaunchKernelGGL(k_prep_scan, dim3(grid), dim3(kBlock), 0, s, scan_status, ntiles, ctrl);
+}
+
+void launch_scan_reps(const uint32_t* block, uint32_t N, uint32_t* rank, Ctrl* ctrl,
+                      unsigned long long* scan_status, hipStream_t s) {
+  if (!N) return;
+  hipLaunchKernelGGL(k_scan_reps, dim3(grid_for(N, kScanTile)), dim3(kBlock), 0, s, block, N, rank, ctrl,
+                     scan_status);
+}
+
+void launch_emit(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
+                 const uint32_t* block, const uint32_t* rank, hipStream_t s) {
+  if (!N) return;
+  if (batch)
+    hipLaunchKernelGGL(k_emit<true>, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, N, inst_of, desc,
+                       block, rank);
+  else
+    hipLaunchKernelGGL(k_emit<false>, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, N, inst_of, desc,
+                       block, rank);
+}
+
+void launch_results(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
+                    const uint32_t* refine_cnt, ResultDev* res, hipStream_t s) {
+  if (!ninst) return;
+  hipLaunchKernelGGL(k_results, dim3(grid_for(ninst, kBlock)), dim3(kBlock), 0, s, ninst, desc, rank,
+                     refine_cnt, res);
+}
+
+}  // namespace dfamin

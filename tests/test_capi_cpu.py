@@ -1,0 +1,52 @@
+"""Host-side checks of the C-ABI library (no GPU compute)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2410_22764_amd import dfamin
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "dfamin.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfamin_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = dfamin.load()
+    declared = _declared_functions()
+    assert len(declared) >= 12
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(dfamin.EXPORTS) == declared
+
+
+def test_status_strings():
+    for code in range(0, -9, -1):
+        s = dfamin.status_str(code)
+        assert s and s != "unknown status"
+    assert dfamin.status_str(-100) == "unknown status"
+
+
+def test_null_arguments_rejected_without_device_work():
+    lib = dfamin.load()
+    assert lib.dfamin_minimize(None, None, None, None, None) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_minimize_device(None, None, None, None, None, None) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_minimize_batch(None, 0, None, None, None, None) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_submit(None, None, None, None) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_cancel(None, 1) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_set_profiling(None, 1) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_create(0, 0, None) == dfamin.DFAMIN_E_INVAL
+
+
+def test_create_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    rc = dfamin.load().dfamin_create(0, 0, ctypes.byref(h))
+    assert rc == dfamin.DFAMIN_E_DEVICE and not h.value

@@ -1,0 +1,224 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle.
+
+Every comparison is exact (integer output, canonical numbering).  Sizes span
+several workgroup tiles (256 states per signature workgroup, 1024 per scan
+tile) and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22764_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_22764_amd import dfamin
+    c = dfamin.dfamin_create(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, d, closure="off", **kw):
+    from paper_2410_22764_amd import dfamin
+    print(f"[case] {d.name} n={d.n} k={d.k} closure={closure}", flush=True)
+    return dfamin.dfamin_minimize(ctx, d, dict(closure=closure, **kw))
+
+
+def _check(ctx, d, closure="off", rounds=None, **kw):
+    out, res = _run(ctx, d, closure, **kw)
+    want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+    assert res["num_blocks"] == nb
+    assert np.array_equal(out, want)
+    assert res["initial_block"] == want[d.q0]
+    if rounds is not None:
+        assert res["refine_rounds"] == rounds
+    assert res["rounds_executed"] == res["refine_rounds"] + 1
+    return out, res
+
+
+SIZES = [1, 2, 7, 63, 255, 256, 257, 1000, 1023, 1024, 1025, 4097, 65537]
+
+
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_random_dfas_match_hopcroft_and_moore_rounds(ctx, n, k):
+    d = W.random_dfa(n, k, seed=n * 31 + k)
+    _, _, mr = oracle.moore(d.n, d.k, d.delta, d.accept)
+    _check(ctx, d, rounds=mr)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4, 5])
+def test_plain_single_workload(ctx, seed):
+    d = W.plain_single(seed)
+    _, _, mr = oracle.moore(d.n, d.k, d.delta, d.accept)
+    _check(ctx, d, rounds=mr)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_coarse_partitions(ctx, seed):
+    """Few accepting states and small alphabets: big classes, skewed groups."""
+    n = [300, 5000, 20000, 70000, 1000, 123457][seed]
+    d = W.random_dfa(n, 1 + seed % 3, seed)
+    acc = np.zeros(n, bool)
+    acc[np.arange(0, n, 97)] = True
+    d.accept = W.pack_accept(acc)
+    _, _, mr = oracle.moore(d.n, d.k, d.delta, d.accept)
+    out, res = _check(ctx, d, rounds=mr)
+
+
+@pytest.mark.parametrize("closure", ["off", "on", "auto"])
+def test_closure_modes_identical(ctx, closure):
+    for seed in range(4):
+        d = W.random_dfa(3000 + seed, 2, seed)
+        _check(ctx, d, closure)
+        c = W.permuted_chain_dfa(777 + seed, 3, seed)
+        out, res = _check(ctx, c, closure)
+        assert np.array_equal(out, np.arange(c.n))
+
+
+def test_closure_round_count_matches_oracle(ctx):
+    for d in [W.chain_dfa(1000, 2), W.permuted_chain_dfa(600, 2, 9), W.fib_dfa(12), W.random_dfa(500, 2, 4)]:
+        _, _, rr = oracle.moore_closure(d.n, d.k, d.delta, d.accept)
+        _, res = _check(ctx, d, "on", rounds=rr)
+        assert res["closure_levels"] == oracle.floor_log2(d.n)
+
+
+def test_figure1_chain(ctx):
+    d = W.chain_dfa(10, 1)
+    _check(ctx, d, "off", rounds=8)
+    _check(ctx, d, "on", rounds=3)
+
+
+def test_deep_chain_workload_closed_form(ctx):
+    """Chain with n = 2^20: every state is its own class; 19 refining rounds
+    with the closure (largest popcount of a distance below 2^20 - 1)."""
+    d = W.deep_chain()
+    out, res = _run(ctx, d, "on")
+    assert res["num_blocks"] == d.n
+    assert np.array_equal(out, np.arange(d.n))
+    assert res["refine_rounds"] == 19 and res["rounds_executed"] == 20
+    assert res["closure_levels"] == 20
+    assert res["closure_letters"] == 21  # the identity letter is dropped
+
+
+def test_deep_chain_auto(ctx):
+    d = W.deep_chain()
+    out, res = _run(ctx, d, "auto")
+    assert res["num_blocks"] == d.n and np.array_equal(out, np.arange(d.n))
+    assert res["closure_levels"] == 20
+
+
+@pytest.mark.parametrize("m", [8, 10, 14, 18])
+def test_fib_family(ctx, m):
+    d = W.fib_dfa(m)
+    out, res = _check(ctx, d, "auto")
+    assert res["num_blocks"] == d.n
+    if d.n < 2000:
+        _check(ctx, d, "off", rounds=d.n - 2)
+
+
+@pytest.mark.parametrize("m", [3, 6, 10, 15])
+def test_bitsplitter_family(ctx, m):
+    d = W.bitsplitter_dfa(m)
+    out, res = _check(ctx, d, "off", rounds=m - 1)
+    assert res["num_blocks"] == 2 ** m
+
+
+def test_degenerate_inputs(ctx):
+    for n in [1, 2, 300, 5000]:
+        for acc in (np.zeros(n, bool), np.ones(n, bool)):
+            d = W.random_dfa(n, 2, n)
+            d.accept = W.pack_accept(acc)
+            out, res = _check(ctx, d, rounds=0)
+            assert res["num_blocks"] == 1 and not out.any()
+    # all letters the identity
+    d = W.from_rows(np.tile(np.arange(100, dtype=np.uint32), (3, 1)), np.arange(100) % 3 == 0)
+    _check(ctx, d, rounds=0)
+    # duplicate letters
+    base = W.random_dfa(999, 2, 3)
+    rows = np.vstack([base.rows(), base.rows()[1], base.rows()[0]])
+    d = W.from_rows(rows, base.accept_bool())
+    out, res = _check(ctx, d)
+    out2, _ = _check(ctx, base)
+    assert np.array_equal(out, out2)
+
+
+def test_bad_transition_rejected_output_untouched(ctx):
+    from paper_2410_22764_amd import dfamin
+    d = W.random_dfa(5000, 3, 1)
+    d.delta = d.delta.copy()
+    d.delta[2 * 5000 + 4321] = 5000
+    out, res = dfamin.dfamin_minimize(ctx, d, None, check=False)
+    assert res["rc"] == dfamin.DFAMIN_E_BAD_DFA
+    # the context still works afterwards
+    _check(ctx, W.random_dfa(100, 2, 2))
+
+
+def test_invalid_arguments(ctx):
+    from paper_2410_22764_amd import dfamin
+    d = W.random_dfa(10, 2, 1)
+    d.q0 = 10
+    _, res = dfamin.dfamin_minimize(ctx, d, None, check=False)
+    assert res["rc"] == dfamin.DFAMIN_E_INVAL
+    d.q0 = 0
+    _, res = dfamin.dfamin_minimize(ctx, d, {"closure": 7}, check=False)
+    assert res["rc"] == dfamin.DFAMIN_E_INVAL
+
+
+def test_round_cap(ctx):
+    from paper_2410_22764_amd import dfamin
+    d = W.chain_dfa(50, 1)
+    _, res = dfamin.dfamin_minimize(ctx, d, dict(closure="off", max_rounds=10), check=False)
+    assert res["rc"] == dfamin.DFAMIN_E_INTERNAL
+
+
+def test_deterministic_repeats(ctx):
+    d = W.random_dfa(200000, 3, 11)
+    a, ra = _run(ctx, d)
+    for _ in range(3):
+        b, rb = _run(ctx, d)
+        assert np.array_equal(a, b) and ra == rb
+
+
+def test_batch_matches_solo_and_oracle(ctx):
+    from paper_2410_22764_amd import dfamin
+    dfas = W.batch_mixed(seed=3, count=96, n_min=16, n_max=5000)
+    dfas.append(W.random_dfa(1, 2, 0))
+    dfas.append(W.chain_dfa(64, 1))
+    for closure in ["off", "auto", "on"]:
+        print(f"[case] batch closure={closure}", flush=True)
+        outs, results = dfamin.dfamin_minimize_batch(ctx, dfas, dict(closure=closure))
+        for d, o, r in zip(dfas, outs, results):
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert r["num_blocks"] == nb and np.array_equal(o, want), d.name
+            solo, rs = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+            assert np.array_equal(solo, o)
+            assert rs["refine_rounds"] == r["refine_rounds"]
+
+
+def test_batch_bad_instance(ctx):
+    from paper_2410_22764_amd import dfamin
+    dfas = [W.random_dfa(100, 2, i) for i in range(5)]
+    dfas[3].delta = dfas[3].delta.copy()
+    dfas[3].delta[7] = 1000
+    outs, results = dfamin.dfamin_minimize_batch(ctx, dfas, None, check=False)
+    assert results[0]["rc"] == dfamin.DFAMIN_E_BAD_DFA
+    assert [r["status"] for r in results] == [0, 0, 0, dfamin.DFAMIN_E_BAD_DFA, 0]
+
+
+def test_device_entry_point_with_torch_buffers(ctx):
+    import torch
+    from paper_2410_22764_amd import dfamin
+    d = W.random_dfa(123457, 4, 5)
+    dev = torch.device("cuda:0")
+    delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+    accept = torch.from_numpy(d.accept).to(dev)
+    out = torch.full((d.n,), -1, dtype=torch.int32, device=dev)
+    res = dfamin.dfamin_minimize_device(ctx, d.n, d.k, delta.data_ptr(), accept.data_ptr(), d.q0,
+                                        out.data_ptr(), stream=torch.cuda.current_stream().cuda_stream)
+    got = out.cpu().numpy().view(np.uint32)
+    want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+    assert res["num_blocks"] == nb and np.array_equal(got, want)
