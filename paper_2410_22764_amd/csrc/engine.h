@@ -45,10 +45,12 @@ class Profiler {
   struct Pending {
     int stat;
     hipEvent_t a, b;
+    double bytes;
   };
   int stat_index(const char* name);
   hipEvent_t get_event();
   bool on_ = false;
+  bool trace_ = false;  // DFAMIN_TRACE set: print every timed launch to stderr
   std::vector<dfamin_kernel_stat> stats_;
   std::vector<Pending> pending_;
   std::vector<hipEvent_t> free_events_;
@@ -102,7 +104,8 @@ class Engine {
   DevBuf d_desc_, d_rows_, d_jobs_, d_joboff_, d_flags_, d_inst_off_, d_minF_, d_minN_;
   DevBuf d_inst_of_, d_block_, d_act_, d_act2_, d_slot_of_, d_nb_, d_keep_, d_rank_;
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_, d_closure_;
-  HostBuf h_ctrl_, h_flags_, h_results_;
+  DevBuf d_wgflags_, d_part_, d_dense_, d_counts_;
+  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_;
 };
 
 // The object behind dfamin_ctx.

@@ -13,6 +13,8 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace dfamin {
@@ -50,6 +52,8 @@ Profiler::~Profiler() {
 
 void Profiler::set_enabled(bool on) {
   on_ = on;
+  const char* t = std::getenv("DFAMIN_TRACE");
+  trace_ = t && *t && *t != '0';
   if (on) stats_.clear();
 }
 
@@ -76,6 +80,7 @@ hipEvent_t Profiler::get_event() {
 void Profiler::begin(hipStream_t s, const char* name, double alg_bytes) {
   if (!on_) return;
   cur_.stat = stat_index(name);
+  cur_.bytes = alg_bytes;
   stats_[cur_.stat].alg_bytes += alg_bytes;
   stats_[cur_.stat].launches += 1;
   cur_.a = get_event();
@@ -93,6 +98,9 @@ void Profiler::collect() {
   for (auto& p : pending_) {
     float ms = 0.f;
     if (p.a && p.b && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) stats_[p.stat].total_ms += ms;
+    if (trace_)
+      std::fprintf(stderr, "[dfamin] %-14s %9.1f us %8.1f GB/s\n", stats_[p.stat].name, 1e3 * ms,
+                   ms > 0 ? p.bytes / (ms * 1e-3) / 1e9 : 0.0);
     if (p.a) free_events_.push_back(p.a);
     if (p.b) free_events_.push_back(p.b);
   }
@@ -110,10 +118,11 @@ Engine::~Engine() {
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
-                    &d_results_, &d_ctrl_, &d_closure_};
+                    &d_results_, &d_ctrl_, &d_closure_, &d_wgflags_, &d_part_, &d_dense_,
+                    &d_counts_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
-  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_};
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -122,7 +131,8 @@ uint64_t Engine::device_bytes() const {
   const DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                           &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
-                          &d_results_, &d_ctrl_, &d_closure_};
+                          &d_results_, &d_ctrl_, &d_closure_, &d_wgflags_, &d_part_, &d_dense_,
+                          &d_counts_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   return t;
@@ -291,9 +301,12 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
   }
   lvl_job_begin[Lmax + 1] = (uint32_t)jobs.size();
   if (!jobs.empty()) {
+    uint32_t max_wgs = 0;
+    for (uint32_t l = 1; l <= Lmax; ++l) max_wgs = std::max(max_wgs, lvl_wg_total[l]);
     TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
     TRY(ensure(d_joboff_, joboff.size() * 4));
     TRY(ensure(d_flags_, jobs.size() * 4));
+    TRY(ensure(d_wgflags_, (size_t)max_wgs * 4));
     HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
     HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
     HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
@@ -304,7 +317,7 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
       for (uint32_t j = b; j < e; ++j) bytes += 12.0 * jobs[j].n;
       ctx_->prof.begin(s, "closure_level", bytes);
       launch_closure_level(d_jobs_.as<RowJob>() + b, d_joboff_.as<uint32_t>() + b, e - b,
-                           lvl_wg_total[l], d_flags_.as<uint32_t>(), s);
+                           lvl_wg_total[l], d_wgflags_.as<uint32_t>(), d_flags_.as<uint32_t>() + b, s);
       ctx_->prof.end(s);
       HIP(hipGetLastError());
     }
@@ -348,7 +361,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   uint64_t N = 0;
   uint32_t nmax = 0;
   for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
-  if (N >= 0xFFFFFF00ull) return DFAMIN_E_INVAL;
+  if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // active indices are 31-bit in hash slots
   N_ = N;
   closure_used_ = 0;
   Profiler& prof = ctx_->prof;
@@ -372,6 +385,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
   TRY(ensure(d_joboff_, joboff.size() * 4));
   TRY(ensure(d_flags_, jobs.size() * 4));
+  TRY(ensure(d_wgflags_, (size_t)wgs * 4));
   TRY(ensure_host(h_flags_, jobs.size() * 4));
   HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
   HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
@@ -381,7 +395,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     for (auto& x : in_) bytes += 4.0 * x.n * x.k;
     prof.begin(s, "validate", bytes);
     launch_row_check(d_jobs_.as<RowJob>(), d_joboff_.as<uint32_t>(), (uint32_t)jobs.size(), wgs,
-                     d_flags_.as<uint32_t>(), s);
+                     d_wgflags_.as<uint32_t>(), d_flags_.as<uint32_t>(), s);
     prof.end(s);
     HIP(hipGetLastError());
   }
@@ -450,8 +464,10 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   TRY(ensure(d_ctrl_, sizeof(Ctrl)));
   TRY(ensure(d_inst_off_, I * 4));
   if (batch) TRY(ensure(d_inst_of_, N * 4));
+  TRY(ensure(d_counts_, I * 4));
   TRY(ensure_host(h_ctrl_, sizeof(Ctrl)));
   TRY(ensure_host(h_results_, I * sizeof(ResultDev)));
+  TRY(ensure_host(h_counts_, I * 4));
   TRY(upload_layout(s));
   // workgroup offsets of the per-instance init jobs
   std::vector<uint32_t> inst_off(I);
@@ -461,14 +477,15 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
   }
   HIP(hipMemcpyAsync(d_inst_off_.p, inst_off.data(), I * 4, hipMemcpyHostToDevice, s));
+  TRY(ensure(d_part_, (size_t)init_wgs * 8));
   HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
 
   // ---- 4. initial partition {F, Q\F}
-  prof.begin(s, "init_minmax", 0.0);
-  launch_init_minmax(d_desc_.as<InstDesc>(), (uint32_t)I, d_minF_.as<uint32_t>(),
-                     d_minN_.as<uint32_t>(), s);
+  prof.begin(s, "init_minmax", (double)N / 8.0);
+  launch_init_minmax(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
+                     d_part_.as<unsigned long long>(), d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(), s);
   prof.end(s);
   prof.begin(s, "init_block", (8.125 + (batch ? 4.0 : 0.0)) * (double)N);
   launch_init_block(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
@@ -484,6 +501,8 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   bool any_auto = false;
   for (auto& x : in_) any_auto |= (x.closure == DFAMIN_CLOSURE_AUTO);
   uint64_t m = N;
+  // upper bound on each instance's block count before the next round
+  std::vector<uint64_t> ub(I, 2);
   uint32_t* cur = d_act_.as<uint32_t>();
   uint32_t* nxt = d_act2_.as<uint32_t>();
   uint64_t salt = 0x5DEECE66Dull;
@@ -512,6 +531,57 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
       }
     }
     if (rounds >= max_rounds) return DFAMIN_E_INTERNAL;
+    // Key mode per instance (see InstDesc): exact keys while
+    // (kp+1) * ceil(log2 B) fits in 31 bits, B = blocks before this round.
+    {
+      bool need_dense = false, dirty = false;
+      auto decide = [&](bool exact_counts) {
+        need_dense = false;
+        for (size_t i = 0; i < I; ++i) {
+          const uint64_t kp1 = desc_[i].kp + 1ull;
+          uint32_t eb = 0, ds = 0;
+          if (rounds == 0) {
+            if (kp1 <= 31) { eb = 1; ds = 1; }
+          } else {
+            const uint64_t B = exact_counts ? std::max<uint64_t>(h_counts_.as<uint32_t>()[i], 1) : ub[i];
+            const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
+            if (kp1 * bits <= 31) { eb = bits; need_dense = true; }
+          }
+          if (desc_[i].ebits != eb || desc_[i].dsrc != ds) {
+            desc_[i].ebits = eb;
+            desc_[i].dsrc = ds;
+            dirty = true;
+          }
+        }
+      };
+      decide(false);
+      if (need_dense) {
+        // exact block counts and dense numbers from a scan over all states
+        const uint32_t nt = (uint32_t)((N + kScanTile - 1) / kScanTile);
+        launch_prep_scan(d_status_.as<unsigned long long>(), nt, d_ctrl_.as<Ctrl>(), s);
+        prof.begin(s, "scan_reps", 8.0 * (double)N);
+        launch_scan_reps(d_block_.as<uint32_t>(), (uint32_t)N, d_rank_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                         d_status_.as<unsigned long long>(), s);
+        prof.end(s);
+        launch_block_counts((uint32_t)I, d_desc_.as<InstDesc>(), d_rank_.as<uint32_t>(),
+                            d_counts_.as<uint32_t>(), s);
+        HIP(hipGetLastError());
+        HIP(hipMemcpyAsync(h_counts_.p, d_counts_.p, I * 4, hipMemcpyDeviceToHost, s));
+        HIP(hipStreamSynchronize(s));
+        prof.collect();
+        for (size_t i = 0; i < I; ++i) ub[i] = std::max<uint64_t>(h_counts_.as<uint32_t>()[i], 1);
+        decide(true);
+        if (need_dense) {
+          TRY(ensure(d_dense_, N * 4));
+          prof.begin(s, "dense", (12.0 + (batch ? 4.0 : 0.0)) * (double)N);
+          launch_dense(batch, (uint32_t)N, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                       d_block_.as<uint32_t>(), d_rank_.as<uint32_t>(), d_dense_.as<uint32_t>(), s);
+          prof.end(s);
+        }
+      }
+      if (dirty)
+        HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    }
     const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * m));
     const uint64_t tsize = 1ull << tbits;
     TRY(ensure(d_table_, tsize * sizeof(Slot)));
@@ -519,15 +589,16 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     const double md = (double)m;
     const double inst_b = batch ? 4.0 : 0.0;
 
-    prof.begin(s, "clear_table", 16.0 * (double)tsize);
+    prof.begin(s, "clear_table", 8.0 * (double)tsize);
     launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
     prof.end(s);
-    prof.begin(s, "signature", md * (4 + inst_b + 4 + 8 * kpbar + 4 * (kpbar + 1) + 4 + 16));
+    prof.begin(s, "signature", md * (4 + inst_b + 4 + 8 * kpbar + 4 * (kpbar + 1) + 4 + 8));
     launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_sig_.as<uint32_t>(),
-                     d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, s);
+                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.as<uint32_t>(),
+                     d_sig_.as<uint32_t>(), d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt,
+                     s);
     prof.end(s);
-    prof.begin(s, "resolve", md * (4 + inst_b + 4 + 16 + 4 + 4 + 1));
+    prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
     launch_resolve(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                    d_sig_.as<uint32_t>(), d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
                    d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(), d_keep_.as<uint8_t>(),
@@ -546,12 +617,22 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     HIP(hipStreamSynchronize(s));
     prof.collect();
     const Ctrl c = *h_ctrl_.as<Ctrl>();
+    if (prof.enabled() && std::getenv("DFAMIN_TRACE"))
+      std::fprintf(stderr, "[dfamin] round %llu: m=%llu table=2^%u next=%u changed=%u collision=%u\n",
+                   (unsigned long long)rounds + 1, (unsigned long long)m, tbits, c.m_next, c.any_changed,
+                   c.collision);
     if (c.collision) {
       if (++retries > kMaxSaltRetries) return DFAMIN_E_INTERNAL;
       salt = mix64(salt + 0x9E3779B97F4A7C15ull);
       continue;
     }
     ++rounds;
+    for (size_t i = 0; i < I; ++i) {
+      // a round maps each block to at most B^(kp+1) signatures
+      const uint64_t kp1 = desc_[i].kp + 1ull;
+      const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(ub[i]));
+      ub[i] = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
+    }
     std::swap(cur, nxt);
     m = c.m_next;
     if (!c.any_changed) break;

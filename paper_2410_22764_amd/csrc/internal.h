@@ -20,12 +20,23 @@
 namespace dfamin {
 
 constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
-constexpr int kScanItems = 4;         // items per thread in scan / compaction tiles
+constexpr int kScanItems = 8;         // items per thread in scan / compaction tiles
 constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kLocalSlots = 512;      // LDS hash slots per signature workgroup
+constexpr int kSigItems = 2;          // states per thread in the signature kernel
+constexpr int kSigTile = kBlock * kSigItems;
+constexpr int kLocalSlots = 2 * kSigTile;  // LDS hash slots per signature workgroup
 constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
 
-// Per-instance descriptor (device copy).  48 bytes.
+// Per-instance descriptor (device copy).  64 bytes.
+//
+// Key mode of the current round.  With B blocks before the round, a state's
+// signature (own block, successor blocks) in dense block numbers 0..B-1 is
+// an exact integer of (kp+1)*ceil(log2 B) bits.  When that fits in 31 bits
+// (ebits > 0) the round groups on that exact key: no hashing shortcut, so no
+// signature records and no verification.  Otherwise (ebits == 0) it groups
+// on a 64-bit hash and verifies full signatures.  Dense numbers come from
+// the accept bitmap while the partition is still {F, Q\F} (dsrc == 1) or
+// from the dense[] array (dsrc == 0).
 struct InstDesc {
   uint32_t state_off;   // first global state id
   uint32_t n;           // states
@@ -36,14 +47,20 @@ struct InstDesc {
   uint64_t out;         // device address of the output (n uint32)
   uint32_t q0;
   uint32_t k;           // original alphabet size
+  uint32_t ebits;       // bits per key component in exact mode, 0 = hash mode
+  uint32_t dsrc;        // exact mode: 1 = accept bit, 0 = dense[] array
+  uint64_t pad;
 };
 
-// Global hash-table slot: 16 bytes.  key == 0 marks an empty slot.
-struct Slot {
-  unsigned long long key;  // 64-bit signature hash (never 0)
-  uint32_t jmin;           // least active index with this hash
-  uint32_t cnt;            // number of active states with this hash
-};
+// Global hash-table slot: one 64-bit word, 0 = empty.
+//   bits 63..32  fragment of the signature hash (never 0)
+//   bit  31      shared: at least two active states carry this hash
+//   bits 30..0   least active-list index carrying this hash
+// The home position comes from the low hash bits, the fragment from the high
+// ones.  A slot is claimed, joined and lowered with 64-bit CAS only.
+typedef unsigned long long Slot;
+constexpr uint32_t kSlotShared = 0x80000000u;
+constexpr uint32_t kSlotIndexMask = 0x7fffffffu;
 
 // Control block shared by the round kernels and read by the host.
 struct Ctrl {
@@ -79,20 +96,32 @@ constexpr uint32_t kFlagDiffers = 4u;  // closure level differs from the previou
 // Kernel launchers (kernels.hip).  All are asynchronous on `s`.
 // Jobs: a list of work units each covering `len` elements; job_wg_off[j] is
 // the first workgroup of job j (exclusive prefix over ceil(len/tile)).
+// Row checks write one flag word per workgroup (wg_flags) and then OR them
+// into one word per job (flags); no contended atomics.
 void launch_row_check(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
-                      uint32_t total_wgs, uint32_t* flags, hipStream_t s);
+                      uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s);
 void launch_closure_level(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
-                          uint32_t total_wgs, uint32_t* flags, hipStream_t s);
-void launch_init_minmax(const InstDesc* desc, uint32_t ninst, uint32_t* minF, uint32_t* minN,
-                        hipStream_t s);
+                          uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s);
+// Least accepting / non-accepting state per instance: per-workgroup partial
+// minima over the instance's states, reduced per instance.
+void launch_init_minmax(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
+                        uint32_t total_wgs, unsigned long long* wg_part, uint32_t* minF,
+                        uint32_t* minN, hipStream_t s);
 void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
                        uint32_t total_wgs, const uint32_t* minF, const uint32_t* minN,
                        uint32_t* inst_of, uint32_t* block, uint32_t* act, hipStream_t s);
 void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s);
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
-                      uint32_t* sig, Slot* table, uint32_t tbits, uint32_t* slot_of,
-                      uint64_t salt, hipStream_t s);
+                      const uint32_t* dense, uint32_t* sig, Slot* table, uint32_t tbits,
+                      uint32_t* slot_of, uint64_t salt, hipStream_t s);
+// dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
+// instance's blocks in order of least member.
+void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
+                  const uint32_t* block, const uint32_t* rank, uint32_t* dense, hipStream_t s);
+// counts[i] = number of blocks of instance i (from rank).
+void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
+                         uint32_t* counts, hipStream_t s);
 void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const InstDesc* desc, const uint32_t* sig, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,

@@ -3,10 +3,10 @@
 // One refinement round (the loop body of the paper's Algorithm 4, Section
 // 3.3) is four kernels over the active list:
 //   k_signature  gather: sig(q) = (block[q], block[delta'(q,a)] for a in
-//                Sigma'), a 64-bit hash of it, workgroup-local grouping of
-//                equal hashes in LDS and one global hash-table insert per
-//                local group (hash grouping, the alternative to sorting that
-//                the paper attributes to Tewari et al.);
+//                Sigma'), a 64-bit hash of it, grouping of equal hashes in
+//                LDS and one global hash-table update per local group (hash
+//                grouping, the alternative to sorting that the paper
+//                attributes to Tewari et al.);
 //   k_resolve    every state learns its group's least member (the new block
 //                id) and checks its full signature against that member's,
 //                so grouping is exact and never trusts a hash alone;
@@ -19,7 +19,9 @@
 //
 // Cross-workgroup communication inside a kernel happens only through device
 // atomics (hash slots, look-back status words); everything else is handed
-// from one kernel to the next.
+// from one kernel to the next.  Per-workgroup partial results (flags, minima)
+// are written to their own words and reduced by a second kernel, so no
+// address is hammered by thousands of workgroups.
 #include "internal.h"
 
 namespace dfamin {
@@ -40,7 +42,7 @@ __device__ __forceinline__ uint64_t hash_final(uint64_t h) {
   h ^= h >> 32;
   h *= 0xD6E8FEB86659FD93ull;
   h ^= h >> 32;
-  return h ? h : 1ull;  // 0 marks an empty slot
+  return h ? h : 1ull;  // 0 marks an empty LDS slot
 }
 
 __device__ __forceinline__ unsigned long long load_status(unsigned long long* p) {
@@ -51,30 +53,45 @@ __device__ __forceinline__ void store_status(unsigned long long* p, unsigned lon
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Decoupled look-back (one thread): publishes this tile's aggregate, sums the
-// predecessors' values back to the first inclusive prefix, publishes its own
-// inclusive prefix and returns the exclusive one.  Tiles are numbered in the
-// order workgroups obtained them, so every predecessor is running or done.
-__device__ uint32_t lookback(unsigned long long* status, uint32_t tile, uint32_t total) {
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Decoupled look-back by the first wave of the workgroup: publishes this
+// tile's aggregate, then reads 64 predecessors at a time and adds their
+// aggregates back to the first inclusive prefix; publishes its own inclusive
+// prefix and returns the exclusive one (valid in wave 0).  Tiles are numbered
+// in the order workgroups obtained them, so every predecessor is running or
+// done and the wait ends.
+__device__ uint32_t lookback_wave0(unsigned long long* status, uint32_t tile, uint32_t total) {
+  const uint32_t lane = threadIdx.x & 63u;
   if (tile == 0) {
-    store_status(&status[0], kFlagPrefix | total);
+    if (lane == 0) store_status(&status[0], kFlagPrefix | total);
     return 0;
   }
-  store_status(&status[tile], kFlagAgg | total);
+  if (lane == 0) store_status(&status[tile], kFlagAgg | total);
   uint32_t excl = 0;
-  int t = (int)tile - 1;
+  int base = (int)tile - 1;
   while (true) {
-    unsigned long long v = load_status(&status[t]);
-    unsigned long long flag = v >> 62;
-    if (flag == 0) {
+    const int t = base - (int)lane;
+    // positions before tile 0 act as an inclusive prefix of 0
+    const unsigned long long v = (t >= 0) ? load_status(&status[t]) : kFlagPrefix;
+    const uint32_t flag = (uint32_t)(v >> 62);
+    const unsigned long long not_ready = __ballot(flag == 0);
+    const unsigned long long is_prefix = __ballot(flag == 2);
+    const int first_p = is_prefix ? (int)__builtin_ctzll(is_prefix) : 63;
+    const unsigned long long need = (first_p >= 63) ? ~0ull : ((2ull << first_p) - 1ull);
+    if (not_ready & need) {
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
-    excl += (uint32_t)v;
-    if (flag == 2) break;
-    --t;
+    excl += wave_sum(((int)lane <= first_p) ? (uint32_t)v : 0u);
+    if (is_prefix) break;
+    base -= 64;
   }
-  store_status(&status[tile], kFlagPrefix | (unsigned long long)(excl + total));
+  if (lane == 0) store_status(&status[tile], kFlagPrefix | (unsigned long long)(excl + total));
   return excl;
 }
 
@@ -121,12 +138,24 @@ __device__ __forceinline__ uint32_t find_job(const uint32_t* job_wg_off, uint32_
   return *s_job;
 }
 
+// OR of one flag word per thread into a single word per workgroup.
+__device__ __forceinline__ uint32_t block_or(uint32_t bits, uint32_t* s_or) {
+  if (threadIdx.x == 0) *s_or = 0;
+  __syncthreads();
+  const uint32_t lane = threadIdx.x & 63u;
+  bool b0 = __any(bits & 1u), b1 = __any(bits & 2u), b2 = __any(bits & 4u);
+  uint32_t w = (b0 ? 1u : 0u) | (b1 ? 2u : 0u) | (b2 ? 4u : 0u);
+  if (lane == 0 && w) atomicOr(s_or, w);
+  __syncthreads();
+  return *s_or;
+}
+
 // ---------------------------------------------------------------- row jobs
-// Algorithmic bytes: 4 per element read.
+// Validation and identity detection.  Algorithmic bytes: 4 per element read.
 __global__ __launch_bounds__(kBlock) void k_row_check(const RowJob* __restrict__ jobs,
                                                       const uint32_t* __restrict__ job_wg_off,
-                                                      uint32_t njobs, uint32_t* __restrict__ flags) {
-  __shared__ uint32_t s_job;
+                                                      uint32_t njobs, uint32_t* __restrict__ wg_flags) {
+  __shared__ uint32_t s_job, s_or;
   const uint32_t j = find_job(job_wg_off, njobs, &s_job);
   const RowJob J = jobs[j];
   const uint32_t* __restrict__ row = reinterpret_cast<const uint32_t*>(J.src);
@@ -141,10 +170,8 @@ __global__ __launch_bounds__(kBlock) void k_row_check(const RowJob* __restrict__
       if (v != q) bits |= kFlagNonId;
     }
   }
-  // wave-aggregate before touching the flag word
-  bool any_bad = __any(bits & kFlagBad), any_nonid = __any(bits & kFlagNonId);
-  if ((threadIdx.x & 63u) == 0 && (any_bad || any_nonid))
-    atomicOr(&flags[J.flag_idx], (any_bad ? kFlagBad : 0u) | (any_nonid ? kFlagNonId : 0u));
+  const uint32_t w = block_or(bits, &s_or);
+  if (threadIdx.x == 0) wg_flags[blockIdx.x] = w;
 }
 
 // One closure level for every job: dst[q] = src[src[q]] (Algorithm 5).
@@ -152,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_row_check(const RowJob* __restrict__
 __global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restrict__ jobs,
                                                           const uint32_t* __restrict__ job_wg_off,
                                                           uint32_t njobs,
-                                                          uint32_t* __restrict__ flags) {
-  __shared__ uint32_t s_job;
+                                                          uint32_t* __restrict__ wg_flags) {
+  __shared__ uint32_t s_job, s_or;
   const uint32_t j = find_job(job_wg_off, njobs, &s_job);
   const RowJob J = jobs[j];
   const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(J.src);
@@ -165,52 +192,102 @@ __global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restri
     uint32_t q = base + e * kBlock + threadIdx.x;
     s1[e] = (q < J.n) ? src[q] : 0u;
   }
-  bool differs = false, nonid = false;
+  uint32_t bits = 0;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     uint32_t q = base + e * kBlock + threadIdx.x;
     if (q < J.n) {
       uint32_t s2 = src[s1[e]];
       dst[q] = s2;
-      differs |= (s2 != s1[e]);
-      nonid |= (s2 != q);
+      if (s2 != s1[e]) bits |= kFlagDiffers;
+      if (s2 != q) bits |= kFlagNonId;
     }
   }
-  bool d = __any(differs), ni = __any(nonid);
-  if ((threadIdx.x & 63u) == 0 && (d || ni))
-    atomicOr(&flags[J.flag_idx], (d ? kFlagDiffers : 0u) | (ni ? kFlagNonId : 0u));
+  const uint32_t w = block_or(bits, &s_or);
+  if (threadIdx.x == 0) wg_flags[blockIdx.x] = w;
+}
+
+// flags[j] = OR of the workgroup flags of job j (one workgroup per job).
+__global__ __launch_bounds__(kBlock) void k_flags_reduce(const uint32_t* __restrict__ job_wg_off,
+                                                         uint32_t njobs, uint32_t total_wgs,
+                                                         const uint32_t* __restrict__ wg_flags,
+                                                         uint32_t* __restrict__ flags) {
+  __shared__ uint32_t s_or;
+  const uint32_t j = blockIdx.x;
+  const uint32_t b = job_wg_off[j], e = (j + 1 < njobs) ? job_wg_off[j + 1] : total_wgs;
+  uint32_t bits = 0;
+  for (uint32_t w = b + threadIdx.x; w < e; w += kBlock) bits |= wg_flags[w];
+  const uint32_t r = block_or(bits, &s_or);
+  if (threadIdx.x == 0) flags[j] = r;
 }
 
 // ---------------------------------------------------------------- init
-// Least accepting and least non-accepting state of each instance (the two
-// initial blocks {F, Q\F} of Algorithm 4, named by their least members).
-// One workgroup per instance scans the bitmap from the front and stops as
-// soon as both are found.
-__global__ __launch_bounds__(kBlock) void k_init_minmax(const InstDesc* __restrict__ desc,
-                                                        uint32_t* __restrict__ minF,
-                                                        uint32_t* __restrict__ minN) {
-  __shared__ uint32_t sF, sN;
-  const InstDesc D = desc[blockIdx.x];
+// Per-workgroup least accepting and least non-accepting state of its chunk
+// of one instance (the two initial blocks {F, Q\F} of Algorithm 4 are named
+// by their least members).  Partial: (minF << 32) | minN.
+__global__ __launch_bounds__(kBlock) void k_init_minmax_part(const InstDesc* __restrict__ desc,
+                                                             const uint32_t* __restrict__ job_wg_off,
+                                                             uint32_t ninst,
+                                                             unsigned long long* __restrict__ part) {
+  __shared__ uint32_t s_job, sF, sN;
+  const uint32_t i = find_job(job_wg_off, ninst, &s_job);
+  const InstDesc D = desc[i];
   const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
   if (threadIdx.x == 0) { sF = 0xffffffffu; sN = 0xffffffffu; }
   __syncthreads();
+  // kRowTile states = kRowTile/8 bytes per workgroup
+  const uint32_t b = (blockIdx.x - job_wg_off[i]) * (kRowTile / 8) + threadIdx.x;
   const uint32_t nbytes = (D.n + 7) >> 3;
-  for (uint32_t b0 = 0; b0 < nbytes; b0 += kBlock) {
-    uint32_t b = b0 + threadIdx.x;
-    if (b < nbytes) {
-      uint32_t valid = D.n - b * 8;
-      uint32_t vmask = valid >= 8 ? 0xffu : ((1u << valid) - 1u);
-      uint32_t v = acc[b];
-      uint32_t f = v & vmask, nf = ~v & vmask;
-      if (f) atomicMin(&sF, b * 8 + __builtin_ctz(f));
-      if (nf) atomicMin(&sN, b * 8 + __builtin_ctz(nf));
-    }
-    __syncthreads();
-    bool done = (sF != 0xffffffffu) && (sN != 0xffffffffu);
-    __syncthreads();
-    if (done) break;
+  uint32_t mf = 0xffffffffu, mn = 0xffffffffu;
+  if (threadIdx.x < kRowTile / 8 && b < nbytes) {
+    const uint32_t valid = D.n - b * 8;
+    const uint32_t vmask = valid >= 8 ? 0xffu : ((1u << valid) - 1u);
+    const uint32_t v = acc[b];
+    const uint32_t f = v & vmask, nf = ~v & vmask;
+    if (f) mf = b * 8 + __builtin_ctz(f);
+    if (nf) mn = b * 8 + __builtin_ctz(nf);
   }
-  if (threadIdx.x == 0) { minF[blockIdx.x] = sF; minN[blockIdx.x] = sN; }
+  // wave minima, then one LDS atomic per wave
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mf = min(mf, (uint32_t)__shfl_xor(mf, off, 64));
+    mn = min(mn, (uint32_t)__shfl_xor(mn, off, 64));
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    atomicMin(&sF, mf);
+    atomicMin(&sN, mn);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((unsigned long long)sF << 32) | sN;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_minmax_reduce(const uint32_t* __restrict__ job_wg_off,
+                                                               uint32_t ninst, uint32_t total_wgs,
+                                                               const unsigned long long* __restrict__ part,
+                                                               uint32_t* __restrict__ minF,
+                                                               uint32_t* __restrict__ minN) {
+  __shared__ uint32_t sF, sN;
+  const uint32_t i = blockIdx.x;
+  const uint32_t b = job_wg_off[i], e = (i + 1 < ninst) ? job_wg_off[i + 1] : total_wgs;
+  if (threadIdx.x == 0) { sF = 0xffffffffu; sN = 0xffffffffu; }
+  __syncthreads();
+  uint32_t mf = 0xffffffffu, mn = 0xffffffffu;
+  for (uint32_t w = b + threadIdx.x; w < e; w += kBlock) {
+    const unsigned long long v = part[w];
+    mf = min(mf, (uint32_t)(v >> 32));
+    mn = min(mn, (uint32_t)v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mf = min(mf, (uint32_t)__shfl_xor(mf, off, 64));
+    mn = min(mn, (uint32_t)__shfl_xor(mn, off, 64));
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    atomicMin(&sF, mf);
+    atomicMin(&sN, mn);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) { minF[i] = sF; minN[i] = sN; }
 }
 
 // block[g] = least member of g's initial block; act = all states.
@@ -243,32 +320,66 @@ __global__ __launch_bounds__(kBlock) void k_init_block(const InstDesc* __restric
 }
 
 // ---------------------------------------------------------------- round
+// Algorithmic bytes: 8 per slot.
 __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table, uint64_t tsize,
                                                         Ctrl* __restrict__ ctrl) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->any_changed = 0;
     ctrl->collision = 0;
   }
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t s = (uint64_t)blockIdx.x * kBlock + threadIdx.x; s < tsize; s += stride) {
-    Slot e;
-    e.key = 0ull;
-    e.jmin = 0xffffffffu;
-    e.cnt = 0u;
-    table[s] = e;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock * 2;
+  for (uint64_t s = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2; s < tsize; s += stride) {
+    table[s] = 0ull;
+    if (s + 1 < tsize) table[s + 1] = 0ull;
   }
 }
 
-// Signature gather + grouping by hash.  Algorithmic bytes per active state:
-// 4 (act) [+4 inst_of] + 4 (own block) + 8*kp (delta' row entry and the
-// gathered successor block per letter) + 4*(kp+1) (signature record) + 4
-// (slot id) + 16 (one hash-slot update per local group, upper bound).
+// Insert a local group (least index j, `shared` if it already has two
+// members) into the global table; returns the slot.  The plain load is a
+// shortcut only: a stale value just leads to a CAS that returns the current
+// one, and slot words change monotonically (claimed once, index only
+// lowered, shared bit only set).
+__device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint64_t mask, uint64_t h,
+                                                 uint32_t frag, uint32_t j, bool shared) {
+  uint64_t p = h & mask;
+  const unsigned long long mine =
+      ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)j;
+  while (true) {
+    unsigned long long cur = table[p];
+    if (cur == 0ull) {
+      const unsigned long long prev = atomicCAS(&table[p], 0ull, mine);
+      if (prev == 0ull) return (uint32_t)p;
+      cur = prev;
+    }
+    if ((uint32_t)(cur >> 32) == frag) {
+      while (true) {
+        const uint32_t lo = (uint32_t)cur;
+        const uint32_t want_lo = min(lo & kSlotIndexMask, j) | kSlotShared;
+        if (want_lo == lo) break;
+        const unsigned long long want = (cur & 0xffffffff00000000ull) | want_lo;
+        const unsigned long long prev = atomicCAS(&table[p], cur, want);
+        if (prev == cur) break;
+        cur = prev;
+      }
+      return (uint32_t)p;
+    }
+    p = (p + 1) & mask;
+  }
+}
+
+// Signature gather + grouping.  Hash mode: algorithmic bytes per active
+// state 4 (act) [+4 inst_of] + 4 (own block) + 8*kp (delta' row entry and
+// the gathered successor block per letter) + 4*(kp+1) (signature record) + 4
+// (slot id) + 8 (one hash-slot update per local group, upper bound).  Exact
+// mode: the same without the record, with dense numbers (or accept bits)
+// gathered instead of block ids.
 template <bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_signature(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
-    const uint32_t* __restrict__ block, uint32_t* __restrict__ sig, Slot* __restrict__ table,
-    uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt) {
+    const uint32_t* __restrict__ block, const uint32_t* __restrict__ dense,
+    uint32_t* __restrict__ sig, Slot* __restrict__ table, uint32_t tbits,
+    uint32_t* __restrict__ slot_of, uint64_t salt) {
   __shared__ unsigned long long lkey[kLocalSlots];
   __shared__ uint32_t lmin[kLocalSlots], lcnt[kLocalSlots], lslot[kLocalSlots];
   for (uint32_t s = threadIdx.x; s < kLocalSlots; s += kBlock) {
@@ -277,68 +388,106 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     lcnt[s] = 0u;
   }
   __syncthreads();
-  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  const bool valid = j < m;
-  uint64_t h = 0;
-  uint32_t lp = 0;
-  if (valid) {
+  uint64_t h[kSigItems];
+  uint32_t frag[kSigItems], lp[kSigItems], jj[kSigItems];
+  bool valid[kSigItems];
+#pragma unroll
+  for (int e = 0; e < kSigItems; ++e) {
+    const uint32_t j = blockIdx.x * kSigTile + e * kBlock + threadIdx.x;
+    jj[e] = j;
+    valid[e] = j < m;
+    h[e] = 0;
+    frag[e] = 0;
+    lp[e] = 0;
+    if (!valid[e]) continue;
     const uint32_t g = act[j];
     const uint32_t i = BATCH ? inst_of[g] : 0u;
     const InstDesc D = desc[i];
     const uint32_t q = g - D.state_off;
     const uint32_t kp = D.kp;
-    uint32_t* __restrict__ rec = sig + D.sig_off + (uint64_t)q * (kp + 1);
-    const uint32_t own = block[g];
-    rec[0] = own;
-    h = hash_step(salt ^ 0x243F6A8885A308D3ull, own);
     const uint64_t* __restrict__ R = rows + D.rows_off;
-    for (uint32_t r0 = 0; r0 < kp; r0 += 8) {
-      const uint32_t cnt = (kp - r0) < 8u ? (kp - r0) : 8u;
-      uint32_t s[8], b[8];
+    unsigned long long lk;  // local grouping key (exact key + 1, or the hash)
+    if (D.ebits) {
+      // exact key: own dense number, then one per letter, ebits each
+      const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
+      const uint32_t* __restrict__ dn = dense + D.state_off;
+      uint32_t key = D.dsrc ? ((acc[q >> 3] >> (q & 7)) & 1u) : dn[q];
+      uint32_t shift = D.ebits;
+      for (uint32_t r0 = 0; r0 < kp; r0 += 8) {
+        const uint32_t cnt = (kp - r0) < 8u ? (kp - r0) : 8u;
+        uint32_t s[8], b[8];
 #pragma unroll
-      for (uint32_t t = 0; t < 8; ++t)
-        if (t < cnt) s[t] = reinterpret_cast<const uint32_t*>(R[r0 + t])[q];
+        for (uint32_t t = 0; t < 8; ++t)
+          if (t < cnt) s[t] = reinterpret_cast<const uint32_t*>(R[r0 + t])[q];
 #pragma unroll
-      for (uint32_t t = 0; t < 8; ++t)
-        if (t < cnt) b[t] = block[D.state_off + s[t]];
+        for (uint32_t t = 0; t < 8; ++t)
+          if (t < cnt) b[t] = D.dsrc ? ((acc[s[t] >> 3] >> (s[t] & 7)) & 1u) : dn[s[t]];
 #pragma unroll
-      for (uint32_t t = 0; t < 8; ++t)
-        if (t < cnt) {
-          rec[1 + r0 + t] = b[t];
-          h = hash_step(h, b[t]);
-        }
+        for (uint32_t t = 0; t < 8; ++t)
+          if (t < cnt) {
+            key |= b[t] << shift;
+            shift += D.ebits;
+          }
+      }
+      // Keys are numbers within one instance: the instance joins the local
+      // key and the home position.  Two instances that still meet in a
+      // global slot are caught by k_resolve (least member outside the
+      // instance) and the round is redone with another salt.
+      frag[e] = key + 1u;  // < 2^31 + 1, never 0
+      h[e] = hash_final(hash_step(hash_step(salt ^ 0x13198A2E03707344ull, key), i));
+      lk = ((unsigned long long)i << 32) | frag[e];
+    } else {
+      uint32_t* __restrict__ rec = sig + D.sig_off + (uint64_t)q * (kp + 1);
+      const uint32_t own = block[g];
+      rec[0] = own;
+      uint64_t hh = hash_step(salt ^ 0x243F6A8885A308D3ull, own);
+      for (uint32_t r0 = 0; r0 < kp; r0 += 8) {
+        const uint32_t cnt = (kp - r0) < 8u ? (kp - r0) : 8u;
+        uint32_t s[8], b[8];
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t)
+          if (t < cnt) s[t] = reinterpret_cast<const uint32_t*>(R[r0 + t])[q];
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t)
+          if (t < cnt) b[t] = block[D.state_off + s[t]];
+#pragma unroll
+        for (uint32_t t = 0; t < 8; ++t)
+          if (t < cnt) {
+            rec[1 + r0 + t] = b[t];
+            hh = hash_step(hh, b[t]);
+          }
+      }
+      hh = hash_final(hh);
+      h[e] = hh;
+      frag[e] = (uint32_t)(hh >> 32) | 1u;
+      lk = hh | (1ull << 63);  // hash keys and exact keys (< 2^32) never meet
     }
-    h = hash_final(h);
-    uint32_t p = (uint32_t)h & (kLocalSlots - 1);
+    uint32_t p = (uint32_t)h[e] & (kLocalSlots - 1);
     while (true) {
-      unsigned long long prev = atomicCAS(&lkey[p], 0ull, (unsigned long long)h);
-      if (prev == 0ull || prev == h) break;
+      const unsigned long long prev = atomicCAS(&lkey[p], 0ull, lk);
+      if (prev == 0ull || prev == lk) break;
       p = (p + 1) & (kLocalSlots - 1);
     }
-    lp = p;
+    lp[e] = p;
     atomicMin(&lmin[p], j);
     atomicAdd(&lcnt[p], 1u);
   }
   __syncthreads();
-  if (valid && lmin[lp] == j) {
-    const uint64_t mask = (tbits >= 64) ? ~0ull : ((1ull << tbits) - 1ull);
-    uint64_t p = h >> (64 - tbits);
-    while (true) {
-      unsigned long long prev = atomicCAS(&table[p].key, 0ull, (unsigned long long)h);
-      if (prev == 0ull || prev == h) break;
-      p = (p + 1) & mask;
-    }
-    atomicMin(&table[p].jmin, j);
-    atomicAdd(&table[p].cnt, lcnt[lp]);
-    lslot[lp] = (uint32_t)p;
+  const uint64_t mask = (1ull << tbits) - 1ull;
+#pragma unroll
+  for (int e = 0; e < kSigItems; ++e) {
+    if (valid[e] && lmin[lp[e]] == jj[e])
+      lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], jj[e], lcnt[lp[e]] > 1u);
   }
   __syncthreads();
-  if (valid) slot_of[j] = lslot[lp];
+#pragma unroll
+  for (int e = 0; e < kSigItems; ++e)
+    if (valid[e]) slot_of[jj[e]] = lslot[lp[e]];
 }
 
 // New block id = least member of the state's hash group; exact check of the
 // full signature against that member's.  Algorithmic bytes per active state:
-// 4 (act) [+4 inst_of] + 4 (slot id) + 16 (slot) + 4 (old block) + 4 (new
+// 4 (act) [+4 inst_of] + 4 (slot id) + 8 (slot) + 4 (old block) + 4 (new
 // id) + 1 (keep flag), plus 4 + 8*(kp+1) when the state is not the least
 // member of its group (its record and the least member's).
 template <bool BATCH>
@@ -356,19 +505,20 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
   if (j < m) {
     const uint32_t g = act[j];
     const uint32_t i = BATCH ? inst_of[g] : 0u;
-    const Slot e = table[slot_of[j]];
+    const uint32_t w = (uint32_t)table[slot_of[j]];
+    const uint32_t jmin = w & kSlotIndexMask;
     uint32_t rep = g;
-    if (e.jmin != j) {
+    if (jmin != j) {
       const InstDesc D = desc[i];
-      const uint32_t gc = act[e.jmin];
+      const uint32_t gc = act[jmin];
       rep = gc;
-      const uint32_t w = D.kp + 1;
-      const uint32_t* __restrict__ r1 = sig + D.sig_off + (uint64_t)(g - D.state_off) * w;
-      const uint32_t* __restrict__ r2 = sig + D.sig_off + (uint64_t)(gc - D.state_off) * w;
+      const uint32_t words = D.kp + 1;
       if (gc < D.state_off || gc - D.state_off >= D.n) {
         coll = true;  // the group's least member belongs to another instance
-      } else {
-        for (uint32_t t = 0; t < w; ++t) coll |= (r1[t] != r2[t]);
+      } else if (!D.ebits) {  // exact keys need no check
+        const uint32_t* __restrict__ r1 = sig + D.sig_off + (uint64_t)(g - D.state_off) * words;
+        const uint32_t* __restrict__ r2 = sig + D.sig_off + (uint64_t)(gc - D.state_off) * words;
+        for (uint32_t t = 0; t < words; ++t) coll |= (r1[t] != r2[t]);
       }
     }
     if (rep != block[g]) {
@@ -376,7 +526,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
       changed_inst[i] = 1u;
     }
     nb[j] = rep;
-    keep[j] = e.cnt > 1u ? 1 : 0;
+    keep[j] = (w & kSlotShared) ? 1 : 0;
   }
   const bool any_changed = __any(changed), any_coll = __any(coll);
   if ((threadIdx.x & 63u) == 0) {
@@ -387,8 +537,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
 
 // Apply the new ids and keep the states whose block is still shared and whose
 // instance split this round.  Algorithmic bytes per active state: 4 (act)
-// [+4 inst_of] + 4 (new id) + 1 (keep) + 4 (changed flag, cached) + 4 (block
-// write) + 4 per kept state (next active list).
+// [+4 inst_of] + 4 (new id) + 1 (keep) + 4 (block write) + 4 per kept state
+// (next active list).
 template <bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_compact(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
@@ -420,10 +570,12 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   }
   uint32_t rank[kScanItems];
   const uint32_t total = tile_ballot_scan(f, rank, s_cnt);
-  if (threadIdx.x == 0) {
-    const uint32_t excl = lookback(scan_status, tile, total);
-    s_prefix = excl;
-    if (base + kScanTile >= m) ctrl->m_next = excl + total;
+  if (threadIdx.x < 64) {
+    const uint32_t excl = lookback_wave0(scan_status, tile, total);
+    if (threadIdx.x == 0) {
+      s_prefix = excl;
+      if (base + kScanTile >= m) ctrl->m_next = excl + total;
+    }
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
@@ -472,10 +624,12 @@ __global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict
   }
   uint32_t r[kScanItems];
   const uint32_t total = tile_ballot_scan(f, r, s_cnt);
-  if (threadIdx.x == 0) {
-    const uint32_t excl = lookback(scan_status, tile, total);
-    s_prefix = excl;
-    if (base + kScanTile >= N) rank[N] = excl + total;
+  if (threadIdx.x < 64) {
+    const uint32_t excl = lookback_wave0(scan_status, tile, total);
+    if (threadIdx.x == 0) {
+      s_prefix = excl;
+      if (base + kScanTile >= N) rank[N] = excl + total;
+    }
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
@@ -487,7 +641,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict
 }
 
 // out[q] = rank[block[g]] - rank[state_off]: canonical ids by least member.
-// Algorithmic bytes: 16 per state (block, gathered rank, out write; +4 inst_of).
+// Algorithmic bytes: 12 per state (block, gathered rank, out write; +4 inst_of).
 template <bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_emit(uint32_t N, const uint32_t* __restrict__ inst_of,
                                                  const InstDesc* __restrict__ desc,
@@ -516,6 +670,27 @@ __global__ __launch_bounds__(kBlock) void k_results(uint32_t ninst, const InstDe
   res[i] = r;
 }
 
+// Algorithmic bytes: 12 per state (block, gathered rank, dense write; +4 inst_of).
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_dense(uint32_t N, const uint32_t* __restrict__ inst_of,
+                                                  const InstDesc* __restrict__ desc,
+                                                  const uint32_t* __restrict__ block,
+                                                  const uint32_t* __restrict__ rank,
+                                                  uint32_t* __restrict__ dense) {
+  const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= N) return;
+  const uint32_t i = BATCH ? inst_of[g] : 0u;
+  dense[g] = rank[block[g]] - rank[desc[i].state_off];
+}
+
+__global__ __launch_bounds__(kBlock) void k_block_counts(uint32_t ninst, const InstDesc* __restrict__ desc,
+                                                         const uint32_t* __restrict__ rank,
+                                                         uint32_t* __restrict__ counts) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= ninst) return;
+  counts[i] = rank[desc[i].state_off + desc[i].n] - rank[desc[i].state_off];
+}
+
 inline uint32_t grid_for(uint64_t items, uint64_t per_wg) {
   return (uint32_t)((items + per_wg - 1) / per_wg);
 }
@@ -524,22 +699,30 @@ inline uint32_t grid_for(uint64_t items, uint64_t per_wg) {
 
 // ---------------------------------------------------------------- launchers
 void launch_row_check(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
-                      uint32_t total_wgs, uint32_t* flags, hipStream_t s) {
+                      uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s) {
   if (!total_wgs) return;
-  hipLaunchKernelGGL(k_row_check, dim3(total_wgs), dim3(kBlock), 0, s, jobs, job_wg_off, njobs, flags);
+  hipLaunchKernelGGL(k_row_check, dim3(total_wgs), dim3(kBlock), 0, s, jobs, job_wg_off, njobs, wg_flags);
+  hipLaunchKernelGGL(k_flags_reduce, dim3(njobs), dim3(kBlock), 0, s, job_wg_off, njobs, total_wgs,
+                     wg_flags, flags);
 }
 
 void launch_closure_level(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
-                          uint32_t total_wgs, uint32_t* flags, hipStream_t s) {
+                          uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s) {
   if (!total_wgs) return;
   hipLaunchKernelGGL(k_closure_level, dim3(total_wgs), dim3(kBlock), 0, s, jobs, job_wg_off, njobs,
-                     flags);
+                     wg_flags);
+  hipLaunchKernelGGL(k_flags_reduce, dim3(njobs), dim3(kBlock), 0, s, job_wg_off, njobs, total_wgs,
+                     wg_flags, flags);
 }
 
-void launch_init_minmax(const InstDesc* desc, uint32_t ninst, uint32_t* minF, uint32_t* minN,
-                        hipStream_t s) {
-  if (!ninst) return;
-  hipLaunchKernelGGL(k_init_minmax, dim3(ninst), dim3(kBlock), 0, s, desc, minF, minN);
+void launch_init_minmax(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
+                        uint32_t total_wgs, unsigned long long* wg_part, uint32_t* minF,
+                        uint32_t* minN, hipStream_t s) {
+  if (!ninst || !total_wgs) return;
+  hipLaunchKernelGGL(k_init_minmax_part, dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst,
+                     wg_part);
+  hipLaunchKernelGGL(k_init_minmax_reduce, dim3(ninst), dim3(kBlock), 0, s, job_wg_off, ninst, total_wgs,
+                     wg_part, minF, minN);
 }
 
 void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
@@ -551,7 +734,7 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
 }
 
 void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) {
-  uint32_t grid = grid_for(tsize, kBlock);
+  uint32_t grid = grid_for(tsize, 2 * kBlock);
   if (grid > 65536u) grid = 65536u;
   if (grid == 0) grid = 1;
   hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl);
@@ -559,16 +742,34 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) 
 
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
-                      uint32_t* sig, Slot* table, uint32_t tbits, uint32_t* slot_of,
-                      uint64_t salt, hipStream_t s) {
+                      const uint32_t* dense, uint32_t* sig, Slot* table, uint32_t tbits,
+                      uint32_t* slot_of, uint64_t salt, hipStream_t s) {
   if (!m) return;
-  const uint32_t grid = grid_for(m, kBlock);
+  const uint32_t grid = grid_for(m, kSigTile);
   if (batch)
     hipLaunchKernelGGL(k_signature<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, sig, table, tbits, slot_of, salt);
+                       block, dense, sig, table, tbits, slot_of, salt);
   else
     hipLaunchKernelGGL(k_signature<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, sig, table, tbits, slot_of, salt);
+                       block, dense, sig, table, tbits, slot_of, salt);
+}
+
+void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
+                  const uint32_t* block, const uint32_t* rank, uint32_t* dense, hipStream_t s) {
+  if (!N) return;
+  if (batch)
+    hipLaunchKernelGGL(k_dense<true>, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, N, inst_of, desc,
+                       block, rank, dense);
+  else
+    hipLaunchKernelGGL(k_dense<false>, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, N, inst_of, desc,
+                       block, rank, dense);
+}
+
+void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
+                         uint32_t* counts, hipStream_t s) {
+  if (!ninst) return;
+  hipLaunchKernelGGL(k_block_counts, dim3(grid_for(ninst, kBlock)), dim3(kBlock), 0, s, ninst, desc, rank,
+                     counts);
 }
 
 void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,

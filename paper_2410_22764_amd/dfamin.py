@@ -79,6 +79,13 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2410_22764_amd.build.build()")
+    # PyTorch bundles its own HIP runtime under the same soname.  Loading it
+    # first makes libdfamin bind to that copy, so the process holds a single
+    # HIP runtime whether or not the caller uses torch tensors afterwards.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     vp, i32, u32, u64, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
