@@ -12,6 +12,8 @@
 //   5. canonical numbering by least member and emission.
 #include "engine.h"
 
+#include "closure.h"
+
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
@@ -20,12 +22,6 @@
 namespace dfamin {
 
 namespace {
-
-inline uint32_t floor_log2_u32(uint32_t n) {
-  uint32_t L = 0;
-  while (n >> 1) { n >>= 1; ++L; }
-  return L;
-}
 
 inline uint32_t ceil_log2_u64(uint64_t x) {
   uint32_t b = 0;
@@ -203,10 +199,11 @@ int Engine::upload_layout(hipStream_t s) {
     desc_[i].rows_off = (uint32_t)rows_.size();
     desc_[i].kp = (uint32_t)inst_rows_[i].size();
     rows_.insert(rows_.end(), inst_rows_[i].begin(), inst_rows_[i].end());
-    desc_[i].sig_off = sig_words;
+    desc_[i].sig = sig_words;  // word offset for now, made absolute below
     sig_words += (uint64_t)desc_[i].n * (desc_[i].kp + 1);
   }
   TRY(ensure(d_sig_, sig_words * 4));
+  for (size_t i = 0; i < I; ++i) desc_[i].sig = reinterpret_cast<uint64_t>(d_sig_.p) + 4 * desc_[i].sig;
   TRY(ensure(d_desc_, I * sizeof(InstDesc)));
   TRY(ensure(d_rows_, std::max<size_t>(rows_.size(), 1) * 8));
   HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
@@ -215,137 +212,71 @@ int Engine::upload_layout(hipStream_t s) {
   return DFAMIN_OK;
 }
 
-// Partial transitive closure (Algorithm 5) for the listed instances: levels
-// 1..L of every non-identity letter by pointer jumping, one launch per
-// level for all of them; then the row list keeps, per letter, the levels up
-// to (excluding) the first one that equals its predecessor or is the
-// identity -- all later levels would equal it.
+// Partial transitive closure (Algorithm 5) for the listed instances; the
+// level storage is appended to this call's closure buffer.
 int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts,
                           hipStream_t s) {
-  struct LJob { uint32_t inst, letter, level; };
-  std::vector<uint32_t> L(which.size());
+  std::vector<ClosureSpec> specs(which.size());
   uint64_t words = 0;
-  uint32_t Lmax = 0;
   for (size_t w = 0; w < which.size(); ++w) {
     const uint32_t i = which[w];
     uint32_t l = floor_log2_u32(in_[i].n);
     if (opts.max_levels && opts.max_levels < l) l = opts.max_levels;
-    L[w] = l;
-    Lmax = std::max(Lmax, l);
+    specs[w].n = in_[i].n;
+    specs[w].delta = in_[i].delta;
+    specs[w].letters = nonid_[i];
+    specs[w].L = l;
     words += (uint64_t)nonid_[i].size() * l * in_[i].n;
   }
-  // storage: appended after what earlier closures of this call use
   const uint64_t base = closure_used_;
-  if (words) {
-    // grow keeping old contents is not needed: earlier closures belong to
-    // instances that are already converged or are rebuilt here.
-    if (d_closure_.cap < (base + words) * 4) {
-      if (base != 0) {
-        // keep rows of earlier instances valid: copy into a new buffer
-        DevBuf nb;
-        TRY(ensure(nb, (base + words) * 4));
-        HIP(hipMemcpyAsync(nb.p, d_closure_.p, base * 4, hipMemcpyDeviceToDevice, s));
-        HIP(hipStreamSynchronize(s));
-        const uint64_t old = reinterpret_cast<uint64_t>(d_closure_.p);
-        const uint64_t nw = reinterpret_cast<uint64_t>(nb.p);
-        for (auto& rl : inst_rows_)
-          for (auto& r : rl)
-            if (r >= old && r < old + base * 4) r = r - old + nw;
-        (void)hipFree(d_closure_.p);
-        ctx_->used -= d_closure_.cap;
-        d_closure_ = nb;
-      } else {
-        TRY(ensure(d_closure_, words * 4));
-      }
+  if (words && d_closure_.cap < (base + words) * 4) {
+    if (base != 0) {
+      // keep the rows of earlier closures of this call valid
+      DevBuf nb;
+      TRY(ensure(nb, (base + words) * 4));
+      HIP(hipMemcpyAsync(nb.p, d_closure_.p, base * 4, hipMemcpyDeviceToDevice, s));
+      HIP(hipStreamSynchronize(s));
+      const uint64_t old = reinterpret_cast<uint64_t>(d_closure_.p);
+      const uint64_t nw = reinterpret_cast<uint64_t>(nb.p);
+      for (auto& rl : inst_rows_)
+        for (auto& r : rl)
+          if (r >= old && r < old + base * 4) r = r - old + nw;
+      (void)hipFree(d_closure_.p);
+      ctx_->used -= d_closure_.cap;
+      d_closure_ = nb;
+    } else {
+      TRY(ensure(d_closure_, words * 4));
     }
   }
-  const uint64_t cbase = reinterpret_cast<uint64_t>(d_closure_.p);
-  // level l of letter index x of instance w lives at row_ptr(w, x, l)
-  std::vector<uint64_t> first_row(which.size());
-  {
-    uint64_t off = base;
-    for (size_t w = 0; w < which.size(); ++w) {
-      first_row[w] = off;
-      off += (uint64_t)nonid_[which[w]].size() * L[w] * in_[which[w]].n;
-    }
+  uint64_t off = base;
+  for (auto& sp : specs) {
+    sp.storage = d_closure_.as<uint32_t>() + off;
+    off += (uint64_t)sp.letters.size() * sp.L * sp.n;
   }
-  auto row_ptr = [&](size_t w, size_t x, uint32_t l) -> uint64_t {
-    const uint32_t i = which[w];
-    if (l == 0) return reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * nonid_[i][x] * in_[i].n;
-    return cbase + 4ull * (first_row[w] + ((uint64_t)x * L[w] + (l - 1)) * in_[i].n);
+  ClosureScratch scratch;
+  DevBuf* bufs[4] = {&d_jobs_, &d_joboff_, &d_flags_, &d_wgflags_};
+  scratch.ensure = [&](int b, size_t bytes) -> void* {
+    return ensure(*bufs[b], bytes) == DFAMIN_OK ? bufs[b]->p : nullptr;
   };
-  // jobs for all levels, grouped by level
-  std::vector<RowJob> jobs;
-  std::vector<uint32_t> joboff;
-  std::vector<LJob> meta;
-  std::vector<uint32_t> lvl_job_begin(Lmax + 2, 0), lvl_wg_total(Lmax + 2, 0);
-  for (uint32_t l = 1; l <= Lmax; ++l) {
-    lvl_job_begin[l] = (uint32_t)jobs.size();
-    uint32_t wgs = 0;
-    for (size_t w = 0; w < which.size(); ++w) {
-      if (L[w] < l) continue;
-      const uint32_t i = which[w];
-      for (size_t x = 0; x < nonid_[i].size(); ++x) {
-        RowJob J;
-        J.src = row_ptr(w, x, l - 1);
-        J.dst = row_ptr(w, x, l);
-        J.n = in_[i].n;
-        J.flag_idx = (uint32_t)jobs.size();
-        joboff.push_back(wgs);
-        wgs += (J.n + kRowTile - 1) / kRowTile;
-        jobs.push_back(J);
-        meta.push_back({(uint32_t)w, (uint32_t)x, l});
-      }
-    }
-    lvl_wg_total[l] = wgs;
+  scratch.host_flags = [&](size_t bytes) -> void* {
+    return ensure_host(h_flags_, bytes) == DFAMIN_OK ? h_flags_.p : nullptr;
+  };
+  std::vector<std::vector<uint64_t>> rows;
+  if (ctx_->prof.enabled()) {
+    double bytes = 0;
+    for (auto& sp : specs) bytes += 12.0 * sp.letters.size() * sp.L * sp.n;
+    ctx_->prof.begin(s, "closure", bytes);
   }
-  lvl_job_begin[Lmax + 1] = (uint32_t)jobs.size();
-  if (!jobs.empty()) {
-    uint32_t max_wgs = 0;
-    for (uint32_t l = 1; l <= Lmax; ++l) max_wgs = std::max(max_wgs, lvl_wg_total[l]);
-    TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
-    TRY(ensure(d_joboff_, joboff.size() * 4));
-    TRY(ensure(d_flags_, jobs.size() * 4));
-    TRY(ensure(d_wgflags_, (size_t)max_wgs * 4));
-    HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
-    HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
-    HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
-    for (uint32_t l = 1; l <= Lmax; ++l) {
-      const uint32_t b = lvl_job_begin[l], e = lvl_job_begin[l + 1];
-      if (b == e) continue;
-      double bytes = 0;
-      for (uint32_t j = b; j < e; ++j) bytes += 12.0 * jobs[j].n;
-      ctx_->prof.begin(s, "closure_level", bytes);
-      launch_closure_level(d_jobs_.as<RowJob>() + b, d_joboff_.as<uint32_t>() + b, e - b,
-                           lvl_wg_total[l], d_wgflags_.as<uint32_t>(), d_flags_.as<uint32_t>() + b, s);
-      ctx_->prof.end(s);
-      HIP(hipGetLastError());
-    }
-    TRY(ensure_host(h_flags_, jobs.size() * 4));
-    HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
-    HIP(hipStreamSynchronize(s));
+  const int rc = build_closure_levels(specs, scratch, s, rows);
+  if (ctx_->prof.enabled()) {
+    ctx_->prof.end(s);
     ctx_->prof.collect();
   }
-  const uint32_t* flags = h_flags_.as<uint32_t>();
-  // per (w, x): highest level kept
+  if (rc != DFAMIN_OK) return rc;
   for (size_t w = 0; w < which.size(); ++w) {
-    const uint32_t i = which[w];
-    inst_rows_[i].clear();
-    for (size_t x = 0; x < nonid_[i].size(); ++x) {
-      inst_rows_[i].push_back(row_ptr(w, x, 0));
-      for (uint32_t l = 1; l <= L[w]; ++l) {
-        // find job of (w, x, l)
-        uint32_t jb = lvl_job_begin[l], je = lvl_job_begin[l + 1], found = UINT32_MAX;
-        for (uint32_t j = jb; j < je; ++j)
-          if (meta[j].inst == w && meta[j].letter == x) { found = j; break; }
-        if (found == UINT32_MAX) break;
-        const uint32_t f = flags[found];
-        if (!(f & kFlagDiffers) || !(f & kFlagNonId)) break;
-        inst_rows_[i].push_back(row_ptr(w, x, l));
-      }
-    }
-    levels_[i] = L[w];
-    has_closure_[i] = 1;
+    inst_rows_[which[w]] = rows[w];
+    levels_[which[w]] = specs[w].L;
+    has_closure_[which[w]] = 1;
   }
   closure_used_ = base + words;
   return DFAMIN_OK;
@@ -595,28 +526,29 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     prof.begin(s, "signature", md * (4 + inst_b + 4 + 8 * kpbar + 4 * (kpbar + 1) + 4 + 8));
     launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                      d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.as<uint32_t>(),
-                     d_sig_.as<uint32_t>(), d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt,
-                     s);
+                     d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt,
+                     d_ctrl_.as<Ctrl>(), s);
     prof.end(s);
     prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
     launch_resolve(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-                   d_sig_.as<uint32_t>(), d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
+                   d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
                    d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(), d_keep_.as<uint8_t>(),
                    d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
                    d_status_.as<unsigned long long>(), ntiles, s);
     prof.end(s);
     prof.begin(s, "compact", md * (4 + inst_b + 4 + 1 + 4));
     launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
-                   d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), d_block_.as<uint32_t>(), nxt,
-                   d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), s);
+                   d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(),
+                   nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), s);
     prof.end(s);
-    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(),
+    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
                      d_ctrl_.as<Ctrl>(), s);
     HIP(hipGetLastError());
     HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP(hipStreamSynchronize(s));
     prof.collect();
     const Ctrl c = *h_ctrl_.as<Ctrl>();
+    if (c.fault) return DFAMIN_E_INTERNAL;
     if (prof.enabled() && std::getenv("DFAMIN_TRACE"))
       std::fprintf(stderr, "[dfamin] round %llu: m=%llu table=2^%u next=%u changed=%u collision=%u\n",
                    (unsigned long long)rounds + 1, (unsigned long long)m, tbits, c.m_next, c.any_changed,
@@ -653,8 +585,10 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
                  d_refine_.as<uint32_t>(), d_results_.as<ResultDev>(), s);
   HIP(hipGetLastError());
   HIP(hipMemcpyAsync(h_results_.p, d_results_.p, I * sizeof(ResultDev), hipMemcpyDeviceToHost, s));
+  HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
   HIP(hipStreamSynchronize(s));
   prof.collect();
+  if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
   const ResultDev* r = h_results_.as<ResultDev>();
   for (size_t i = 0; i < I; ++i) {
     res[i].num_blocks = r[i].num_blocks;

@@ -42,7 +42,7 @@ struct InstDesc {
   uint32_t n;           // states
   uint32_t kp;          // signature letters in use (rows)
   uint32_t rows_off;    // index of the first row pointer in rows[]
-  uint64_t sig_off;     // word offset of the signature records: n * (kp + 1) words
+  uint64_t sig;         // device address of the signature records: n * (kp + 1) words
   uint64_t accept;      // device address of the accept bitmap
   uint64_t out;         // device address of the output (n uint32)
   uint32_t q0;
@@ -62,15 +62,23 @@ typedef unsigned long long Slot;
 constexpr uint32_t kSlotShared = 0x80000000u;
 constexpr uint32_t kSlotIndexMask = 0x7fffffffu;
 
-// Control block shared by the round kernels and read by the host.
+// Control block shared by the round kernels and read by the host.  Words
+// that workgroups update concurrently are only ever touched with device
+// atomics; the tile counter lives on its own 128-byte line.
 struct Ctrl {
   uint32_t any_changed;   // some block split this round
   uint32_t collision;     // two different signatures shared a hash this round
   uint32_t m_next;        // active states for the next round
+  uint32_t fault;         // a bounded device wait or probe ran out (never expected)
+  uint32_t pad0[28];
   uint32_t tile_counter;  // dynamic tile ids for the look-back scans
-  uint32_t bad;           // a delta entry >= n was seen
-  uint32_t pad[3];
+  uint32_t pad1[31];
 };
+static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
+
+// Bounds on device-side waiting and probing: hitting one sets Ctrl::fault,
+// the kernel finishes, and the host reports DFAMIN_E_INTERNAL.
+constexpr uint32_t kMaxSpin = 1u << 22;
 
 // One row of n entries handled by a row job (validation, closure level).
 struct RowJob {
@@ -113,8 +121,8 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
 void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s);
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
-                      const uint32_t* dense, uint32_t* sig, Slot* table, uint32_t tbits,
-                      uint32_t* slot_of, uint64_t salt, hipStream_t s);
+                      const uint32_t* dense, Slot* table, uint32_t tbits, uint32_t* slot_of,
+                      uint64_t salt, Ctrl* ctrl, hipStream_t s);
 // dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
 // instance's blocks in order of least member.
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
@@ -123,16 +131,40 @@ void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDes
 void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
                          uint32_t* counts, hipStream_t s);
 void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
-                    const InstDesc* desc, const uint32_t* sig, const Slot* table,
+                    const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
                     uint32_t ntiles, hipStream_t s);
+// dead (nullable): instances whose states leave the active list (cancelled).
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
-                    uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
+                    const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
                     unsigned long long* scan_status, hipStream_t s);
-void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt,
+// last (nullable) receives this round's per-instance changed flags.
+void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
                       const Ctrl* ctrl, hipStream_t s);
+// Instances joining a running set: like launch_init_block, with instance
+// ids slot[j] for job j and their states appended to act at act_off[j].
+void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                      uint32_t njobs, uint32_t total_wgs, const uint32_t* act_off,
+                      const uint32_t* minF, const uint32_t* minN, uint32_t* inst_of,
+                      uint32_t* block, uint32_t* act, hipStream_t s);
+void launch_init_minmax_slots(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                              uint32_t njobs, uint32_t total_wgs, unsigned long long* wg_part,
+                              uint32_t* minF, uint32_t* minN, hipStream_t s);
+// Per-instance (segmented) canonical numbering for the instances slot[j]:
+// rank[g] = representatives before g within its instance; totals[j] = the
+// instance's block count; then out[q] = rank[block[g]] and per-instance
+// results.  job_tile_off: scan tiles (kScanTile states) per job, prefix.
+void launch_scan_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_tile_off,
+                      uint32_t njobs, uint32_t total_tiles, const uint32_t* block, uint32_t* rank,
+                      uint32_t* totals, Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s);
+void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                      uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
+                      hipStream_t s);
+void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,
+                         const uint32_t* totals, const uint32_t* refine_cnt, ResultDev* res,
+                         hipStream_t s);
 void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s);
 void launch_scan_reps(const uint32_t* block, uint32_t N, uint32_t* rank, Ctrl* ctrl,
                       unsigned long long* scan_status, hipStream_t s);

@@ -65,25 +65,31 @@ __device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
 // prefix and returns the exclusive one (valid in wave 0).  Tiles are numbered
 // in the order workgroups obtained them, so every predecessor is running or
 // done and the wait ends.
-__device__ uint32_t lookback_wave0(unsigned long long* status, uint32_t tile, uint32_t total) {
+__device__ uint32_t lookback_wave0(unsigned long long* status, uint32_t tile, uint32_t total,
+                                   Ctrl* ctrl, uint32_t seg_start = 0) {
   const uint32_t lane = threadIdx.x & 63u;
-  if (tile == 0) {
-    if (lane == 0) store_status(&status[0], kFlagPrefix | total);
+  if (tile == seg_start) {
+    if (lane == 0) store_status(&status[tile], kFlagPrefix | total);
     return 0;
   }
   if (lane == 0) store_status(&status[tile], kFlagAgg | total);
   uint32_t excl = 0;
   int base = (int)tile - 1;
+  uint32_t spins = 0;
   while (true) {
     const int t = base - (int)lane;
-    // positions before tile 0 act as an inclusive prefix of 0
-    const unsigned long long v = (t >= 0) ? load_status(&status[t]) : kFlagPrefix;
+    // positions before the segment's first tile act as an inclusive prefix of 0
+    const unsigned long long v = (t >= (int)seg_start) ? load_status(&status[t]) : kFlagPrefix;
     const uint32_t flag = (uint32_t)(v >> 62);
     const unsigned long long not_ready = __ballot(flag == 0);
     const unsigned long long is_prefix = __ballot(flag == 2);
     const int first_p = is_prefix ? (int)__builtin_ctzll(is_prefix) : 63;
     const unsigned long long need = (first_p >= 63) ? ~0ull : ((2ull << first_p) - 1ull);
     if (not_ready & need) {
+      if (++spins > kMaxSpin) {  // a predecessor never published: give up, flag it
+        if (lane == 0) atomicOr(&ctrl->fault, 1u);
+        break;
+      }
       __builtin_amdgcn_s_sleep(1);
       continue;
     }
@@ -324,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_init_block(const InstDesc* __restric
 __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table, uint64_t tsize,
                                                         Ctrl* __restrict__ ctrl) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    ctrl->any_changed = 0;
-    ctrl->collision = 0;
+    atomicExch(&ctrl->any_changed, 0u);
+    atomicExch(&ctrl->collision, 0u);
   }
   const uint64_t stride = (uint64_t)gridDim.x * kBlock * 2;
   for (uint64_t s = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2; s < tsize; s += stride) {
@@ -340,31 +346,33 @@ __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table
 // one, and slot words change monotonically (claimed once, index only
 // lowered, shared bit only set).
 __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint64_t mask, uint64_t h,
-                                                 uint32_t frag, uint32_t j, bool shared) {
+                                                 uint32_t frag, uint32_t j, bool shared,
+                                                 Ctrl* __restrict__ ctrl) {
   uint64_t p = h & mask;
   const unsigned long long mine =
       ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)j;
-  while (true) {
+  for (uint64_t probes = 0; probes <= mask; ++probes) {
     unsigned long long cur = table[p];
-    if (cur == 0ull) {
-      const unsigned long long prev = atomicCAS(&table[p], 0ull, mine);
-      if (prev == 0ull) return (uint32_t)p;
-      cur = prev;
-    }
-    if ((uint32_t)(cur >> 32) == frag) {
-      while (true) {
-        const uint32_t lo = (uint32_t)cur;
-        const uint32_t want_lo = min(lo & kSlotIndexMask, j) | kSlotShared;
-        if (want_lo == lo) break;
-        const unsigned long long want = (cur & 0xffffffff00000000ull) | want_lo;
-        const unsigned long long prev = atomicCAS(&table[p], cur, want);
-        if (prev == cur) break;
+    while (true) {
+      if (cur == 0ull) {
+        const unsigned long long prev = atomicCAS(&table[p], 0ull, mine);
+        if (prev == 0ull) return (uint32_t)p;
         cur = prev;
+        continue;
       }
-      return (uint32_t)p;
+      if ((uint32_t)(cur >> 32) != frag) break;  // another key: next slot
+      const uint32_t lo = (uint32_t)cur;
+      const uint32_t want_lo = min(lo & kSlotIndexMask, j) | kSlotShared;
+      if (want_lo == lo) return (uint32_t)p;
+      const unsigned long long want = (cur & 0xffffffff00000000ull) | want_lo;
+      const unsigned long long prev = atomicCAS(&table[p], cur, want);
+      if (prev == cur) return (uint32_t)p;
+      cur = prev;  // re-examined from the top: empty, other key or same key
     }
     p = (p + 1) & mask;
   }
+  atomicOr(&ctrl->fault, 1u);  // a table at most half full has a free slot
+  return (uint32_t)(h & mask);
 }
 
 // Signature gather + grouping.  Hash mode: algorithmic bytes per active
@@ -378,8 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
     const uint32_t* __restrict__ block, const uint32_t* __restrict__ dense,
-    uint32_t* __restrict__ sig, Slot* __restrict__ table, uint32_t tbits,
-    uint32_t* __restrict__ slot_of, uint64_t salt) {
+    Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
+    Ctrl* __restrict__ ctrl) {
   __shared__ unsigned long long lkey[kLocalSlots];
   __shared__ uint32_t lmin[kLocalSlots], lcnt[kLocalSlots], lslot[kLocalSlots];
   for (uint32_t s = threadIdx.x; s < kLocalSlots; s += kBlock) {
@@ -437,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
       h[e] = hash_final(hash_step(hash_step(salt ^ 0x13198A2E03707344ull, key), i));
       lk = ((unsigned long long)i << 32) | frag[e];
     } else {
-      uint32_t* __restrict__ rec = sig + D.sig_off + (uint64_t)q * (kp + 1);
+      uint32_t* __restrict__ rec = reinterpret_cast<uint32_t*>(D.sig) + (uint64_t)q * (kp + 1);
       const uint32_t own = block[g];
       rec[0] = own;
       uint64_t hh = hash_step(salt ^ 0x243F6A8885A308D3ull, own);
@@ -477,7 +485,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
 #pragma unroll
   for (int e = 0; e < kSigItems; ++e) {
     if (valid[e] && lmin[lp[e]] == jj[e])
-      lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], jj[e], lcnt[lp[e]] > 1u);
+      lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], jj[e], lcnt[lp[e]] > 1u, ctrl);
   }
   __syncthreads();
 #pragma unroll
@@ -493,14 +501,14 @@ __global__ __launch_bounds__(kBlock) void k_signature(
 template <bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_resolve(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
-    const InstDesc* __restrict__ desc, const uint32_t* __restrict__ sig,
+    const InstDesc* __restrict__ desc,
     const Slot* __restrict__ table, const uint32_t* __restrict__ slot_of,
     const uint32_t* __restrict__ block, uint32_t* __restrict__ nb, uint8_t* __restrict__ keep,
     uint32_t* __restrict__ changed_inst, Ctrl* __restrict__ ctrl,
     unsigned long long* __restrict__ scan_status, uint32_t ntiles) {
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j < ntiles) scan_status[j] = 0ull;
-  if (j == 0) ctrl->tile_counter = 0u;
+  if (j < ntiles) store_status(&scan_status[j], 0ull);
+  if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
   bool changed = false, coll = false;
   if (j < m) {
     const uint32_t g = act[j];
@@ -516,8 +524,9 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
       if (gc < D.state_off || gc - D.state_off >= D.n) {
         coll = true;  // the group's least member belongs to another instance
       } else if (!D.ebits) {  // exact keys need no check
-        const uint32_t* __restrict__ r1 = sig + D.sig_off + (uint64_t)(g - D.state_off) * words;
-        const uint32_t* __restrict__ r2 = sig + D.sig_off + (uint64_t)(gc - D.state_off) * words;
+        const uint32_t* __restrict__ sg = reinterpret_cast<const uint32_t*>(D.sig);
+        const uint32_t* __restrict__ r1 = sg + (uint64_t)(g - D.state_off) * words;
+        const uint32_t* __restrict__ r2 = sg + (uint64_t)(gc - D.state_off) * words;
         for (uint32_t t = 0; t < words; ++t) coll |= (r1[t] != r2[t]);
       }
     }
@@ -530,8 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
   }
   const bool any_changed = __any(changed), any_coll = __any(coll);
   if ((threadIdx.x & 63u) == 0) {
-    if (any_changed) ctrl->any_changed = 1u;
-    if (any_coll) ctrl->collision = 1u;
+    if (any_changed) atomicOr(&ctrl->any_changed, 1u);
+    if (any_coll) atomicOr(&ctrl->collision, 1u);
   }
 }
 
@@ -543,15 +552,21 @@ template <bool BATCH>
 __global__ __launch_bounds__(kBlock) void k_compact(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const uint32_t* __restrict__ nb, const uint8_t* __restrict__ keep,
-    const uint32_t* __restrict__ changed_inst, uint32_t* __restrict__ block,
-    uint32_t* __restrict__ act_next, Ctrl* __restrict__ ctrl,
+    const uint32_t* __restrict__ changed_inst, const uint32_t* __restrict__ dead,
+    uint32_t* __restrict__ block, uint32_t* __restrict__ act_next, Ctrl* __restrict__ ctrl,
     unsigned long long* __restrict__ scan_status) {
-  if (ctrl->collision) return;  // the round is redone with another salt
-  __shared__ uint32_t s_tile, s_prefix;
+  // On a hash collision the round is redone with another salt: nothing is
+  // written, but every tile still takes part in the look-back so that no
+  // workgroup can wait for one that left early.
+  __shared__ uint32_t s_tile, s_prefix, s_coll;
   __shared__ uint32_t s_cnt[kScanItems * 4];
-  if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tile_counter, 1u);
+  if (threadIdx.x == 0) {
+    s_tile = atomicAdd(&ctrl->tile_counter, 1u);
+    s_coll = __hip_atomic_load(&ctrl->collision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
   __syncthreads();
   const uint32_t tile = s_tile;
+  const bool coll = s_coll != 0;
   const uint32_t base = tile * kScanTile;
   bool f[kScanItems];
   uint32_t gs[kScanItems];
@@ -560,21 +575,21 @@ __global__ __launch_bounds__(kBlock) void k_compact(
     const uint32_t j = base + e * kBlock + threadIdx.x;
     f[e] = false;
     gs[e] = 0;
-    if (j < m) {
+    if (j < m && !coll) {
       const uint32_t g = act[j];
       gs[e] = g;
       block[g] = nb[j];
       const uint32_t i = BATCH ? inst_of[g] : 0u;
-      f[e] = keep[j] && changed_inst[i];
+      f[e] = keep[j] && changed_inst[i] && !(dead && dead[i]);
     }
   }
   uint32_t rank[kScanItems];
   const uint32_t total = tile_ballot_scan(f, rank, s_cnt);
   if (threadIdx.x < 64) {
-    const uint32_t excl = lookback_wave0(scan_status, tile, total);
+    const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl);
     if (threadIdx.x == 0) {
       s_prefix = excl;
-      if (base + kScanTile >= m) ctrl->m_next = excl + total;
+      if (base + kScanTile >= m && tile < gridDim.x) atomicExch(&ctrl->m_next, excl + total);
     }
   }
   __syncthreads();
@@ -587,11 +602,14 @@ __global__ __launch_bounds__(kBlock) void k_compact(
 __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
                                                       uint32_t* __restrict__ changed_inst,
                                                       uint32_t* __restrict__ refine_cnt,
+                                                      uint32_t* __restrict__ last,
                                                       const Ctrl* __restrict__ ctrl) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= ninst) return;
+  const uint32_t coll = __hip_atomic_load(&ctrl->collision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (last) last[i] = coll ? 0u : changed_inst[i];
   if (changed_inst[i]) {
-    if (!ctrl->collision) refine_cnt[i] += 1u;
+    if (!coll) refine_cnt[i] += 1u;
     changed_inst[i] = 0u;
   }
 }
@@ -600,8 +618,8 @@ __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
 __global__ __launch_bounds__(kBlock) void k_prep_scan(unsigned long long* __restrict__ scan_status,
                                                       uint32_t ntiles, Ctrl* __restrict__ ctrl) {
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-  if (j < ntiles) scan_status[j] = 0ull;
-  if (j == 0) ctrl->tile_counter = 0u;
+  if (j < ntiles) store_status(&scan_status[j], 0ull);
+  if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
 }
 
 // rank[g] = number of block representatives (block[x] == x) with x < g;
@@ -625,7 +643,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict
   uint32_t r[kScanItems];
   const uint32_t total = tile_ballot_scan(f, r, s_cnt);
   if (threadIdx.x < 64) {
-    const uint32_t excl = lookback_wave0(scan_status, tile, total);
+    const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl);
     if (threadIdx.x == 0) {
       s_prefix = excl;
       if (base + kScanTile >= N) rank[N] = excl + total;
@@ -691,6 +709,189 @@ __global__ __launch_bounds__(kBlock) void k_block_counts(uint32_t ninst, const I
   counts[i] = rank[desc[i].state_off + desc[i].n] - rank[desc[i].state_off];
 }
 
+// ------------------------------------------------------- joining instances
+__global__ __launch_bounds__(kBlock) void k_init_minmax_slots(const InstDesc* __restrict__ desc,
+                                                              const uint32_t* __restrict__ slot,
+                                                              const uint32_t* __restrict__ job_wg_off,
+                                                              uint32_t njobs,
+                                                              unsigned long long* __restrict__ part) {
+  __shared__ uint32_t s_job, sF, sN;
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const InstDesc D = desc[slot[j]];
+  const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
+  if (threadIdx.x == 0) { sF = 0xffffffffu; sN = 0xffffffffu; }
+  __syncthreads();
+  const uint32_t b = (blockIdx.x - job_wg_off[j]) * (kRowTile / 8) + threadIdx.x;
+  const uint32_t nbytes = (D.n + 7) >> 3;
+  uint32_t mf = 0xffffffffu, mn = 0xffffffffu;
+  if (threadIdx.x < kRowTile / 8 && b < nbytes) {
+    const uint32_t valid = D.n - b * 8;
+    const uint32_t vmask = valid >= 8 ? 0xffu : ((1u << valid) - 1u);
+    const uint32_t v = acc[b];
+    const uint32_t f = v & vmask, nf = ~v & vmask;
+    if (f) mf = b * 8 + __builtin_ctz(f);
+    if (nf) mn = b * 8 + __builtin_ctz(nf);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mf = min(mf, (uint32_t)__shfl_xor(mf, off, 64));
+    mn = min(mn, (uint32_t)__shfl_xor(mn, off, 64));
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    atomicMin(&sF, mf);
+    atomicMin(&sN, mn);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ((unsigned long long)sF << 32) | sN;
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_minmax_slots_reduce(
+    const uint32_t* __restrict__ slot, const uint32_t* __restrict__ job_wg_off, uint32_t njobs,
+    uint32_t total_wgs, const unsigned long long* __restrict__ part, uint32_t* __restrict__ minF,
+    uint32_t* __restrict__ minN) {
+  __shared__ uint32_t sF, sN;
+  const uint32_t j = blockIdx.x;
+  const uint32_t b = job_wg_off[j], e = (j + 1 < njobs) ? job_wg_off[j + 1] : total_wgs;
+  if (threadIdx.x == 0) { sF = 0xffffffffu; sN = 0xffffffffu; }
+  __syncthreads();
+  uint32_t mf = 0xffffffffu, mn = 0xffffffffu;
+  for (uint32_t w = b + threadIdx.x; w < e; w += kBlock) {
+    const unsigned long long v = part[w];
+    mf = min(mf, (uint32_t)(v >> 32));
+    mn = min(mn, (uint32_t)v);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    mf = min(mf, (uint32_t)__shfl_xor(mf, off, 64));
+    mn = min(mn, (uint32_t)__shfl_xor(mn, off, 64));
+  }
+  if ((threadIdx.x & 63u) == 0) {
+    atomicMin(&sF, mf);
+    atomicMin(&sN, mn);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) { minF[slot[j]] = sF; minN[slot[j]] = sN; }
+}
+
+// Initial partition of joining instances; their states are appended to act.
+__global__ __launch_bounds__(kBlock) void k_init_join(const InstDesc* __restrict__ desc,
+                                                      const uint32_t* __restrict__ slot,
+                                                      const uint32_t* __restrict__ job_wg_off,
+                                                      uint32_t njobs,
+                                                      const uint32_t* __restrict__ act_off,
+                                                      const uint32_t* __restrict__ minF,
+                                                      const uint32_t* __restrict__ minN,
+                                                      uint32_t* __restrict__ inst_of,
+                                                      uint32_t* __restrict__ block,
+                                                      uint32_t* __restrict__ act) {
+  __shared__ uint32_t s_job;
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const uint32_t i = slot[j];
+  const InstDesc D = desc[i];
+  const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
+  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+  const uint32_t f = D.state_off + minF[i], nf = D.state_off + minN[i];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < D.n) {
+      const uint32_t g = D.state_off + q;
+      const bool a = (acc[q >> 3] >> (q & 7)) & 1u;
+      block[g] = a ? f : nf;
+      inst_of[g] = i;
+      act[act_off[j] + q] = g;
+    }
+  }
+}
+
+// --------------------------------------------------- per-instance numbering
+// Segmented version of k_scan_reps over the instances slot[j]: every job
+// starts its own prefix at 0.  Algorithmic bytes: 8 per state.
+__global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict__ desc,
+                                                      const uint32_t* __restrict__ slot,
+                                                      const uint32_t* __restrict__ job_tile_off,
+                                                      uint32_t njobs,
+                                                      const uint32_t* __restrict__ block,
+                                                      uint32_t* __restrict__ rank,
+                                                      uint32_t* __restrict__ totals,
+                                                      Ctrl* __restrict__ ctrl,
+                                                      unsigned long long* __restrict__ scan_status) {
+  __shared__ uint32_t s_tile, s_job, s_prefix;
+  __shared__ uint32_t s_cnt[kScanItems * 4];
+  if (threadIdx.x == 0) {
+    const uint32_t t = atomicAdd(&ctrl->tile_counter, 1u);
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (job_tile_off[mid] <= t) lo = mid; else hi = mid;
+    }
+    s_tile = t;
+    s_job = lo;
+  }
+  __syncthreads();
+  const uint32_t tile = s_tile, j = s_job;
+  const InstDesc D = desc[slot[j]];
+  const uint32_t base = (tile - job_tile_off[j]) * kScanTile;
+  bool f[kScanItems];
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    f[e] = (q < D.n) && (block[D.state_off + q] == D.state_off + q);
+  }
+  uint32_t r[kScanItems];
+  const uint32_t total = tile_ballot_scan(f, r, s_cnt);
+  if (threadIdx.x < 64) {
+    const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl, job_tile_off[j]);
+    if (threadIdx.x == 0) {
+      s_prefix = excl;
+      if (base + kScanTile >= D.n) totals[j] = excl + total;
+    }
+  }
+  __syncthreads();
+  const uint32_t pre = s_prefix;
+#pragma unroll
+  for (int e = 0; e < kScanItems; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < D.n) rank[D.state_off + q] = pre + r[e];
+  }
+}
+
+// out[q] = rank[block[g]] (ranks are already relative to the instance).
+__global__ __launch_bounds__(kBlock) void k_emit_jobs(const InstDesc* __restrict__ desc,
+                                                      const uint32_t* __restrict__ slot,
+                                                      const uint32_t* __restrict__ job_wg_off,
+                                                      uint32_t njobs,
+                                                      const uint32_t* __restrict__ block,
+                                                      const uint32_t* __restrict__ rank) {
+  __shared__ uint32_t s_job;
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const InstDesc D = desc[slot[j]];
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(D.out);
+  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < D.n) out[q] = rank[block[D.state_off + q]];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_results_jobs(const InstDesc* __restrict__ desc,
+                                                         const uint32_t* __restrict__ slot,
+                                                         uint32_t njobs,
+                                                         const uint32_t* __restrict__ totals,
+                                                         const uint32_t* __restrict__ refine_cnt,
+                                                         ResultDev* __restrict__ res) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= njobs) return;
+  const InstDesc D = desc[slot[j]];
+  ResultDev r;
+  r.num_blocks = totals[j];
+  r.initial_block = reinterpret_cast<const uint32_t*>(D.out)[D.q0];
+  r.refine_rounds = refine_cnt[slot[j]];
+  r.pad = 0;
+  res[j] = r;
+}
+
 inline uint32_t grid_for(uint64_t items, uint64_t per_wg) {
   return (uint32_t)((items + per_wg - 1) / per_wg);
 }
@@ -742,16 +943,16 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) 
 
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
-                      const uint32_t* dense, uint32_t* sig, Slot* table, uint32_t tbits,
-                      uint32_t* slot_of, uint64_t salt, hipStream_t s) {
+                      const uint32_t* dense, Slot* table, uint32_t tbits, uint32_t* slot_of,
+                      uint64_t salt, Ctrl* ctrl, hipStream_t s) {
   if (!m) return;
   const uint32_t grid = grid_for(m, kSigTile);
   if (batch)
     hipLaunchKernelGGL(k_signature<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, sig, table, tbits, slot_of, salt);
+                       block, dense, table, tbits, slot_of, salt, ctrl);
   else
     hipLaunchKernelGGL(k_signature<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, sig, table, tbits, slot_of, salt);
+                       block, dense, table, tbits, slot_of, salt, ctrl);
 }
 
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
@@ -773,39 +974,82 @@ void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* r
 }
 
 void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
-                    const InstDesc* desc, const uint32_t* sig, const Slot* table,
+                    const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
                     uint32_t ntiles, hipStream_t s) {
   if (!m) return;
   const uint32_t grid = grid_for(m, kBlock);
   if (batch)
-    hipLaunchKernelGGL(k_resolve<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, sig, table,
+    hipLaunchKernelGGL(k_resolve<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
                        slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles);
   else
-    hipLaunchKernelGGL(k_resolve<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, sig, table,
+    hipLaunchKernelGGL(k_resolve<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
                        slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles);
 }
 
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
-                    uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
+                    const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
                     unsigned long long* scan_status, hipStream_t s) {
   if (!m) return;
   const uint32_t grid = grid_for(m, kScanTile);
   if (batch)
     hipLaunchKernelGGL(k_compact<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, nb, keep,
-                       changed_inst, block, act_next, ctrl, scan_status);
+                       changed_inst, dead, block, act_next, ctrl, scan_status);
   else
     hipLaunchKernelGGL(k_compact<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, nb, keep,
-                       changed_inst, block, act_next, ctrl, scan_status);
+                       changed_inst, dead, block, act_next, ctrl, scan_status);
 }
 
-void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt,
+void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
                       const Ctrl* ctrl, hipStream_t s) {
   if (!ninst) return;
   hipLaunchKernelGGL(k_round_end, dim3(grid_for(ninst, kBlock)), dim3(kBlock), 0, s, ninst,
-                     changed_inst, refine_cnt, ctrl);
+                     changed_inst, refine_cnt, last, ctrl);
+}
+
+void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                      uint32_t njobs, uint32_t total_wgs, const uint32_t* act_off,
+                      const uint32_t* minF, const uint32_t* minN, uint32_t* inst_of,
+                      uint32_t* block, uint32_t* act, hipStream_t s) {
+  if (!total_wgs) return;
+  hipLaunchKernelGGL(k_init_join, dim3(total_wgs), dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs,
+                     act_off, minF, minN, inst_of, block, act);
+}
+
+void launch_init_minmax_slots(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                              uint32_t njobs, uint32_t total_wgs, unsigned long long* wg_part,
+                              uint32_t* minF, uint32_t* minN, hipStream_t s) {
+  if (!njobs || !total_wgs) return;
+  hipLaunchKernelGGL(k_init_minmax_slots, dim3(total_wgs), dim3(kBlock), 0, s, desc, slot, job_wg_off,
+                     njobs, wg_part);
+  hipLaunchKernelGGL(k_init_minmax_slots_reduce, dim3(njobs), dim3(kBlock), 0, s, slot, job_wg_off, njobs,
+                     total_wgs, wg_part, minF, minN);
+}
+
+void launch_scan_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_tile_off,
+                      uint32_t njobs, uint32_t total_tiles, const uint32_t* block, uint32_t* rank,
+                      uint32_t* totals, Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s) {
+  if (!total_tiles) return;
+  hipLaunchKernelGGL(k_scan_jobs, dim3(total_tiles), dim3(kBlock), 0, s, desc, slot, job_tile_off, njobs,
+                     block, rank, totals, ctrl, scan_status);
+}
+
+void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                      uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
+                      hipStream_t s) {
+  if (!total_wgs) return;
+  hipLaunchKernelGGL(k_emit_jobs, dim3(total_wgs), dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs,
+                     block, rank);
+}
+
+void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,
+                         const uint32_t* totals, const uint32_t* refine_cnt, ResultDev* res,
+                         hipStream_t s) {
+  if (!njobs) return;
+  hipLaunchKernelGGL(k_results_jobs, dim3(grid_for(njobs, kBlock)), dim3(kBlock), 0, s, desc, slot, njobs,
+                     totals, refine_cnt, res);
 }
 
 void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s) {

@@ -1,16 +1,907 @@
-// serving.hip -- continuous-batching request loop (placeholder: not yet wired).
+// serving.hip -- continuous-batching request loop.
+//
+// One worker thread owns a resident set of requests on the device.  Every
+// step it
+//   1. admits queued requests while a state range, a descriptor slot and
+//      their device buffers fit the budget (admission by HBM footprint);
+//      newcomers are validated, get their initial partition {F, Q\F} and
+//      append their states to the shared active list;
+//   2. runs ONE refinement round (the same fused kernels as the batch path)
+//      over every resident request -- requests that arrived while others were
+//      on the device join at the next step, so their work overlaps;
+//   3. retires every request whose round split nothing: canonical numbering
+//      of its states only (segmented scan), copy-out, buffers released.
+// Instances never interact: block ids are global state ids, so a request's
+// result is the same alone and in any mix.
 #include "serving.h"
 
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "closure.h"
 #include "engine.h"
 
 namespace dfamin {
 
-struct Serving::Impl {};
+namespace {
 
-Serving::Serving(Context*) : impl_(new Impl) {}
+constexpr uint32_t kSlots = 4096;               // resident requests at most
+constexpr uint64_t kDefaultArenaStates = 1ull << 26;
+constexpr uint32_t kDefaultAutoRounds = 8;
+constexpr size_t kMaxQueue = 1u << 16;
+
+inline uint32_t ceil_log2_u64(uint64_t x) {
+  uint32_t b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+inline uint64_t mix64(uint64_t z) {
+  z ^= z >> 30; z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27; z *= 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// First-fit allocator of state-id ranges in [0, cap).
+class RangeAlloc {
+ public:
+  void reset(uint64_t cap) {
+    free_.clear();
+    if (cap) free_[0] = cap;
+  }
+  bool alloc(uint64_t n, uint64_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= n) {
+        *off = it->first;
+        const uint64_t rest = it->second - n, start = it->first + n;
+        free_.erase(it);
+        if (rest) free_[start] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(uint64_t off, uint64_t n) {
+    auto it = free_.emplace(off, n).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+
+ private:
+  std::map<uint64_t, uint64_t> free_;  // offset -> length
+};
+
+// Caching device allocator with power-of-two size classes, bounded by a
+// byte budget.  Blocks are reused by later requests; nothing is returned to
+// HIP until the pool is destroyed (or space is needed for a larger class).
+class DevicePool {
+ public:
+  ~DevicePool() { release_all(); }
+  void set_budget(uint64_t b) { budget_ = b; }
+  uint64_t used() const { return used_; }
+  uint64_t budget() const { return budget_; }
+  static size_t size_class(size_t bytes) {
+    size_t c = 4096;
+    while (c < bytes) c <<= 1;
+    return c;
+  }
+  uint64_t live() const { return used_ - cached_; }
+  void* alloc(size_t bytes) {
+    const size_t c = size_class(bytes);
+    auto& fl = free_[c];
+    if (!fl.empty()) {
+      void* p = fl.back();
+      fl.pop_back();
+      cached_ -= c;
+      return p;
+    }
+    if (used_ + c > budget_) trim(used_ + c - budget_);
+    if (used_ + c > budget_) return nullptr;
+    void* p = nullptr;
+    if (hipMalloc(&p, c) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    used_ += c;
+    return p;
+  }
+  void free(void* p, size_t bytes) {
+    if (!p) return;
+    const size_t c = size_class(bytes);
+    free_[c].push_back(p);
+    cached_ += c;
+  }
+  void release_all() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) (void)hipFree(p);
+    free_.clear();
+    used_ -= cached_;
+    cached_ = 0;
+  }
+
+ private:
+  void trim(uint64_t need) {
+    for (auto& kv : free_) {
+      while (!kv.second.empty() && need > 0) {
+        (void)hipFree(kv.second.back());
+        kv.second.pop_back();
+        used_ -= kv.first;
+        cached_ -= kv.first;
+        need = need > kv.first ? need - kv.first : 0;
+      }
+    }
+  }
+  std::map<size_t, std::vector<void*>> free_;
+  uint64_t budget_ = 0, used_ = 0, cached_ = 0;
+};
+
+struct Request {
+  uint64_t ticket = 0;
+  uint32_t n = 0, k = 0, q0 = 0;
+  dfamin_opts opts{};
+  std::vector<uint32_t> delta;
+  std::vector<uint8_t> accept;
+  std::vector<uint32_t> out;
+  dfamin_result result{};
+  int status = 1;  // 1 pending, else a DFAMIN_* code
+  std::atomic<bool> cancelled{false};
+};
+
+struct Resident {
+  std::shared_ptr<Request> req;
+  uint32_t slot = 0;
+  uint64_t off = 0;
+  void* d_delta = nullptr;
+  void* d_accept = nullptr;
+  void* d_out = nullptr;
+  void* d_sig = nullptr;
+  void* d_closure = nullptr;
+  size_t sz_delta = 0, sz_accept = 0, sz_out = 0, sz_sig = 0, sz_closure = 0;
+  std::vector<uint32_t> nonid;
+  std::vector<uint64_t> rows;
+  uint32_t rounds = 0;
+  uint32_t levels = 0;
+  bool closure = false;
+  bool dead = false;
+};
+
+}  // namespace
+
+struct Serving::Impl {
+  explicit Impl(Context* c) : ctx(c) {}
+  ~Impl() { shutdown(); }
+
+  Context* ctx;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<Request>> queue;
+  std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
+  uint64_t next_ticket = 1;
+  bool stop = false;
+  bool started = false;
+  std::thread worker;
+  int init_rc = DFAMIN_OK;
+
+  // ---- device state (worker thread only)
+  hipStream_t stream = nullptr;
+  uint64_t cap = 0;  // state arena capacity
+  DevicePool pool;
+  RangeAlloc arena;
+  std::vector<Resident*> slots;
+  std::vector<InstDesc> desc;
+  std::vector<uint64_t> rows_host;
+  uint32_t m = 0;
+  uint64_t salt = 0x9E3779B97F4A7C15ull;
+  // fixed device buffers
+  void *d_block = nullptr, *d_inst_of = nullptr, *d_act = nullptr, *d_act2 = nullptr;
+  void *d_slot_of = nullptr, *d_nb = nullptr, *d_keep = nullptr, *d_rank = nullptr;
+  void *d_status = nullptr, *d_table = nullptr, *d_desc = nullptr, *d_rows = nullptr;
+  void *d_changed = nullptr, *d_last = nullptr, *d_refine = nullptr, *d_dead = nullptr;
+  void *d_minF = nullptr, *d_minN = nullptr, *d_ctrl = nullptr, *d_results = nullptr;
+  void *d_totals = nullptr;
+  size_t rows_cap = 0;
+  uint64_t table_cap = 0;
+  // scratch that grows
+  DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux;
+  HostBuf h_flags, h_ctrl, h_last, h_results;
+
+  void shutdown() {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      stop = true;
+    }
+    cv_work.notify_all();
+    if (worker.joinable()) worker.join();
+    {
+      std::lock_guard<std::mutex> g(mu);
+      for (auto& r : queue) { r->status = DFAMIN_E_CANCELLED; }
+      queue.clear();
+      for (auto& kv : tickets)
+        if (kv.second->status == 1) kv.second->status = DFAMIN_E_CANCELLED;
+    }
+    cv_done.notify_all();
+    free_device();
+  }
+
+  // ------------------------------------------------------------ memory
+  void* dmalloc(size_t bytes) {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 64) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  bool grow(DevBuf& b, size_t bytes) {
+    if (b.cap >= bytes) return true;
+    if (b.p) (void)hipFree(b.p);
+    size_t want = (bytes + bytes / 4 + 4095) & ~size_t(4095);
+    b.p = dmalloc(want);
+    b.cap = b.p ? want : 0;
+    return b.p != nullptr;
+  }
+  bool grow_host(HostBuf& b, size_t bytes) {
+    if (b.cap >= bytes) return true;
+    if (b.p) (void)hipHostFree(b.p);
+    size_t want = bytes + bytes / 4 + 64;
+    if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+      b.p = nullptr;
+      b.cap = 0;
+      return false;
+    }
+    b.cap = want;
+    return true;
+  }
+  void free_device() {
+    for (Resident* r : slots)
+      if (r) release_resident(r);
+    slots.clear();
+    void** ps[] = {&d_block, &d_inst_of, &d_act, &d_act2, &d_slot_of, &d_nb, &d_keep, &d_rank,
+                   &d_status, &d_table, &d_desc, &d_rows, &d_changed, &d_last, &d_refine, &d_dead,
+                   &d_minF, &d_minN, &d_ctrl, &d_results, &d_totals};
+    for (void** p : ps)
+      if (*p) { (void)hipFree(*p); *p = nullptr; }
+    DevBuf* db[] = {&s_jobs, &s_off, &s_flags, &s_wg, &s_part, &s_slot, &s_aux};
+    for (DevBuf* b : db)
+      if (b->p) { (void)hipFree(b->p); b->p = nullptr; b->cap = 0; }
+    HostBuf* hb[] = {&h_flags, &h_ctrl, &h_last, &h_results};
+    for (HostBuf* b : hb)
+      if (b->p) { (void)hipHostFree(b->p); b->p = nullptr; b->cap = 0; }
+    pool.release_all();
+    if (stream) { (void)hipStreamDestroy(stream); stream = nullptr; }
+  }
+
+  int init_device() {
+    if (hipSetDevice(ctx->device) != hipSuccess) return DFAMIN_E_DEVICE;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return DFAMIN_E_DEVICE;
+    // arena sized from the budget: ~37 bytes per state of fixed buffers,
+    // 16 per state of hash table, the rest for request buffers
+    cap = kDefaultArenaStates;
+    if (const char* e = std::getenv("DFAMIN_SERVING_STATES")) {
+      const unsigned long long v = std::strtoull(e, nullptr, 10);
+      if (v >= 1024 && v < (1ull << 31)) cap = v;
+    }
+    while (cap > (1u << 16) && cap * 64 > ctx->budget / 2) cap >>= 1;
+    const uint64_t fixed = cap * 53;
+    pool.set_budget(ctx->budget > fixed ? ctx->budget - fixed : 0);
+    d_block = dmalloc(cap * 4); d_inst_of = dmalloc(cap * 4);
+    d_act = dmalloc(cap * 4); d_act2 = dmalloc(cap * 4);
+    d_slot_of = dmalloc(cap * 4); d_nb = dmalloc(cap * 4);
+    d_keep = dmalloc(cap); d_rank = dmalloc(cap * 4 + 4);
+    d_status = dmalloc(((cap + kScanTile - 1) / kScanTile + kSlots + 1) * 8);
+    table_cap = 1ull << std::max<uint32_t>(9, ceil_log2_u64(2 * cap));
+    d_table = dmalloc(table_cap * sizeof(Slot));
+    d_desc = dmalloc(kSlots * sizeof(InstDesc));
+    d_changed = dmalloc(kSlots * 4); d_last = dmalloc(kSlots * 4);
+    d_refine = dmalloc(kSlots * 4); d_dead = dmalloc(kSlots * 4);
+    d_minF = dmalloc(kSlots * 4); d_minN = dmalloc(kSlots * 4);
+    d_ctrl = dmalloc(sizeof(Ctrl)); d_results = dmalloc(kSlots * sizeof(ResultDev));
+    d_totals = dmalloc(kSlots * 4);
+    void* all[] = {d_block, d_inst_of, d_act, d_act2, d_slot_of, d_nb, d_keep, d_rank, d_status,
+                   d_table, d_desc, d_changed, d_last, d_refine, d_dead, d_minF, d_minN, d_ctrl,
+                   d_results, d_totals};
+    for (void* p : all)
+      if (!p) return DFAMIN_E_NOMEM;
+    if (hipMemsetAsync(d_changed, 0, kSlots * 4, stream) != hipSuccess ||
+        hipMemsetAsync(d_refine, 0, kSlots * 4, stream) != hipSuccess ||
+        hipMemsetAsync(d_dead, 0, kSlots * 4, stream) != hipSuccess ||
+        hipMemsetAsync(d_ctrl, 0, sizeof(Ctrl), stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    if (!grow_host(h_ctrl, sizeof(Ctrl)) || !grow_host(h_last, kSlots * 4) ||
+        !grow_host(h_results, kSlots * sizeof(ResultDev)))
+      return DFAMIN_E_NOMEM;
+    arena.reset(cap);
+    slots.assign(kSlots, nullptr);
+    desc.assign(kSlots, InstDesc{});
+    return hipStreamSynchronize(stream) == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
+  }
+
+  void release_resident(Resident* r) {
+    pool.free(r->d_delta, r->sz_delta);
+    pool.free(r->d_accept, r->sz_accept);
+    pool.free(r->d_out, r->sz_out);
+    pool.free(r->d_sig, r->sz_sig);
+    pool.free(r->d_closure, r->sz_closure);
+    arena.release(r->off, r->req->n);
+    slots[r->slot] = nullptr;
+    desc[r->slot] = InstDesc{};
+    delete r;
+  }
+
+  // Device bytes a request needs besides the fixed per-state buffers.
+  static size_t footprint(const Request& q) {
+    const size_t n = q.n, k = q.k;
+    size_t b = DevicePool::size_class(4 * n * k) + DevicePool::size_class((n + 7) / 8) +
+               DevicePool::size_class(4 * n) + DevicePool::size_class(4 * n * (k + 1));
+    if (q.opts.closure != DFAMIN_CLOSURE_OFF) {
+      const size_t L = floor_log2_u32(q.n);
+      b += DevicePool::size_class(4 * n * k * L) + DevicePool::size_class(4 * n * (k * (L + 1) + 1));
+    }
+    return b;
+  }
+
+  // ------------------------------------------------------------ worker
+  void finish(const std::shared_ptr<Request>& r, int status) {
+    {
+      std::lock_guard<std::mutex> g(mu);
+      r->status = status;
+    }
+    cv_done.notify_all();
+  }
+
+  // (re)upload descriptors and row pointers of every resident request
+  int upload_layout() {
+    rows_host.clear();
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      Resident* r = slots[s];
+      if (!r) continue;
+      desc[s].rows_off = (uint32_t)rows_host.size();
+      desc[s].kp = (uint32_t)r->rows.size();
+      rows_host.insert(rows_host.end(), r->rows.begin(), r->rows.end());
+    }
+    if (rows_host.size() * 8 > rows_cap) {
+      if (d_rows) (void)hipFree(d_rows);
+      rows_cap = (rows_host.size() * 8 * 2 + 4096);
+      d_rows = dmalloc(rows_cap);
+      if (!d_rows) return DFAMIN_E_NOMEM;
+    }
+    if (!rows_host.empty() &&
+        hipMemcpyAsync(d_rows, rows_host.data(), rows_host.size() * 8, hipMemcpyHostToDevice, stream) !=
+            hipSuccess)
+      return DFAMIN_E_DEVICE;
+    if (hipMemcpyAsync(d_desc, desc.data(), kSlots * sizeof(InstDesc), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+      return DFAMIN_E_DEVICE;
+    return DFAMIN_OK;
+  }
+
+  ClosureScratch scratch() {
+    ClosureScratch sc;
+    sc.ensure = [this](int b, size_t bytes) -> void* {
+      DevBuf* bufs[4] = {&s_jobs, &s_off, &s_flags, &s_wg};
+      return grow(*bufs[b], bytes) ? bufs[b]->p : nullptr;
+    };
+    sc.host_flags = [this](size_t bytes) -> void* { return grow_host(h_flags, bytes) ? h_flags.p : nullptr; };
+    return sc;
+  }
+
+  // Closure (Algorithm 5) for the given residents; swaps their signature
+  // buffers for ones sized to the new letter count.
+  int build_closures(const std::vector<Resident*>& rs) {
+    std::vector<ClosureSpec> specs(rs.size());
+    for (size_t w = 0; w < rs.size(); ++w) {
+      Resident* r = rs[w];
+      uint32_t L = floor_log2_u32(r->req->n);
+      if (r->req->opts.max_levels && r->req->opts.max_levels < L) L = r->req->opts.max_levels;
+      specs[w].n = r->req->n;
+      specs[w].delta = static_cast<const uint32_t*>(r->d_delta);
+      specs[w].letters = r->nonid;
+      specs[w].L = L;
+      const size_t words = (size_t)r->nonid.size() * L * r->req->n;
+      if (words) {
+        r->sz_closure = words * 4;
+        r->d_closure = pool.alloc(r->sz_closure);
+        if (!r->d_closure) return DFAMIN_E_NOMEM;
+      }
+      specs[w].storage = static_cast<uint32_t*>(r->d_closure);
+      r->levels = L;
+    }
+    std::vector<std::vector<uint64_t>> rows;
+    int rc = build_closure_levels(specs, scratch(), stream, rows);
+    if (rc != DFAMIN_OK) return rc;
+    for (size_t w = 0; w < rs.size(); ++w) {
+      Resident* r = rs[w];
+      r->rows = rows[w];
+      r->closure = true;
+      pool.free(r->d_sig, r->sz_sig);
+      r->sz_sig = (size_t)r->req->n * (r->rows.size() + 1) * 4;
+      r->d_sig = pool.alloc(r->sz_sig);
+      if (!r->d_sig) return DFAMIN_E_NOMEM;
+      desc[r->slot].sig = reinterpret_cast<uint64_t>(r->d_sig);
+    }
+    return DFAMIN_OK;
+  }
+
+  // Bring newly admitted requests onto the device.
+  int join(std::vector<Resident*>& js) {
+    // upload inputs
+    for (Resident* r : js) {
+      if (hipMemcpyAsync(r->d_delta, r->req->delta.data(), r->sz_delta, hipMemcpyHostToDevice, stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(r->d_accept, r->req->accept.data(), r->req->accept.size(), hipMemcpyHostToDevice,
+                         stream) != hipSuccess)
+        return DFAMIN_E_DEVICE;
+    }
+    // validation and identity letters: one row job per (request, letter)
+    std::vector<RowJob> jobs;
+    std::vector<uint32_t> joboff;
+    uint32_t wgs = 0;
+    for (Resident* r : js)
+      for (uint32_t a = 0; a < r->req->k; ++a) {
+        RowJob J;
+        J.src = reinterpret_cast<uint64_t>(r->d_delta) + 4ull * a * r->req->n;
+        J.dst = 0;
+        J.n = r->req->n;
+        J.flag_idx = (uint32_t)jobs.size();
+        joboff.push_back(wgs);
+        wgs += (J.n + kRowTile - 1) / kRowTile;
+        jobs.push_back(J);
+      }
+    if (!grow(s_jobs, jobs.size() * sizeof(RowJob)) || !grow(s_off, joboff.size() * 4) ||
+        !grow(s_flags, jobs.size() * 4) || !grow(s_wg, (size_t)wgs * 4) ||
+        !grow_host(h_flags, jobs.size() * 4))
+      return DFAMIN_E_NOMEM;
+    if (hipMemcpyAsync(s_jobs.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(s_off.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    launch_row_check(s_jobs.as<RowJob>(), s_off.as<uint32_t>(), (uint32_t)jobs.size(), wgs,
+                     s_wg.as<uint32_t>(), s_flags.as<uint32_t>(), stream);
+    if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
+    if (hipMemcpyAsync(h_flags.p, s_flags.p, jobs.size() * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    const uint32_t* f = h_flags.as<uint32_t>();
+    std::vector<Resident*> ok, need_closure;
+    size_t j = 0;
+    for (Resident* r : js) {
+      bool bad = false;
+      r->nonid.clear();
+      for (uint32_t a = 0; a < r->req->k; ++a, ++j) {
+        if (f[j] & kFlagBad) bad = true;
+        if (f[j] & kFlagNonId) r->nonid.push_back(a);
+      }
+      if (bad) {
+        auto req = r->req;
+        release_resident(r);
+        finish(req, DFAMIN_E_BAD_DFA);
+        continue;
+      }
+      r->rows.clear();
+      for (uint32_t a : r->nonid)
+        r->rows.push_back(reinterpret_cast<uint64_t>(r->d_delta) + 4ull * a * r->req->n);
+      InstDesc& D = desc[r->slot];
+      D = InstDesc{};
+      D.state_off = (uint32_t)r->off;
+      D.n = r->req->n;
+      D.k = r->req->k;
+      D.q0 = r->req->q0;
+      D.accept = reinterpret_cast<uint64_t>(r->d_accept);
+      D.out = reinterpret_cast<uint64_t>(r->d_out);
+      D.sig = reinterpret_cast<uint64_t>(r->d_sig);
+      ok.push_back(r);
+      if (r->req->opts.closure == DFAMIN_CLOSURE_ON) need_closure.push_back(r);
+    }
+    js = ok;
+    if (js.empty()) return DFAMIN_OK;
+    if (!need_closure.empty()) {
+      int rc = build_closures(need_closure);
+      if (rc != DFAMIN_OK) return rc;
+    }
+    // first round of each newcomer groups on exact keys from accept bits
+    for (Resident* r : js) {
+      desc[r->slot].ebits = (r->rows.size() + 1 <= 31) ? 1u : 0u;
+      desc[r->slot].dsrc = 1u;
+    }
+    int rc = upload_layout();
+    if (rc != DFAMIN_OK) return rc;
+    // reset per-slot counters and build the initial partition
+    std::vector<uint32_t> slot_ids, wgoff, actoff;
+    uint32_t iw = 0, am = m;
+    for (Resident* r : js) {
+      slot_ids.push_back(r->slot);
+      wgoff.push_back(iw);
+      actoff.push_back(am);
+      iw += (r->req->n + kRowTile - 1) / kRowTile;
+      am += r->req->n;
+      if (hipMemsetAsync(static_cast<uint32_t*>(d_changed) + r->slot, 0, 4, stream) != hipSuccess ||
+          hipMemsetAsync(static_cast<uint32_t*>(d_refine) + r->slot, 0, 4, stream) != hipSuccess ||
+          hipMemsetAsync(static_cast<uint32_t*>(d_dead) + r->slot, 0, 4, stream) != hipSuccess)
+        return DFAMIN_E_DEVICE;
+    }
+    const size_t nj = js.size();
+    if (!grow(s_slot, nj * 4 * 3) || !grow(s_part, (size_t)iw * 8)) return DFAMIN_E_NOMEM;
+    uint32_t* d_sl = s_slot.as<uint32_t>();
+    if (hipMemcpyAsync(d_sl, slot_ids.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(d_sl + nj, wgoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(d_sl + 2 * nj, actoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    launch_init_minmax_slots(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, iw,
+                             s_part.as<unsigned long long>(), static_cast<uint32_t*>(d_minF),
+                             static_cast<uint32_t*>(d_minN), stream);
+    launch_init_join(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, iw, d_sl + 2 * nj,
+                     static_cast<uint32_t*>(d_minF), static_cast<uint32_t*>(d_minN),
+                     static_cast<uint32_t*>(d_inst_of), static_cast<uint32_t*>(d_block),
+                     static_cast<uint32_t*>(d_act), stream);
+    if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
+    // host vectors must outlive the asynchronous copies
+    if (hipStreamSynchronize(stream) != hipSuccess) return DFAMIN_E_DEVICE;
+    m = am;
+    return DFAMIN_OK;
+  }
+
+  // Canonical numbering and copy-out for retiring residents.
+  int retire(const std::vector<Resident*>& rs) {
+    std::vector<Resident*> live;
+    for (Resident* r : rs)
+      if (!r->dead) live.push_back(r);
+    if (!live.empty()) {
+      const size_t nj = live.size();
+      std::vector<uint32_t> slot_ids, tileoff, wgoff;
+      uint32_t tiles = 0, wgs = 0;
+      for (Resident* r : live) {
+        slot_ids.push_back(r->slot);
+        tileoff.push_back(tiles);
+        wgoff.push_back(wgs);
+        tiles += (r->req->n + kScanTile - 1) / kScanTile;
+        wgs += (r->req->n + kRowTile - 1) / kRowTile;
+      }
+      if (!grow(s_aux, nj * 4 * 3)) return DFAMIN_E_NOMEM;
+      uint32_t* d_sl = s_aux.as<uint32_t>();
+      if (hipMemcpyAsync(d_sl, slot_ids.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+          hipMemcpyAsync(d_sl + nj, tileoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+          hipMemcpyAsync(d_sl + 2 * nj, wgoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+        return DFAMIN_E_DEVICE;
+      launch_prep_scan(static_cast<unsigned long long*>(d_status), tiles, static_cast<Ctrl*>(d_ctrl), stream);
+      launch_scan_jobs(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, tiles,
+                       static_cast<uint32_t*>(d_block), static_cast<uint32_t*>(d_rank),
+                       static_cast<uint32_t*>(d_totals), static_cast<Ctrl*>(d_ctrl),
+                       static_cast<unsigned long long*>(d_status), stream);
+      launch_emit_jobs(static_cast<InstDesc*>(d_desc), d_sl, d_sl + 2 * nj, (uint32_t)nj, wgs,
+                       static_cast<uint32_t*>(d_block), static_cast<uint32_t*>(d_rank), stream);
+      launch_results_jobs(static_cast<InstDesc*>(d_desc), d_sl, (uint32_t)nj,
+                          static_cast<uint32_t*>(d_totals), static_cast<uint32_t*>(d_refine),
+                          static_cast<ResultDev*>(d_results), stream);
+      if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
+      for (Resident* r : live) {
+        r->req->out.resize(r->req->n);
+        if (hipMemcpyAsync(r->req->out.data(), r->d_out, 4ull * r->req->n, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess)
+          return DFAMIN_E_DEVICE;
+      }
+      if (hipMemcpyAsync(h_results.p, d_results, nj * sizeof(ResultDev), hipMemcpyDeviceToHost, stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(h_ctrl.p, d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+          hipStreamSynchronize(stream) != hipSuccess)
+        return DFAMIN_E_DEVICE;
+      if (h_ctrl.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
+      const ResultDev* res = h_results.as<ResultDev>();
+      for (size_t w = 0; w < nj; ++w) {
+        Resident* r = live[w];
+        dfamin_result& o = r->req->result;
+        o.num_blocks = res[w].num_blocks;
+        o.initial_block = res[w].initial_block;
+        o.refine_rounds = res[w].refine_rounds;
+        o.rounds_executed = res[w].refine_rounds + 1;
+        o.closure_levels = r->closure ? r->levels : 0;
+        o.closure_letters = r->closure ? (uint32_t)r->rows.size() : 0;
+        o.status = DFAMIN_OK;
+      }
+    }
+    for (Resident* r : rs) {
+      auto req = r->req;
+      const bool dead = r->dead;
+      release_resident(r);
+      finish(req, dead ? DFAMIN_E_CANCELLED : DFAMIN_OK);
+    }
+    return DFAMIN_OK;
+  }
+
+  // One refinement round over every resident request.
+  int round() {
+    // cancellations take effect in this round's compaction
+    bool dirty = false;
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      Resident* r = slots[s];
+      if (r && !r->dead && r->req->cancelled) {
+        r->dead = true;
+        const uint32_t one = 1;
+        if (hipMemcpyAsync(static_cast<uint32_t*>(d_dead) + s, &one, 4, hipMemcpyHostToDevice, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+          return DFAMIN_E_DEVICE;
+        dirty = true;
+      }
+    }
+    (void)dirty;
+    if (m > 0) {
+      int retries = 0;
+      while (true) {
+        const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2ull * m));
+        const uint64_t tsize = 1ull << tbits;
+        if (tsize > table_cap) return DFAMIN_E_INTERNAL;
+        const uint32_t ntiles = (m + kScanTile - 1) / kScanTile;
+        uint32_t* act = static_cast<uint32_t*>(d_act);
+        uint32_t* nxt = static_cast<uint32_t*>(d_act2);
+        launch_clear_table(static_cast<Slot*>(d_table), tsize, static_cast<Ctrl*>(d_ctrl), stream);
+        launch_signature(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<InstDesc*>(d_desc),
+                         static_cast<uint64_t*>(d_rows), static_cast<uint32_t*>(d_block), nullptr,
+                         static_cast<Slot*>(d_table), tbits, static_cast<uint32_t*>(d_slot_of), salt,
+                         static_cast<Ctrl*>(d_ctrl), stream);
+        launch_resolve(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<InstDesc*>(d_desc),
+                       static_cast<Slot*>(d_table), static_cast<uint32_t*>(d_slot_of),
+                       static_cast<uint32_t*>(d_block), static_cast<uint32_t*>(d_nb),
+                       static_cast<uint8_t*>(d_keep), static_cast<uint32_t*>(d_changed),
+                       static_cast<Ctrl*>(d_ctrl), static_cast<unsigned long long*>(d_status), ntiles, stream);
+        launch_compact(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<uint32_t*>(d_nb),
+                       static_cast<uint8_t*>(d_keep), static_cast<uint32_t*>(d_changed),
+                       static_cast<uint32_t*>(d_dead), static_cast<uint32_t*>(d_block), nxt,
+                       static_cast<Ctrl*>(d_ctrl), static_cast<unsigned long long*>(d_status), stream);
+        launch_round_end(kSlots, static_cast<uint32_t*>(d_changed), static_cast<uint32_t*>(d_refine),
+                         static_cast<uint32_t*>(d_last), static_cast<Ctrl*>(d_ctrl), stream);
+        if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
+        if (hipMemcpyAsync(h_ctrl.p, d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipMemcpyAsync(h_last.p, d_last, kSlots * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+          return DFAMIN_E_DEVICE;
+        const Ctrl c = *h_ctrl.as<Ctrl>();
+        if (c.fault) return DFAMIN_E_INTERNAL;
+        if (c.collision) {
+          if (++retries > 8) return DFAMIN_E_INTERNAL;
+          salt = mix64(salt + 0x9E3779B97F4A7C15ull);
+          continue;
+        }
+        std::swap(d_act, d_act2);
+        m = c.m_next;
+        break;
+      }
+    } else {
+      std::memset(h_last.p, 0, kSlots * 4);
+    }
+    // who is done, who needs the closure, whose next round hashes
+    const uint32_t* last = h_last.as<uint32_t>();
+    std::vector<Resident*> done, auto_closure;
+    bool desc_dirty = false;
+    for (uint32_t s = 0; s < kSlots; ++s) {
+      Resident* r = slots[s];
+      if (!r) continue;
+      r->rounds += 1;
+      if (!last[s] || r->dead) {
+        done.push_back(r);
+        continue;
+      }
+      if (desc[s].dsrc) {  // accept bits only describe the first round's partition
+        desc[s].ebits = 0;
+        desc[s].dsrc = 0;
+        desc_dirty = true;
+      }
+      const uint32_t ar = r->req->opts.auto_rounds ? r->req->opts.auto_rounds : kDefaultAutoRounds;
+      if (r->req->opts.closure == DFAMIN_CLOSURE_AUTO && !r->closure && r->rounds == ar)
+        auto_closure.push_back(r);
+    }
+    if (!auto_closure.empty()) {
+      int rc = build_closures(auto_closure);
+      if (rc != DFAMIN_OK) return rc;
+      desc_dirty = true;
+    }
+    if (desc_dirty) {
+      int rc = upload_layout();
+      if (rc != DFAMIN_OK) return rc;
+    }
+    if (!done.empty()) return retire(done);
+    return DFAMIN_OK;
+  }
+
+  bool any_resident() const {
+    for (Resident* r : slots)
+      if (r) return true;
+    return false;
+  }
+
+  void fail_all(int rc) {
+    std::vector<std::shared_ptr<Request>> rs;
+    {
+      std::lock_guard<std::mutex> g(mu);
+      for (auto& r : queue) rs.push_back(r);
+      queue.clear();
+    }
+    for (Resident* r : slots)
+      if (r) rs.push_back(r->req);
+    for (Resident* r : slots)
+      if (r) release_resident(r);
+    for (auto& r : rs) finish(r, rc);
+  }
+
+  void run() {
+    init_rc = init_device();
+    if (init_rc != DFAMIN_OK) {
+      fail_all(init_rc);
+      std::unique_lock<std::mutex> lk(mu);
+      while (!stop) {
+        for (auto& r : queue) r->status = init_rc;
+        queue.clear();
+        cv_done.notify_all();
+        cv_work.wait(lk);
+      }
+      return;
+    }
+    while (true) {
+      std::vector<Resident*> joining;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [&] { return stop || !queue.empty() || any_resident(); });
+        if (stop) break;
+        // admission by footprint, first come first served
+        while (!queue.empty()) {
+          std::shared_ptr<Request> q = queue.front();
+          if (q->cancelled) {
+            queue.pop_front();
+            q->status = DFAMIN_E_CANCELLED;
+            cv_done.notify_all();
+            continue;
+          }
+          uint32_t slot = kSlots;
+          for (uint32_t s = 0; s < kSlots; ++s)
+            if (!slots[s]) { slot = s; break; }
+          uint64_t off = 0;
+          const size_t fp = footprint(*q);
+          const bool fits = slot < kSlots && pool.live() + fp <= pool.budget() && arena.alloc(q->n, &off);
+          if (!fits) {
+            if (!any_resident() && joining.empty()) {
+              // can never fit: reject instead of waiting forever
+              queue.pop_front();
+              q->status = DFAMIN_E_NOMEM;
+              cv_done.notify_all();
+              continue;
+            }
+            break;
+          }
+          Resident* r = new Resident;
+          r->req = q;
+          r->slot = slot;
+          r->off = off;
+          r->sz_delta = 4ull * q->n * q->k;
+          r->sz_accept = (q->n + 7) / 8;
+          r->sz_out = 4ull * q->n;
+          r->sz_sig = 4ull * q->n * (q->k + 1);
+          r->d_delta = pool.alloc(r->sz_delta);
+          r->d_accept = pool.alloc(r->sz_accept);
+          r->d_out = pool.alloc(r->sz_out);
+          r->d_sig = pool.alloc(r->sz_sig);
+          slots[slot] = r;
+          if (!r->d_delta || !r->d_accept || !r->d_out || !r->d_sig) {
+            release_resident(r);
+            if (!any_resident() && joining.empty()) {
+              queue.pop_front();
+              q->status = DFAMIN_E_NOMEM;
+              cv_done.notify_all();
+              continue;
+            }
+            break;
+          }
+          queue.pop_front();
+          joining.push_back(r);
+        }
+      }
+      int rc = DFAMIN_OK;
+      if (!joining.empty()) rc = join(joining);
+      if (rc == DFAMIN_OK && any_resident()) rc = round();
+      if (rc != DFAMIN_OK) {
+        fail_all(rc);
+        m = 0;
+        arena.reset(cap);
+        if (rc == DFAMIN_E_DEVICE) {
+          ctx->device_lost = true;
+          std::unique_lock<std::mutex> lk(mu);
+          while (!stop) {
+            for (auto& r : queue) r->status = rc;
+            queue.clear();
+            cv_done.notify_all();
+            cv_work.wait(lk);
+          }
+          return;
+        }
+      }
+    }
+  }
+};
+
+Serving::Serving(Context* ctx) : impl_(new Impl(ctx)) {}
+
 Serving::~Serving() { delete impl_; }
-int Serving::submit(const dfamin_dfa&, const dfamin_opts&, uint64_t*) { return DFAMIN_E_INTERNAL; }
-int Serving::wait(uint64_t, int64_t, uint32_t*, dfamin_result*) { return DFAMIN_E_INTERNAL; }
-int Serving::cancel(uint64_t) { return DFAMIN_E_INTERNAL; }
+
+int Serving::submit(const dfamin_dfa& dfa, const dfamin_opts& opts, uint64_t* ticket) {
+  auto r = std::make_shared<Request>();
+  r->n = dfa.n;
+  r->k = dfa.k;
+  r->q0 = dfa.q0;
+  r->opts = opts;
+  try {
+    r->delta.assign(dfa.delta, dfa.delta + (size_t)dfa.n * dfa.k);
+    r->accept.assign(dfa.accept, dfa.accept + ((size_t)dfa.n + 7) / 8);
+  } catch (...) {
+    return DFAMIN_E_NOMEM;
+  }
+  {
+    std::lock_guard<std::mutex> g(impl_->mu);
+    if (impl_->stop) return DFAMIN_E_CANCELLED;
+    if (impl_->queue.size() >= kMaxQueue) return DFAMIN_E_BUSY;
+    r->ticket = impl_->next_ticket++;
+    impl_->tickets[r->ticket] = r;
+    impl_->queue.push_back(r);
+    if (!impl_->started) {
+      impl_->started = true;
+      impl_->worker = std::thread([this] { impl_->run(); });
+    }
+  }
+  impl_->cv_work.notify_all();
+  *ticket = r->ticket;
+  return DFAMIN_OK;
+}
+
+int Serving::wait(uint64_t ticket, int64_t timeout_us, uint32_t* out, dfamin_result* result) {
+  std::unique_lock<std::mutex> lk(impl_->mu);
+  auto it = impl_->tickets.find(ticket);
+  if (it == impl_->tickets.end()) return DFAMIN_E_INVAL;
+  std::shared_ptr<Request> r = it->second;
+  auto done = [&] { return r->status != 1; };
+  if (timeout_us < 0) {
+    impl_->cv_done.wait(lk, done);
+  } else if (!impl_->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+    return DFAMIN_E_TIMEOUT;
+  }
+  const int st = r->status;
+  if (st == DFAMIN_OK) {
+    std::memcpy(out, r->out.data(), 4ull * r->n);
+    if (result) *result = r->result;
+  } else if (result) {
+    std::memset(result, 0, sizeof(*result));
+    result->status = st;
+  }
+  impl_->tickets.erase(it);
+  return st;
+}
+
+int Serving::cancel(uint64_t ticket) {
+  {
+    std::lock_guard<std::mutex> g(impl_->mu);
+    auto it = impl_->tickets.find(ticket);
+    if (it == impl_->tickets.end()) return DFAMIN_E_INVAL;
+    it->second->cancelled = true;
+  }
+  impl_->cv_work.notify_all();
+  return DFAMIN_OK;
+}
 
 }  // namespace dfamin

@@ -1,0 +1,122 @@
+"""Serving (continuous batching) through dfamin_submit / dfamin_wait / dfamin_cancel.
+
+Every result must be identical alone and in any mix (tolerance 0: the output
+is an exact integer partition) and identical to the CPU oracle.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2410_22764_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_22764_amd import dfamin
+    c = dfamin.dfamin_create(0)
+    yield c
+    c.close()
+
+
+def _mix(seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(2 ** rng.uniform(4, 15))
+        k = int(rng.integers(1, 7))
+        kind = rng.choice(["random", "chain", "coarse"], p=[0.6, 0.2, 0.2])
+        closure = ["off", "auto", "on"][i % 3]
+        if kind == "chain":
+            d = W.permuted_chain_dfa(n, k, seed * 1000 + i)
+        else:
+            d = W.random_dfa(n, k, seed * 1000 + i)
+            if kind == "coarse":
+                acc = np.zeros(n, bool)
+                acc[:: 37] = True
+                d.accept = W.pack_accept(acc)
+        if kind == "chain" and closure == "off":
+            closure = "auto"  # keep plain chain rounds bounded
+        out.append((d, closure))
+    return out
+
+
+def test_mix_matches_alone_and_oracle(ctx):
+    from paper_2410_22764_amd import dfamin
+    reqs = _mix(1, 60)
+    print("[case] serving mix of 60", flush=True)
+    tickets = [dfamin.dfamin_submit(ctx, d, {"closure": c}) for d, c in reqs]
+    for (d, c), t in zip(reqs, tickets):
+        rc, out, res = dfamin.dfamin_wait(ctx, t, d.n, timeout_us=20_000_000)
+        assert rc == dfamin.DFAMIN_OK, (d.name, rc)
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        assert res["num_blocks"] == nb and np.array_equal(out, want), d.name
+        alone, ra = dfamin.dfamin_minimize(ctx, d, {"closure": c})
+        assert np.array_equal(alone, out)
+        assert ra["refine_rounds"] == res["refine_rounds"], d.name
+        assert res["initial_block"] == want[d.q0]
+
+
+def test_staggered_arrivals(ctx):
+    """Requests submitted while others are resident join the running set."""
+    from paper_2410_22764_amd import dfamin
+    reqs = _mix(2, 40)
+    print("[case] serving staggered", flush=True)
+    tickets = []
+    for i, (d, c) in enumerate(reqs):
+        tickets.append(dfamin.dfamin_submit(ctx, d, {"closure": c}))
+        if i % 5 == 0:
+            time.sleep(0.002)
+    for (d, c), t in zip(reqs, tickets):
+        rc, out, res = dfamin.dfamin_wait(ctx, t, d.n)
+        assert rc == dfamin.DFAMIN_OK
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        assert np.array_equal(out, want)
+
+
+def test_short_request_overtakes_long_one(ctx):
+    """Continuous batching: a short request that arrives after a long one
+    finishes while the long one is still refining."""
+    from paper_2410_22764_amd import dfamin
+    long = W.chain_dfa(20000, 1)  # closure off: ~20000 rounds
+    short = W.random_dfa(500, 2, 7)
+    print("[case] serving overtake", flush=True)
+    tl = dfamin.dfamin_submit(ctx, long, {"closure": "off"})
+    time.sleep(0.01)
+    ts = dfamin.dfamin_submit(ctx, short, None)
+    rc, out, res = dfamin.dfamin_wait(ctx, ts, short.n, timeout_us=30_000_000)
+    assert rc == dfamin.DFAMIN_OK
+    rc_long, _, _ = dfamin.dfamin_wait(ctx, tl, long.n, timeout_us=0)
+    assert rc_long == dfamin.DFAMIN_E_TIMEOUT  # still on the device
+    rc_long, out_long, res_long = dfamin.dfamin_wait(ctx, tl, long.n)
+    assert rc_long == dfamin.DFAMIN_OK
+    assert np.array_equal(out_long, np.arange(long.n)) and res_long["refine_rounds"] == long.n - 2
+    want, _ = oracle.hopcroft(short.n, short.k, short.delta, short.accept)
+    assert np.array_equal(out, want)
+
+
+def test_cancel_and_errors(ctx):
+    from paper_2410_22764_amd import dfamin
+    print("[case] serving cancel", flush=True)
+    long = W.chain_dfa(20000, 1)
+    t = dfamin.dfamin_submit(ctx, long, {"closure": "off"})
+    time.sleep(0.01)
+    assert dfamin.dfamin_cancel(ctx, t) == dfamin.DFAMIN_OK
+    rc, out, _ = dfamin.dfamin_wait(ctx, t, long.n)
+    assert rc == dfamin.DFAMIN_E_CANCELLED and out is None
+    assert dfamin.dfamin_cancel(ctx, 10 ** 12) == dfamin.DFAMIN_E_INVAL
+    bad = W.random_dfa(100, 2, 1)
+    bad.delta = bad.delta.copy()
+    bad.delta[3] = 100
+    t = dfamin.dfamin_submit(ctx, bad, None)
+    rc, _, _ = dfamin.dfamin_wait(ctx, t, bad.n)
+    assert rc == dfamin.DFAMIN_E_BAD_DFA
+    # the loop keeps serving afterwards
+    d = W.random_dfa(300, 3, 2)
+    t = dfamin.dfamin_submit(ctx, d, None)
+    rc, out, _ = dfamin.dfamin_wait(ctx, t, d.n)
+    want, _ = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+    assert rc == dfamin.DFAMIN_OK and np.array_equal(out, want)

@@ -1,0 +1,73 @@
+"""Full-size synthetic workloads on the GPU against oracle results.
+
+Expected values come from tests/golden/expected_workloads.json, written by
+tests/golden/make_expected.py with the CPU oracle only.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2410_22764_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+EXPECTED = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "expected_workloads.json")))
+
+
+def digest(out):
+    return hashlib.sha256(np.ascontiguousarray(out, dtype="<u4").tobytes()).hexdigest()[:32]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2410_22764_amd import dfamin
+    c = dfamin.dfamin_create(0)
+    yield c
+    c.close()
+
+
+def test_plain_large_full_size(ctx):
+    """Random DFA, n = 2^24, |Sigma| = 4, seed 1, through the device entry point
+    with the closure policy the benchmark uses."""
+    import torch
+    from paper_2410_22764_amd import dfamin
+    print("[case] plain_large seed 1", flush=True)
+    d = W.plain_large(1)
+    dev = torch.device("cuda:0")
+    delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+    accept = torch.from_numpy(d.accept).to(dev)
+    out = torch.empty(d.n, dtype=torch.int32, device=dev)
+    res = dfamin.dfamin_minimize_device(ctx, d.n, d.k, delta.data_ptr(), accept.data_ptr(), d.q0,
+                                        out.data_ptr(), opts="auto",
+                                        stream=torch.cuda.current_stream().cuda_stream)
+    got = out.cpu().numpy().view(np.uint32)
+    exp = EXPECTED["plain_large"]["1"]
+    assert res["num_blocks"] == exp["num_blocks"]
+    assert digest(got) == exp["sha"]
+
+
+@pytest.mark.parametrize("closure", ["auto", "on"])
+def test_batch_mixed_full_size(ctx, closure):
+    """4,096 uneven DFAs (75% random, 25% permuted chains) in one batched call."""
+    from paper_2410_22764_amd import dfamin
+    print(f"[case] batch_mixed seed 1 closure={closure}", flush=True)
+    batch = W.batch_mixed(seed=1)
+    outs, results = dfamin.dfamin_minimize_batch(ctx, batch, {"closure": closure})
+    exp = EXPECTED["batch_mixed"]["1"]
+    assert len(exp) == len(batch) == 4096
+    for d, o, r, e in zip(batch, outs, results, exp):
+        assert (d.n, d.k) == (e["n"], e["k"])
+        assert r["num_blocks"] == e["num_blocks"], d.name
+        assert digest(o) == e["sha"], d.name
+
+
+def test_plain_single_seeds(ctx):
+    from paper_2410_22764_amd import dfamin
+    for seed, e in EXPECTED["plain_single"].items():
+        d = W.plain_single(int(seed))
+        out, res = dfamin.dfamin_minimize(ctx, d, "auto")
+        assert res["num_blocks"] == e["num_blocks"] and digest(out) == e["sha"]
+        assert res["refine_rounds"] == e["refine_rounds"]
