@@ -31,6 +31,7 @@ WORKLOADS = {
                          desc="random complete DFA, n=16384, |Sigma|=2, uniform delta, Bernoulli(0.5) accepting"),
     "deep_chain": dict(kind="chain", n=1 << 20, k=2, closure="on",
                        desc="chain DFA, n=2^20, |Sigma|=2 (second letter the identity), closure on"),
+    "serving": dict(kind="serving", desc="Poisson request stream"),
 }
 
 
@@ -91,6 +92,123 @@ def cpu_baseline(spec, seed, budget_s=20.0):
             "sample": f"Hopcroft (C, 1 thread) on {d.name}, {reps} run(s), {wall:.2f} s each"}
 
 
+def upload_batch(dfas, dev):
+    """Device copies of a list of DFAs: one flat int32 tensor for every delta,
+    one uint8 tensor for every bitmap; returns specs of device pointers."""
+    import numpy as np
+    import torch
+    dsz = sum(d.n * d.k for d in dfas)
+    asz = sum(-(-d.n // 8) + 8 for d in dfas)
+    flat_d = np.empty(dsz, np.uint32)
+    flat_a = np.zeros(asz, np.uint8)
+    offs = []
+    od = oa = 0
+    for d in dfas:
+        flat_d[od:od + d.n * d.k] = d.delta
+        flat_a[oa:oa + d.accept.size] = d.accept
+        offs.append((od, oa))
+        od += d.n * d.k
+        oa += -(-d.n // 8) + 8
+    td = torch.from_numpy(flat_d.view(np.int32)).to(dev)
+    ta = torch.from_numpy(flat_a).to(dev)
+    to = torch.empty(sum(d.n for d in dfas), dtype=torch.int32, device=dev)
+    specs, outs = [], []
+    oo = 0
+    for d, (od, oa) in zip(dfas, offs):
+        specs.append((d.n, d.k, td.data_ptr() + 4 * od, ta.data_ptr() + oa, d.q0))
+        outs.append(to.data_ptr() + 4 * oo)
+        oo += d.n
+    return specs, outs, (td, ta, to)
+
+
+def batched_vs_plain(ctx, seed=1, reps=3):
+    """Batched workload: 4,096 uneven DFAs in one call vs. one call per DFA."""
+    import torch
+    from paper_2410_22764_amd import dfamin, workloads as W
+    print("[bench] batch: generating 4096 DFAs", file=sys.stderr, flush=True)
+    batch = W.batch_mixed(seed=seed)
+    dev = torch.device("cuda:0")
+    specs, outs, keep = upload_batch(batch, dev)
+    stream = torch.cuda.current_stream().cuda_stream
+    trans = sum(d.n * d.k for d in batch)
+    opts = {"closure": "auto"}
+    dfamin.dfamin_minimize_batch_device(ctx, specs, outs, opts, stream)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        dfamin.dfamin_minimize_batch_device(ctx, specs, outs, opts, stream)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    print("[bench] batch: plain per-instance loop", file=sys.stderr, flush=True)
+    for sp, o in zip(specs[:64], outs[:64]):  # warm-up
+        dfamin.dfamin_minimize_device(ctx, *sp, o, opts=opts, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for sp, o in zip(specs, outs):
+        dfamin.dfamin_minimize_device(ctx, *sp, o, opts=opts, stream=stream)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    return {"workload": "batch_mixed: 4096 DFAs, n log-uniform in [64, 65536], |Sigma| in 2..8, "
+                        "25% permuted chains, seed 1, closure auto",
+            "transitions": trans, "batched_ms": round(1e3 * tb, 3), "plain_loop_ms": round(1e3 * tp, 3),
+            "batched_value": trans / tb, "plain_loop_value": trans / tp, "ratio": round(tp / tb, 2)}
+
+
+def serving_run(ctx, seed, count, pool_size, load, threads=64):
+    """Serving workload: Poisson arrivals of minimization requests at `load`
+    times the saturation throughput measured on the same request pool."""
+    import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
+    from paper_2410_22764_amd import dfamin, workloads as W
+    print(f"[bench] serving: generating a pool of {pool_size} requests", file=sys.stderr, flush=True)
+    _, specs = W.serving_stream(seed, pool_size, 1.0)
+    pool = [W.make_request(sp) for sp in specs]
+    opts = {"closure": "auto"}
+    # saturation: submit the whole pool at once, closed loop
+    print("[bench] serving: saturation", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ts = [dfamin.dfamin_submit(ctx, d, opts) for d in pool]
+    for d, t in zip(pool, ts):
+        rc, _, _ = dfamin.dfamin_wait(ctx, t, d.n)
+        assert rc == 0
+    sat = len(pool) / (time.perf_counter() - t0)
+    rate = load * sat
+    arrivals, _ = W.serving_stream(seed + 1, count, rate)
+    order = W.uniform_below(W.stream_key(seed, "serve", "order"), count, pool_size)
+    lat = [0.0] * count
+    print(f"[bench] serving: {count} requests at {rate:.1f}/s", file=sys.stderr, flush=True)
+
+    def waiter(i, t, n, t_arr):
+        rc, _, _ = dfamin.dfamin_wait(ctx, t, n)
+        assert rc == 0
+        lat[i] = time.perf_counter() - t_arr
+
+    ex = ThreadPoolExecutor(max_workers=threads)
+    futs = []
+    start = time.perf_counter()
+    for i in range(count):
+        target = start + arrivals[i]
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            time.sleep(min(target - now, 0.001))
+        d = pool[int(order[i])]
+        t_arr = time.perf_counter()
+        t = dfamin.dfamin_submit(ctx, d, opts)
+        futs.append(ex.submit(waiter, i, t, d.n, t_arr))
+    for f in futs:
+        f.result()
+    wall = time.perf_counter() - start
+    ex.shutdown()
+    trans = sum(pool[int(o)].transitions for o in order)
+    return {"requests": count, "pool": pool_size, "offered_rate_per_s": round(rate, 2),
+            "saturation_dfas_per_s": round(sat, 2), "load": load, "dfas_per_s": round(count / wall, 2),
+            "transitions_per_s": trans / wall,
+            "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                           "p99": round(1e3 * float(np.percentile(lat, 99)), 3)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,6 +218,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event kernel timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--requests", type=int, default=400, help="serving: measured requests")
+    ap.add_argument("--pool", type=int, default=128, help="serving: distinct pre-generated requests")
+    ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / saturation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -124,6 +246,20 @@ def main():
     import numpy as np
     import torch
     from paper_2410_22764_amd import dfamin
+
+    if args.workload == "serving":
+        ctx = dfamin.dfamin_create(0)
+        res = serving_run(ctx, args.seed, args.requests, args.pool, args.load)
+        ctx.close()
+        line = {"metric": METRIC, "value": res["transitions_per_s"], "unit": "transitions/s", "n_gpus": 1,
+                "steps": args.requests, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+                "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+                "config": {"workload": "serving: Poisson stream, n log-uniform in [2^8, 2^22], |Sigma| in "
+                                       "2..16, 20% permuted chains, closure auto", "seed": args.seed,
+                           "parallelism": "single GPU"},
+                "serving": res}
+        print(json.dumps(line), flush=True)
+        return
 
     spec = WORKLOADS[args.workload]
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
@@ -173,6 +309,9 @@ def main():
                     "traffic": load_traffic(top["name"], args.workload),
                     "avg_launch_us": round(per_launch_ms * 1e3, 2),
                     "alg_bytes_per_launch": round(per_launch_bytes)}
+    batched = None
+    if not args.no_batch and args.workload == "plain_large":
+        batched = batched_vs_plain(ctx, args.seed)
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -193,6 +332,7 @@ def main():
         "kernels": [{"name": s["name"], "launches": s["launches"], "ms": round(s["total_ms"], 4),
                      "GBps": round(s["alg_bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1) if s["total_ms"] > 0 else None}
                     for s in stats],
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     ctx.close()

@@ -62,9 +62,10 @@ typedef unsigned long long Slot;
 constexpr uint32_t kSlotShared = 0x80000000u;
 constexpr uint32_t kSlotIndexMask = 0x7fffffffu;
 
-// Control block shared by the round kernels and read by the host.  Words
-// that workgroups update concurrently are only ever touched with device
-// atomics; the tile counter lives on its own 128-byte line.
+// Control block shared by the round kernels and read by the host.  The flags
+// only go from 0 to 1 within a kernel (plain stores of one value); the tile
+// counter and m_next are updated with device atomics and the tile counter
+// lives on its own 128-byte line.
 struct Ctrl {
   uint32_t any_changed;   // some block split this round
   uint32_t collision;     // two different signatures shared a hash this round

@@ -330,8 +330,8 @@ __global__ __launch_bounds__(kBlock) void k_init_block(const InstDesc* __restric
 __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table, uint64_t tsize,
                                                         Ctrl* __restrict__ ctrl) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    atomicExch(&ctrl->any_changed, 0u);
-    atomicExch(&ctrl->collision, 0u);
+    ctrl->any_changed = 0u;
+    ctrl->collision = 0u;
   }
   const uint64_t stride = (uint64_t)gridDim.x * kBlock * 2;
   for (uint64_t s = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2; s < tsize; s += stride) {
@@ -537,10 +537,13 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
     nb[j] = rep;
     keep[j] = (w & kSlotShared) ? 1 : 0;
   }
+  // Flags only ever go from 0 to 1 inside this kernel: plain stores of the
+  // same value, made visible to the next kernel by the kernel boundary (a
+  // device atomic per wave would serialize ~m/64 operations on one word).
   const bool any_changed = __any(changed), any_coll = __any(coll);
   if ((threadIdx.x & 63u) == 0) {
-    if (any_changed) atomicOr(&ctrl->any_changed, 1u);
-    if (any_coll) atomicOr(&ctrl->collision, 1u);
+    if (any_changed) ctrl->any_changed = 1u;
+    if (any_coll) ctrl->collision = 1u;
   }
 }
 
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   __shared__ uint32_t s_cnt[kScanItems * 4];
   if (threadIdx.x == 0) {
     s_tile = atomicAdd(&ctrl->tile_counter, 1u);
-    s_coll = __hip_atomic_load(&ctrl->collision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_coll = ctrl->collision;
   }
   __syncthreads();
   const uint32_t tile = s_tile;
@@ -606,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
                                                       const Ctrl* __restrict__ ctrl) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= ninst) return;
-  const uint32_t coll = __hip_atomic_load(&ctrl->collision, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const uint32_t coll = ctrl->collision;
   if (last) last[i] = coll ? 0u : changed_inst[i];
   if (changed_inst[i]) {
     if (!coll) refine_cnt[i] += 1u;
