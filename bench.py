@@ -31,6 +31,9 @@ WORKLOADS = {
                          desc="random complete DFA, n=16384, |Sigma|=2, uniform delta, Bernoulli(0.5) accepting"),
     "deep_chain": dict(kind="chain", n=1 << 20, k=2, closure="on",
                        desc="chain DFA, n=2^20, |Sigma|=2 (second letter the identity), closure on"),
+    "batch_mixed": dict(kind="batch", closure="auto",
+                        desc="4096 DFAs, n log-uniform in [64, 65536], |Sigma| in 2..8, 25% permuted chains, "
+                             "closure auto, one batched call per step"),
     "serving": dict(kind="serving", desc="Poisson request stream"),
 }
 
@@ -72,20 +75,19 @@ def cpu_baseline(spec, seed, budget_s=20.0):
     kind of input, scaled to transitions/s."""
     import oracle
     from paper_2410_22764_amd import workloads as W
-    n = spec["n"]
-    # shrink the sample until one oracle run fits the budget (~n log n)
+    n = spec.get("n", 0)
     if spec["kind"] == "random":
-        sample_n = min(n, 1 << 22)
-        d = W.random_dfa(sample_n, spec["k"], seed)
+        d = W.random_dfa(min(n, 1 << 22), spec["k"], seed)
+    elif spec["kind"] == "batch":
+        d = W.random_dfa(1 << 20, 5, seed)  # mean |Sigma| of the batch
     else:
-        sample_n = n
         d = W.chain_dfa(n, spec["k"])
     t0 = time.perf_counter()
     reps = 0
     while True:
         oracle.hopcroft(d.n, d.k, d.delta, d.accept)
         reps += 1
-        if time.perf_counter() - t0 > min(budget_s, 1.0) or reps >= 3:
+        if time.perf_counter() - t0 > budget_s / 2 or reps >= 5:
             break
     wall = (time.perf_counter() - t0) / reps
     return {"value": d.n * d.k / wall, "unit": "transitions/s", "cores": 1, "kind": "oracle",
@@ -218,7 +220,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event kernel timing")
-    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain and end-to-end legs")
     ap.add_argument("--requests", type=int, default=400, help="serving: measured requests")
     ap.add_argument("--pool", type=int, default=128, help="serving: distinct pre-generated requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / saturation")
@@ -263,19 +265,38 @@ def main():
 
     spec = WORKLOADS[args.workload]
     print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
-    d = make_input(spec, args.seed)
     dev = torch.device("cuda:0")
-    delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
-    accept = torch.from_numpy(d.accept).to(dev)
-    out = torch.empty(d.n, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
     ctx = dfamin.dfamin_create(0)
     opts = dict(closure=spec["closure"])
+    if spec["kind"] == "batch":
+        from paper_2410_22764_amd import workloads as W
+        batch = W.batch_mixed(seed=args.seed)
+        specs, outs, keep = upload_batch(batch, dev)
+        trans = sum(x.n * x.k for x in batch)
+        cfg = {"workload": f"{args.workload}: {spec['desc']}", "instances": len(batch),
+               "states": sum(x.n for x in batch), "transitions": trans, "seed": args.seed,
+               "closure": spec["closure"], "parallelism": "single GPU"}
 
-    def step():
-        return dfamin.dfamin_minimize_device(ctx, d.n, d.k, delta.data_ptr(), accept.data_ptr(), d.q0,
-                                             out.data_ptr(), opts=opts, stream=stream.cuda_stream)
+        def step():
+            rs = dfamin.dfamin_minimize_batch_device(ctx, specs, outs, opts, stream.cuda_stream)
+            return {"num_blocks": sum(r["num_blocks"] for r in rs),
+                    "refine_rounds": max(r["refine_rounds"] for r in rs),
+                    "rounds_executed": max(r["rounds_executed"] for r in rs),
+                    "closure_levels": max(r["closure_levels"] for r in rs)}
+    else:
+        d = make_input(spec, args.seed)
+        delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+        accept = torch.from_numpy(d.accept).to(dev)
+        out = torch.empty(d.n, dtype=torch.int32, device=dev)
+        trans = d.n * d.k
+        cfg = {"workload": f"{args.workload}: {spec['desc']}", "n": d.n, "k": d.k, "seed": args.seed,
+               "closure": spec["closure"], "parallelism": "single GPU"}
+
+        def step():
+            return dfamin.dfamin_minimize_device(ctx, d.n, d.k, delta.data_ptr(), accept.data_ptr(), d.q0,
+                                                 out.data_ptr(), opts=opts, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
 
     print("[bench] warmup", file=sys.stderr, flush=True)
     res = None
@@ -296,7 +317,20 @@ def main():
     stats = dfamin.dfamin_get_kernel_stats(ctx) if not args.no_profile else []
     dfamin.dfamin_set_profiling(ctx, False)
     ms = 1e3 * wall / args.steps
-    value = d.n * d.k / (wall / args.steps)
+    value = trans / (wall / args.steps)
+
+    end_to_end = None
+    if spec["kind"] != "batch" and not args.no_batch:
+        # host buffers in and out: pageable -> pinned staging -> device and back
+        print("[bench] end-to-end (host buffers)", file=sys.stderr, flush=True)
+        dfamin.dfamin_minimize(ctx, d, opts)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            dfamin.dfamin_minimize(ctx, d, opts)
+        te = (time.perf_counter() - t0) / reps
+        end_to_end = {"value": trans / te, "unit": "transitions/s", "ms_per_step": round(1e3 * te, 3),
+                      "note": "host-resident input and output, PCIe transfers included"}
 
     roofline = None
     if stats:
@@ -322,8 +356,7 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {spec['desc']}", "n": d.n, "k": d.k, "seed": args.seed,
-                   "closure": spec["closure"], "parallelism": "single GPU"},
+        "config": cfg,
         "latency_ms": {"p50": round(1e3 * statistics.median(lat), 4),
                        "p99": round(1e3 * float(np.percentile(lat, 99)), 4)},
         "result": {"num_blocks": res["num_blocks"], "refine_rounds": res["refine_rounds"],
@@ -332,6 +365,7 @@ def main():
         "kernels": [{"name": s["name"], "launches": s["launches"], "ms": round(s["total_ms"], 4),
                      "GBps": round(s["alg_bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1) if s["total_ms"] > 0 else None}
                     for s in stats],
+        "end_to_end": end_to_end,
         "batched": batched,
         "cpu_baseline": cpu,
     }

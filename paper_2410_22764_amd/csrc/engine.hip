@@ -23,6 +23,12 @@ namespace dfamin {
 
 namespace {
 
+inline uint32_t floor_log2_u64(uint64_t x) {
+  uint32_t l = 0;
+  while (x >> 1) { x >>= 1; ++l; }
+  return l;
+}
+
 inline uint32_t ceil_log2_u64(uint64_t x) {
   uint32_t b = 0;
   while ((1ull << b) < x) ++b;
@@ -115,7 +121,7 @@ Engine::~Engine() {
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
                     &d_results_, &d_ctrl_, &d_closure_, &d_wgflags_, &d_part_, &d_dense_,
-                    &d_counts_};
+                    &d_counts_, &d_djobs_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_};
@@ -128,7 +134,7 @@ uint64_t Engine::device_bytes() const {
                           &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
                           &d_results_, &d_ctrl_, &d_closure_, &d_wgflags_, &d_part_, &d_dense_,
-                          &d_counts_};
+                          &d_counts_, &d_djobs_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   return t;
@@ -195,8 +201,10 @@ int Engine::upload_layout(hipStream_t s) {
   const size_t I = in_.size();
   rows_.clear();
   uint64_t sig_words = 0;
+  row_base_.assign(I, 0);
   for (size_t i = 0; i < I; ++i) {
     desc_[i].rows_off = (uint32_t)rows_.size();
+    row_base_[i] = desc_[i].rows_off;
     desc_[i].kp = (uint32_t)inst_rows_[i].size();
     rows_.insert(rows_.end(), inst_rows_[i].begin(), inst_rows_[i].end());
     desc_[i].sig = sig_words;  // word offset for now, made absolute below
@@ -292,7 +300,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   uint64_t N = 0;
   uint32_t nmax = 0;
   for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
-  if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // active indices are 31-bit in hash slots
+  if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
   N_ = N;
   closure_used_ = 0;
   Profiler& prof = ctx_->prof;
@@ -439,80 +447,147 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   uint64_t salt = 0x5DEECE66Dull;
   int retries = 0;
   uint64_t rounds = 0;
-  auto avg_kp = [&]() {
-    // average signature letters per state, weighted by n (for byte counts)
+  int dense_width = 4;
+  // Algorithmic bytes per active state of the signature kernel, averaged
+  // over instances weighted by n: act [+ inst_of] + own key + per letter the
+  // delta' entry and the gathered key + the signature record (hash mode) +
+  // slot id + one slot update.  Keys are an accept bit (1 byte read), a
+  // dense number (dense_width bytes) or a block id (4 bytes).
+  auto sig_bytes = [&]() {
     double w = 0;
-    for (size_t i = 0; i < I; ++i) w += (double)desc_[i].n * desc_[i].kp;
+    for (size_t i = 0; i < I; ++i) {
+      const InstDesc& D = desc_[i];
+      const double key = D.ebits ? (D.dsrc ? 1.0 : (double)dense_width) : 4.0;
+      const double rec = D.ebits ? 0.0 : 4.0 * (D.kp + 1);
+      w += (double)D.n * (4.0 + (batch ? 4.0 : 0.0) + key + D.kp * (4.0 + key) + rec + 4.0 + 8.0);
+    }
     return N ? w / (double)N : 0.0;
   };
-  double kpbar = avg_kp();
+  // Per instance: still refining (every round so far split a block), and
+  // the length j of the Moore partition P_j it holds (P_j: states agree on
+  // all words of length <= j).  Unary instances that get the closure under
+  // AUTO refine by doubling: from P_j, the one letter a^t with t <= j+1
+  // gives exactly P_{j+t}, and a round that splits nothing proves P_j
+  // stable (P_j >= P_{j+1} >= P_{j+t} = P_j).  t is the largest closure
+  // level 2^l <= j+1, so each round gathers one successor instead of one
+  // per level.
+  std::vector<uint8_t> active(I, 1), dbl(I, 0);
+  std::vector<uint64_t> mj(I, 0), step(I, 1);
+  std::vector<uint32_t> cand, exact, jobv;
+  TRY(ensure(d_djobs_, 6 * I * 4 + 64));
   while (m > 0) {
     if (any_auto && rounds == auto_rounds) {
       // instances still refining after auto_rounds rounds get the closure
-      HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
-      HIP(hipStreamSynchronize(s));
-      const uint32_t* rc = h_results_.as<uint32_t>();
       std::vector<uint32_t> which;
       for (size_t i = 0; i < I; ++i)
-        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && rc[i] == rounds) which.push_back((uint32_t)i);
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && active[i]) which.push_back((uint32_t)i);
       if (!which.empty()) {
         TRY(build_closure(which, opts, s));
         TRY(upload_layout(s));
-        kpbar = avg_kp();
+        for (uint32_t i : which) dbl[i] = nonid_[i].size() == 1;
       }
     }
     if (rounds >= max_rounds) return DFAMIN_E_INTERNAL;
+    bool dirty = false;
+    // doubling instances: this round's single closure level
+    for (size_t i = 0; i < I; ++i) {
+      if (!dbl[i] || !active[i]) continue;
+      const uint32_t cnt = (uint32_t)inst_rows_[i].size();
+      uint32_t lvl = (uint32_t)floor_log2_u64(mj[i] + 1);
+      if (lvl > cnt - 1) lvl = cnt - 1;
+      step[i] = 1ull << lvl;
+      if (desc_[i].rows_off != row_base_[i] + lvl || desc_[i].kp != 1) {
+        desc_[i].rows_off = row_base_[i] + lvl;
+        desc_[i].kp = 1;
+        dirty = true;
+      }
+    }
     // Key mode per instance (see InstDesc): exact keys while
     // (kp+1) * ceil(log2 B) fits in 31 bits, B = blocks before this round.
-    {
-      bool need_dense = false, dirty = false;
-      auto decide = [&](bool exact_counts) {
-        need_dense = false;
-        for (size_t i = 0; i < I; ++i) {
-          const uint64_t kp1 = desc_[i].kp + 1ull;
-          uint32_t eb = 0, ds = 0;
-          if (rounds == 0) {
-            if (kp1 <= 31) { eb = 1; ds = 1; }
-          } else {
-            const uint64_t B = exact_counts ? std::max<uint64_t>(h_counts_.as<uint32_t>()[i], 1) : ub[i];
-            const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
-            if (kp1 * bits <= 31) { eb = bits; need_dense = true; }
-          }
-          if (desc_[i].ebits != eb || desc_[i].dsrc != ds) {
-            desc_[i].ebits = eb;
-            desc_[i].dsrc = ds;
-            dirty = true;
-          }
-        }
-      };
-      decide(false);
-      if (need_dense) {
-        // exact block counts and dense numbers from a scan over all states
-        const uint32_t nt = (uint32_t)((N + kScanTile - 1) / kScanTile);
-        launch_prep_scan(d_status_.as<unsigned long long>(), nt, d_ctrl_.as<Ctrl>(), s);
-        prof.begin(s, "scan_reps", 8.0 * (double)N);
-        launch_scan_reps(d_block_.as<uint32_t>(), (uint32_t)N, d_rank_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                         d_status_.as<unsigned long long>(), s);
-        prof.end(s);
-        launch_block_counts((uint32_t)I, d_desc_.as<InstDesc>(), d_rank_.as<uint32_t>(),
-                            d_counts_.as<uint32_t>(), s);
-        HIP(hipGetLastError());
-        HIP(hipMemcpyAsync(h_counts_.p, d_counts_.p, I * 4, hipMemcpyDeviceToHost, s));
-        HIP(hipStreamSynchronize(s));
-        prof.collect();
-        for (size_t i = 0; i < I; ++i) ub[i] = std::max<uint64_t>(h_counts_.as<uint32_t>()[i], 1);
-        decide(true);
-        if (need_dense) {
-          TRY(ensure(d_dense_, N * 4));
-          prof.begin(s, "dense", (12.0 + (batch ? 4.0 : 0.0)) * (double)N);
-          launch_dense(batch, (uint32_t)N, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-                       d_block_.as<uint32_t>(), d_rank_.as<uint32_t>(), d_dense_.as<uint32_t>(), s);
-          prof.end(s);
+    // Only instances still refining matter; their exact block counts and
+    // dense numbers come from a segmented scan over their own states.
+    cand.clear();
+    for (size_t i = 0; i < I; ++i) {
+      const uint64_t kp1 = desc_[i].kp + 1ull;
+      uint32_t eb = 0, ds = 0;
+      if (active[i]) {
+        if (rounds == 0) {
+          if (kp1 <= 31) { eb = 1; ds = 1; }
+        } else if (kp1 * std::max<uint32_t>(1, ceil_log2_u64(ub[i])) <= 31) {
+          cand.push_back((uint32_t)i);
+          continue;  // decided below from the exact count
         }
       }
-      if (dirty)
-        HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+      if (desc_[i].ebits != eb || desc_[i].dsrc != ds) {
+        desc_[i].ebits = eb;
+        desc_[i].dsrc = ds;
+        dirty = true;
+      }
     }
+    if (!cand.empty()) {
+      const uint32_t nj = (uint32_t)cand.size();
+      jobv.assign(3 * nj, 0);
+      uint32_t tiles = 0;
+      double states = 0;
+      for (uint32_t j = 0; j < nj; ++j) {
+        jobv[j] = cand[j];
+        jobv[nj + j] = tiles;
+        tiles += (in_[cand[j]].n + kScanTile - 1) / kScanTile;
+        states += in_[cand[j]].n;
+      }
+      TRY(ensure(d_status_, ((size_t)tiles + 1) * 8));
+      uint32_t* dj = d_djobs_.as<uint32_t>();
+      HIP(hipMemcpyAsync(dj, jobv.data(), 2 * nj * 4, hipMemcpyHostToDevice, s));
+      launch_prep_scan(d_status_.as<unsigned long long>(), tiles, d_ctrl_.as<Ctrl>(), s);
+      prof.begin(s, "scan_jobs", 8.0 * states);
+      launch_scan_jobs(d_desc_.as<InstDesc>(), dj, dj + nj, nj, tiles, d_block_.as<uint32_t>(),
+                       d_rank_.as<uint32_t>(), d_counts_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                       d_status_.as<unsigned long long>(), s);
+      prof.end(s);
+      HIP(hipGetLastError());
+      HIP(hipMemcpyAsync(h_counts_.p, d_counts_.p, nj * 4, hipMemcpyDeviceToHost, s));
+      HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+      HIP(hipStreamSynchronize(s));
+      prof.collect();
+      if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
+      exact.clear();
+      uint32_t eb_max = 0;
+      for (uint32_t j = 0; j < nj; ++j) {
+        const uint32_t i = cand[j];
+        const uint64_t B = std::max<uint64_t>(h_counts_.as<uint32_t>()[j], 1);
+        ub[i] = B;
+        const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
+        const uint32_t eb = ((desc_[i].kp + 1ull) * bits <= 31) ? bits : 0u;
+        if (eb) { exact.push_back(i); eb_max = std::max(eb_max, eb); }
+        if (desc_[i].ebits != eb || desc_[i].dsrc != 0) {
+          desc_[i].ebits = eb;
+          desc_[i].dsrc = 0;
+          dirty = true;
+        }
+      }
+      if (!exact.empty()) {
+        dense_width = eb_max <= 8 ? 1 : (eb_max <= 16 ? 2 : 4);
+        const uint32_t ne = (uint32_t)exact.size();
+        uint32_t* dj2 = dj + 2 * nj;
+        jobv.assign(2 * ne, 0);
+        uint32_t wgs = 0;
+        double es = 0;
+        for (uint32_t j = 0; j < ne; ++j) {
+          jobv[j] = exact[j];
+          jobv[ne + j] = wgs;
+          wgs += (in_[exact[j]].n + kRowTile - 1) / kRowTile;
+          es += in_[exact[j]].n;
+        }
+        TRY(ensure(d_dense_, N * 4));
+        HIP(hipMemcpyAsync(dj2, jobv.data(), 2 * ne * 4, hipMemcpyHostToDevice, s));
+        prof.begin(s, "dense", (8.0 + dense_width) * es);
+        launch_dense_jobs(d_desc_.as<InstDesc>(), dj2, dj2 + ne, ne, wgs, d_block_.as<uint32_t>(),
+                          d_rank_.as<uint32_t>(), d_dense_.p, dense_width, s);
+        prof.end(s);
+      }
+    }
+    if (dirty)
+      HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
     const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * m));
     const uint64_t tsize = 1ull << tbits;
     TRY(ensure(d_table_, tsize * sizeof(Slot)));
@@ -523,9 +598,9 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     prof.begin(s, "clear_table", 8.0 * (double)tsize);
     launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
     prof.end(s);
-    prof.begin(s, "signature", md * (4 + inst_b + 4 + 8 * kpbar + 4 * (kpbar + 1) + 4 + 8));
+    prof.begin(s, "signature", md * sig_bytes());
     launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.as<uint32_t>(),
+                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
                      d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt,
                      d_ctrl_.as<Ctrl>(), s);
     prof.end(s);
@@ -545,6 +620,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
                      d_ctrl_.as<Ctrl>(), s);
     HIP(hipGetLastError());
     HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
     HIP(hipStreamSynchronize(s));
     prof.collect();
     const Ctrl c = *h_ctrl_.as<Ctrl>();
@@ -559,11 +635,15 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
       continue;
     }
     ++rounds;
+    const uint32_t* rc = h_results_.as<uint32_t>();
     for (size_t i = 0; i < I; ++i) {
+      if (!active[i]) continue;
       // a round maps each block to at most B^(kp+1) signatures
       const uint64_t kp1 = desc_[i].kp + 1ull;
       const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(ub[i]));
       ub[i] = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
+      mj[i] += dbl[i] ? step[i] : 1;
+      active[i] = rc[i] == rounds;
     }
     std::swap(cur, nxt);
     m = c.m_next;

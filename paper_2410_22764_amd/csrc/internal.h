@@ -20,7 +20,7 @@
 namespace dfamin {
 
 constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
-constexpr int kScanItems = 8;         // items per thread in scan / compaction tiles
+constexpr int kScanItems = 32;        // items per thread in scan / compaction tiles
 constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kSigItems = 2;          // states per thread in the signature kernel
 constexpr int kSigTile = kBlock * kSigItems;
@@ -55,7 +55,7 @@ struct InstDesc {
 // Global hash-table slot: one 64-bit word, 0 = empty.
 //   bits 63..32  fragment of the signature hash (never 0)
 //   bit  31      shared: at least two active states carry this hash
-//   bits 30..0   least active-list index carrying this hash
+//   bits 30..0   least (global) state id carrying this hash: the new block id
 // The home position comes from the low hash bits, the fragment from the high
 // ones.  A slot is claimed, joined and lowered with 64-bit CAS only.
 typedef unsigned long long Slot;
@@ -120,14 +120,18 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
                        uint32_t total_wgs, const uint32_t* minF, const uint32_t* minN,
                        uint32_t* inst_of, uint32_t* block, uint32_t* act, hipStream_t s);
 void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s);
+// dense / dense_width: dense block numbers (exact-key rounds that read them),
+// stored dense_width (1, 2 or 4) bytes per state.
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
-                      const uint32_t* dense, Slot* table, uint32_t tbits, uint32_t* slot_of,
-                      uint64_t salt, Ctrl* ctrl, hipStream_t s);
+                      const void* dense, int dense_width, Slot* table, uint32_t tbits,
+                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, hipStream_t s);
 // dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
-// instance's blocks in order of least member.
+// instance's blocks in order of least member, dense_width bytes wide (every
+// number must fit).
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
-                  const uint32_t* block, const uint32_t* rank, uint32_t* dense, hipStream_t s);
+                  const uint32_t* block, const uint32_t* rank, void* dense, int dense_width,
+                  hipStream_t s);
 // counts[i] = number of blocks of instance i (from rank).
 void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
                          uint32_t* counts, hipStream_t s);
@@ -143,7 +147,7 @@ void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
                     unsigned long long* scan_status, hipStream_t s);
 // last (nullable) receives this round's per-instance changed flags.
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
-                      const Ctrl* ctrl, hipStream_t s);
+                      Ctrl* ctrl, hipStream_t s);
 // Instances joining a running set: like launch_init_block, with instance
 // ids slot[j] for job j and their states appended to act at act_off[j].
 void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
@@ -163,6 +167,12 @@ void launch_scan_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t
 void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
                       uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
                       hipStream_t s);
+// dense[g] = rank[block[g]] (instance-relative ranks from launch_scan_jobs)
+// for the states of the listed instances, dense_width bytes wide;
+// job_wg_off: kRowTile-state workgroups per job, prefix.
+void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                       uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
+                       void* dense, int dense_width, hipStream_t s);
 void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,
                          const uint32_t* totals, const uint32_t* refine_cnt, ResultDev* res,
                          hipStream_t s);

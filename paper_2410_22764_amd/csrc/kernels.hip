@@ -45,6 +45,15 @@ __device__ __forceinline__ uint64_t hash_final(uint64_t h) {
   return h ? h : 1ull;  // 0 marks an empty LDS slot
 }
 
+// Dense block numbers are stored 1, 2 or 4 bytes wide: narrower arrays keep
+// more of the random successor gathers in L2 / the memory-side cache.
+template <int DW>
+__device__ __forceinline__ uint32_t dense_at(const void* __restrict__ d, uint64_t idx) {
+  if constexpr (DW == 1) return static_cast<const uint8_t*>(d)[idx];
+  else if constexpr (DW == 2) return static_cast<const uint16_t*>(d)[idx];
+  else return static_cast<const uint32_t*>(d)[idx];
+}
+
 __device__ __forceinline__ unsigned long long load_status(unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -340,17 +349,21 @@ __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table
   }
 }
 
-// Insert a local group (least index j, `shared` if it already has two
-// members) into the global table; returns the slot.  The plain load is a
-// shortcut only: a stale value just leads to a CAS that returns the current
-// one, and slot words change monotonically (claimed once, index only
-// lowered, shared bit only set).
+// Insert a local group (least member g, a global state id, `shared` if it
+// already has two members) into the global table; returns the slot.  A slot
+// belongs to one instance: its least member lies in [lo, hi), the inserting
+// instance's state range, or the slot holds another instance's key and the
+// probe moves on.  So exact keys (the same small numbers in every instance)
+// never merge across instances.  The plain load is a shortcut only: a stale
+// value just leads to a CAS that returns the current one, and slot words
+// change monotonically (claimed once, index only lowered within the same
+// instance, shared bit only set).
 __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint64_t mask, uint64_t h,
-                                                 uint32_t frag, uint32_t j, bool shared,
-                                                 Ctrl* __restrict__ ctrl) {
+                                                 uint32_t frag, uint32_t g, bool shared, uint32_t lo,
+                                                 uint32_t hi, Ctrl* __restrict__ ctrl) {
   uint64_t p = h & mask;
   const unsigned long long mine =
-      ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)j;
+      ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)g;
   for (uint64_t probes = 0; probes <= mask; ++probes) {
     unsigned long long cur = table[p];
     while (true) {
@@ -360,10 +373,11 @@ __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint6
         cur = prev;
         continue;
       }
-      if ((uint32_t)(cur >> 32) != frag) break;  // another key: next slot
-      const uint32_t lo = (uint32_t)cur;
-      const uint32_t want_lo = min(lo & kSlotIndexMask, j) | kSlotShared;
-      if (want_lo == lo) return (uint32_t)p;
+      const uint32_t cw = (uint32_t)cur;
+      const uint32_t cg = cw & kSlotIndexMask;
+      if ((uint32_t)(cur >> 32) != frag || cg < lo || cg >= hi) break;  // another key: next slot
+      const uint32_t want_lo = min(cg, g) | kSlotShared;
+      if (want_lo == cw) return (uint32_t)p;
       const unsigned long long want = (cur & 0xffffffff00000000ull) | want_lo;
       const unsigned long long prev = atomicCAS(&table[p], cur, want);
       if (prev == cur) return (uint32_t)p;
@@ -381,11 +395,11 @@ __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint6
 // (slot id) + 8 (one hash-slot update per local group, upper bound).  Exact
 // mode: the same without the record, with dense numbers (or accept bits)
 // gathered instead of block ids.
-template <bool BATCH>
+template <bool BATCH, int DW>
 __global__ __launch_bounds__(kBlock) void k_signature(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
-    const uint32_t* __restrict__ block, const uint32_t* __restrict__ dense,
+    const uint32_t* __restrict__ block, const void* __restrict__ dense,
     Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
     Ctrl* __restrict__ ctrl) {
   __shared__ unsigned long long lkey[kLocalSlots];
@@ -397,29 +411,34 @@ __global__ __launch_bounds__(kBlock) void k_signature(
   }
   __syncthreads();
   uint64_t h[kSigItems];
-  uint32_t frag[kSigItems], lp[kSigItems], jj[kSigItems];
+  uint32_t frag[kSigItems], lp[kSigItems], jj[kSigItems], gg[kSigItems], glo[kSigItems], ghi[kSigItems];
   bool valid[kSigItems];
 #pragma unroll
   for (int e = 0; e < kSigItems; ++e) {
     const uint32_t j = blockIdx.x * kSigTile + e * kBlock + threadIdx.x;
     jj[e] = j;
+    gg[e] = 0;
+    glo[e] = 0;
+    ghi[e] = 0;
     valid[e] = j < m;
     h[e] = 0;
     frag[e] = 0;
     lp[e] = 0;
     if (!valid[e]) continue;
     const uint32_t g = act[j];
+    gg[e] = g;
     const uint32_t i = BATCH ? inst_of[g] : 0u;
     const InstDesc D = desc[i];
     const uint32_t q = g - D.state_off;
+    glo[e] = D.state_off;
+    ghi[e] = D.state_off + D.n;
     const uint32_t kp = D.kp;
     const uint64_t* __restrict__ R = rows + D.rows_off;
     unsigned long long lk;  // local grouping key (exact key + 1, or the hash)
     if (D.ebits) {
       // exact key: own dense number, then one per letter, ebits each
       const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
-      const uint32_t* __restrict__ dn = dense + D.state_off;
-      uint32_t key = D.dsrc ? ((acc[q >> 3] >> (q & 7)) & 1u) : dn[q];
+      uint32_t key = D.dsrc ? ((acc[q >> 3] >> (q & 7)) & 1u) : dense_at<DW>(dense, g);
       uint32_t shift = D.ebits;
       for (uint32_t r0 = 0; r0 < kp; r0 += 8) {
         const uint32_t cnt = (kp - r0) < 8u ? (kp - r0) : 8u;
@@ -429,7 +448,9 @@ __global__ __launch_bounds__(kBlock) void k_signature(
           if (t < cnt) s[t] = reinterpret_cast<const uint32_t*>(R[r0 + t])[q];
 #pragma unroll
         for (uint32_t t = 0; t < 8; ++t)
-          if (t < cnt) b[t] = D.dsrc ? ((acc[s[t] >> 3] >> (s[t] & 7)) & 1u) : dn[s[t]];
+          if (t < cnt)
+            b[t] = D.dsrc ? ((acc[s[t] >> 3] >> (s[t] & 7)) & 1u)
+                          : dense_at<DW>(dense, (uint64_t)D.state_off + s[t]);
 #pragma unroll
         for (uint32_t t = 0; t < 8; ++t)
           if (t < cnt) {
@@ -438,9 +459,8 @@ __global__ __launch_bounds__(kBlock) void k_signature(
           }
       }
       // Keys are numbers within one instance: the instance joins the local
-      // key and the home position.  Two instances that still meet in a
-      // global slot are caught by k_resolve (least member outside the
-      // instance) and the round is redone with another salt.
+      // key and the home position, and a global slot is only joined by
+      // states of the instance that claimed it (table_insert).
       frag[e] = key + 1u;  // < 2^31 + 1, never 0
       h[e] = hash_final(hash_step(hash_step(salt ^ 0x13198A2E03707344ull, key), i));
       lk = ((unsigned long long)i << 32) | frag[e];
@@ -477,15 +497,15 @@ __global__ __launch_bounds__(kBlock) void k_signature(
       p = (p + 1) & (kLocalSlots - 1);
     }
     lp[e] = p;
-    atomicMin(&lmin[p], j);
+    atomicMin(&lmin[p], g);
     atomicAdd(&lcnt[p], 1u);
   }
   __syncthreads();
   const uint64_t mask = (1ull << tbits) - 1ull;
 #pragma unroll
   for (int e = 0; e < kSigItems; ++e) {
-    if (valid[e] && lmin[lp[e]] == jj[e])
-      lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], jj[e], lcnt[lp[e]] > 1u, ctrl);
+    if (valid[e] && lmin[lp[e]] == gg[e])
+      lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], gg[e], lcnt[lp[e]] > 1u, glo[e], ghi[e], ctrl);
   }
   __syncthreads();
 #pragma unroll
@@ -510,16 +530,15 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
   if (j < ntiles) store_status(&scan_status[j], 0ull);
   if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
   bool changed = false, coll = false;
+  uint32_t i = 0xffffffffu;
   if (j < m) {
     const uint32_t g = act[j];
-    const uint32_t i = BATCH ? inst_of[g] : 0u;
+    i = BATCH ? inst_of[g] : 0u;
     const uint32_t w = (uint32_t)table[slot_of[j]];
-    const uint32_t jmin = w & kSlotIndexMask;
-    uint32_t rep = g;
-    if (jmin != j) {
+    const uint32_t gc = w & kSlotIndexMask;  // least member of the group
+    const uint32_t rep = gc;
+    if (gc != g) {
       const InstDesc D = desc[i];
-      const uint32_t gc = act[jmin];
-      rep = gc;
       const uint32_t words = D.kp + 1;
       if (gc < D.state_off || gc - D.state_off >= D.n) {
         coll = true;  // the group's least member belongs to another instance
@@ -530,21 +549,20 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
         for (uint32_t t = 0; t < words; ++t) coll |= (r1[t] != r2[t]);
       }
     }
-    if (rep != block[g]) {
-      changed = true;
-      changed_inst[i] = 1u;
-    }
+    changed = rep != block[g];
     nb[j] = rep;
     keep[j] = (w & kSlotShared) ? 1 : 0;
   }
   // Flags only ever go from 0 to 1 inside this kernel: plain stores of the
-  // same value, made visible to the next kernel by the kernel boundary (a
-  // device atomic per wave would serialize ~m/64 operations on one word).
-  const bool any_changed = __any(changed), any_coll = __any(coll);
-  if ((threadIdx.x & 63u) == 0) {
-    if (any_changed) ctrl->any_changed = 1u;
-    if (any_coll) ctrl->collision = 1u;
-  }
+  // same value, made visible to the next kernel by the kernel boundary.  A
+  // wave stores each instance's flag once (its states are contiguous in the
+  // active list), so no word takes more than a few stores per wave.
+  const uint32_t lane = threadIdx.x & 63u;
+  const unsigned long long cm = __ballot(changed);
+  const int first = cm ? __builtin_ctzll(cm) : 0;
+  const uint32_t i0 = __shfl(i, first, 64);
+  if (changed && ((int)lane == first || i != i0)) changed_inst[i] = 1u;
+  if (__any(coll) && lane == 0) ctrl->collision = 1u;
 }
 
 // Apply the new ids and keep the states whose block is still shared and whose
@@ -606,12 +624,14 @@ __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
                                                       uint32_t* __restrict__ changed_inst,
                                                       uint32_t* __restrict__ refine_cnt,
                                                       uint32_t* __restrict__ last,
-                                                      const Ctrl* __restrict__ ctrl) {
+                                                      Ctrl* __restrict__ ctrl) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t ch = (i < ninst) ? changed_inst[i] : 0u;
+  if (__any(ch != 0u) && (threadIdx.x & 63u) == 0) ctrl->any_changed = 1u;
   if (i >= ninst) return;
   const uint32_t coll = ctrl->collision;
-  if (last) last[i] = coll ? 0u : changed_inst[i];
-  if (changed_inst[i]) {
+  if (last) last[i] = coll ? 0u : ch;
+  if (ch) {
     if (!coll) refine_cnt[i] += 1u;
     changed_inst[i] = 0u;
   }
@@ -691,17 +711,21 @@ __global__ __launch_bounds__(kBlock) void k_results(uint32_t ninst, const InstDe
   res[i] = r;
 }
 
-// Algorithmic bytes: 12 per state (block, gathered rank, dense write; +4 inst_of).
-template <bool BATCH>
+// Algorithmic bytes: 8 + DW per state (block, gathered rank, dense write;
+// +4 inst_of).  The caller picks DW so that every dense number fits.
+template <bool BATCH, int DW>
 __global__ __launch_bounds__(kBlock) void k_dense(uint32_t N, const uint32_t* __restrict__ inst_of,
                                                   const InstDesc* __restrict__ desc,
                                                   const uint32_t* __restrict__ block,
                                                   const uint32_t* __restrict__ rank,
-                                                  uint32_t* __restrict__ dense) {
+                                                  void* __restrict__ dense) {
   const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
   if (g >= N) return;
   const uint32_t i = BATCH ? inst_of[g] : 0u;
-  dense[g] = rank[block[g]] - rank[desc[i].state_off];
+  const uint32_t v = rank[block[g]] - rank[desc[i].state_off];
+  if constexpr (DW == 1) static_cast<uint8_t*>(dense)[g] = (uint8_t)v;
+  else if constexpr (DW == 2) static_cast<uint16_t*>(dense)[g] = (uint16_t)v;
+  else static_cast<uint32_t*>(dense)[g] = v;
 }
 
 __global__ __launch_bounds__(kBlock) void k_block_counts(uint32_t ninst, const InstDesc* __restrict__ desc,
@@ -878,6 +902,34 @@ __global__ __launch_bounds__(kBlock) void k_emit_jobs(const InstDesc* __restrict
   }
 }
 
+// dense[g] = rank[block[g]] for the states of the listed instances (ranks
+// from k_scan_jobs are relative to the instance), DW bytes wide.
+// Algorithmic bytes: 8 + DW per state.
+template <int DW>
+__global__ __launch_bounds__(kBlock) void k_dense_jobs(const InstDesc* __restrict__ desc,
+                                                       const uint32_t* __restrict__ slot,
+                                                       const uint32_t* __restrict__ job_wg_off,
+                                                       uint32_t njobs,
+                                                       const uint32_t* __restrict__ block,
+                                                       const uint32_t* __restrict__ rank,
+                                                       void* __restrict__ dense) {
+  __shared__ uint32_t s_job;
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const InstDesc D = desc[slot[j]];
+  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < D.n) {
+      const uint32_t g = D.state_off + q;
+      const uint32_t v = rank[block[g]];
+      if constexpr (DW == 1) static_cast<uint8_t*>(dense)[g] = (uint8_t)v;
+      else if constexpr (DW == 2) static_cast<uint16_t*>(dense)[g] = (uint16_t)v;
+      else static_cast<uint32_t*>(dense)[g] = v;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_results_jobs(const InstDesc* __restrict__ desc,
                                                          const uint32_t* __restrict__ slot,
                                                          uint32_t njobs,
@@ -944,29 +996,58 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) 
   hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl);
 }
 
-void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
-                      const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
-                      const uint32_t* dense, Slot* table, uint32_t tbits, uint32_t* slot_of,
-                      uint64_t salt, Ctrl* ctrl, hipStream_t s) {
-  if (!m) return;
-  const uint32_t grid = grid_for(m, kSigTile);
-  if (batch)
-    hipLaunchKernelGGL(k_signature<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+namespace {
+template <bool BATCH>
+void launch_signature_w(int dw, dim3 grid, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                        const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
+                        const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
+                        Ctrl* ctrl, hipStream_t s) {
+  if (dw == 1)
+    hipLaunchKernelGGL((k_signature<BATCH, 1>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+                       block, dense, table, tbits, slot_of, salt, ctrl);
+  else if (dw == 2)
+    hipLaunchKernelGGL((k_signature<BATCH, 2>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
                        block, dense, table, tbits, slot_of, salt, ctrl);
   else
-    hipLaunchKernelGGL(k_signature<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+    hipLaunchKernelGGL((k_signature<BATCH, 4>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
                        block, dense, table, tbits, slot_of, salt, ctrl);
 }
 
+template <bool BATCH>
+void launch_dense_w(int dw, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
+                    const uint32_t* block, const uint32_t* rank, void* dense, hipStream_t s) {
+  const dim3 grid(grid_for(N, kBlock));
+  if (dw == 1)
+    hipLaunchKernelGGL((k_dense<BATCH, 1>), grid, dim3(kBlock), 0, s, N, inst_of, desc, block, rank, dense);
+  else if (dw == 2)
+    hipLaunchKernelGGL((k_dense<BATCH, 2>), grid, dim3(kBlock), 0, s, N, inst_of, desc, block, rank, dense);
+  else
+    hipLaunchKernelGGL((k_dense<BATCH, 4>), grid, dim3(kBlock), 0, s, N, inst_of, desc, block, rank, dense);
+}
+}  // namespace
+
+void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+                      const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
+                      const void* dense, int dense_width, Slot* table, uint32_t tbits,
+                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, hipStream_t s) {
+  if (!m) return;
+  const dim3 grid(grid_for(m, kSigTile));
+  if (batch)
+    launch_signature_w<true>(dense_width, grid, act, m, inst_of, desc, rows, block, dense, table, tbits,
+                             slot_of, salt, ctrl, s);
+  else
+    launch_signature_w<false>(dense_width, grid, act, m, inst_of, desc, rows, block, dense, table, tbits,
+                              slot_of, salt, ctrl, s);
+}
+
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
-                  const uint32_t* block, const uint32_t* rank, uint32_t* dense, hipStream_t s) {
+                  const uint32_t* block, const uint32_t* rank, void* dense, int dense_width,
+                  hipStream_t s) {
   if (!N) return;
   if (batch)
-    hipLaunchKernelGGL(k_dense<true>, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, N, inst_of, desc,
-                       block, rank, dense);
+    launch_dense_w<true>(dense_width, N, inst_of, desc, block, rank, dense, s);
   else
-    hipLaunchKernelGGL(k_dense<false>, dim3(grid_for(N, kBlock)), dim3(kBlock), 0, s, N, inst_of, desc,
-                       block, rank, dense);
+    launch_dense_w<false>(dense_width, N, inst_of, desc, block, rank, dense, s);
 }
 
 void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
@@ -1006,7 +1087,7 @@ void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
 }
 
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
-                      const Ctrl* ctrl, hipStream_t s) {
+                      Ctrl* ctrl, hipStream_t s) {
   if (!ninst) return;
   hipLaunchKernelGGL(k_round_end, dim3(grid_for(ninst, kBlock)), dim3(kBlock), 0, s, ninst,
                      changed_inst, refine_cnt, last, ctrl);
@@ -1045,6 +1126,22 @@ void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t
   if (!total_wgs) return;
   hipLaunchKernelGGL(k_emit_jobs, dim3(total_wgs), dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs,
                      block, rank);
+}
+
+void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
+                       uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
+                       void* dense, int dense_width, hipStream_t s) {
+  if (!total_wgs) return;
+  const dim3 grid(total_wgs);
+  if (dense_width == 1)
+    hipLaunchKernelGGL(k_dense_jobs<1>, grid, dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs, block, rank,
+                       dense);
+  else if (dense_width == 2)
+    hipLaunchKernelGGL(k_dense_jobs<2>, grid, dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs, block, rank,
+                       dense);
+  else
+    hipLaunchKernelGGL(k_dense_jobs<4>, grid, dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs, block, rank,
+                       dense);
 }
 
 void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,

@@ -184,6 +184,10 @@ struct Resident {
   uint32_t levels = 0;
   bool closure = false;
   bool dead = false;
+  // unary instances under AUTO refine by doubling (one closure level per
+  // round); mj: the current partition is Moore's P_mj; step: this round's t
+  bool dbl = false;
+  uint64_t mj = 0, step = 1;
 };
 
 }  // namespace
@@ -378,6 +382,14 @@ struct Serving::Impl {
       if (!r) continue;
       desc[s].rows_off = (uint32_t)rows_host.size();
       desc[s].kp = (uint32_t)r->rows.size();
+      if (r->dbl) {  // the single closure level 2^l <= mj + 1
+        uint32_t lvl = 0;
+        for (uint64_t x = r->mj + 1; x >> 1; x >>= 1) ++lvl;
+        if (lvl > r->rows.size() - 1) lvl = (uint32_t)r->rows.size() - 1;
+        r->step = 1ull << lvl;
+        desc[s].rows_off += lvl;
+        desc[s].kp = 1;
+      }
       rows_host.insert(rows_host.end(), r->rows.begin(), r->rows.end());
     }
     if (rows_host.size() * 8 > rows_cap) {
@@ -656,7 +668,7 @@ struct Serving::Impl {
         uint32_t* nxt = static_cast<uint32_t*>(d_act2);
         launch_clear_table(static_cast<Slot*>(d_table), tsize, static_cast<Ctrl*>(d_ctrl), stream);
         launch_signature(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<InstDesc*>(d_desc),
-                         static_cast<uint64_t*>(d_rows), static_cast<uint32_t*>(d_block), nullptr,
+                         static_cast<uint64_t*>(d_rows), static_cast<uint32_t*>(d_block), nullptr, 4,
                          static_cast<Slot*>(d_table), tbits, static_cast<uint32_t*>(d_slot_of), salt,
                          static_cast<Ctrl*>(d_ctrl), stream);
         launch_resolve(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<InstDesc*>(d_desc),
@@ -701,6 +713,8 @@ struct Serving::Impl {
         done.push_back(r);
         continue;
       }
+      r->mj += r->dbl ? r->step : 1;
+      if (r->dbl) desc_dirty = true;  // next level
       if (desc[s].dsrc) {  // accept bits only describe the first round's partition
         desc[s].ebits = 0;
         desc[s].dsrc = 0;
@@ -713,6 +727,7 @@ struct Serving::Impl {
     if (!auto_closure.empty()) {
       int rc = build_closures(auto_closure);
       if (rc != DFAMIN_OK) return rc;
+      for (Resident* r : auto_closure) r->dbl = r->nonid.size() == 1;
       desc_dirty = true;
     }
     if (desc_dirty) {

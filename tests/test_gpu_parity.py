@@ -105,10 +105,60 @@ def test_deep_chain_workload_closed_form(ctx):
 
 
 def test_deep_chain_auto(ctx):
+    """AUTO on the 2^20 chain: 8 plain rounds reach P_8, then doubling rounds
+    with t = 8, 16, ..., 2^19 reach P_(2^20), the first partition with every
+    state alone: 8 + 17 = 25 refining rounds (5 + ceil(log2(n - 2)))."""
     d = W.deep_chain()
     out, res = _run(ctx, d, "auto")
     assert res["num_blocks"] == d.n and np.array_equal(out, np.arange(d.n))
     assert res["closure_levels"] == 20
+    assert res["refine_rounds"] == 25 and res["rounds_executed"] == 26
+
+
+def _kept_levels(d, a):
+    """Closure levels kept for letter a: level 0, then every level that
+    differs from its predecessor and is not the identity, up to the first
+    that fails that test."""
+    L = oracle.floor_log2(d.n)
+    rows = oracle.closure(d.n, d.k, d.delta, L)
+    ident = np.arange(d.n, dtype=np.uint32)
+    kept = 1
+    for lv in range(1, L + 1):
+        cur, prev = rows[a * (L + 1) + lv], rows[a * (L + 1) + lv - 1]
+        if np.array_equal(cur, prev) or np.array_equal(cur, ident):
+            break
+        kept += 1
+    return kept
+
+
+def _auto_unary_rounds(d, auto_rounds=8):
+    """Refining rounds of AUTO on a unary instance, from Moore's partitions
+    P_j alone: plain rounds (j -> j + 1) until auto_rounds, then j -> j + t
+    with t the largest kept level 2^l <= j + 1; stop at the first step that
+    leaves the block count unchanged."""
+    rows = d.rows()
+    letters = [a for a in range(d.k) if not np.array_equal(rows[a], np.arange(d.n))]
+    assert len(letters) == 1
+    kept = _kept_levels(d, letters[0])
+    prev = oracle.moore_partial(d.n, d.k, d.delta, d.accept, 0)[1]
+    j = r = 0
+    while True:
+        t = 1
+        if r >= auto_rounds:
+            t = 2 ** min(oracle.floor_log2(j + 1), kept - 1)
+        c = oracle.moore_partial(d.n, d.k, d.delta, d.accept, j + t)[1]
+        if c == prev:
+            return r
+        prev, j, r = c, j + t, r + 1
+
+
+@pytest.mark.parametrize("which", range(6))
+def test_auto_doubling_rounds(ctx, which):
+    """Unary instances under AUTO refine by doubling after the plain rounds:
+    same partition as the oracle, round count as derived from P_j."""
+    d = [W.chain_dfa(1000, 2), W.permuted_chain_dfa(1500, 3, 5), W.fib_dfa(14),
+         W.random_dfa(1200, 1, 3), W.chain_dfa(9, 1), W.fib_dfa_word(9)][which]
+    _check(ctx, d, "auto", rounds=_auto_unary_rounds(d))
 
 
 @pytest.mark.parametrize("m", [8, 10, 14, 18])
