@@ -106,7 +106,7 @@ class Engine {
   DevBuf d_inst_of_, d_block_, d_act_, d_act2_, d_slot_of_, d_nb_, d_keep_, d_rank_;
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_, d_closure_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
-  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_;
+  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_;
 };
 
 // The object behind dfamin_ctx.

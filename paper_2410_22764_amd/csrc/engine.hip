@@ -124,7 +124,7 @@ Engine::~Engine() {
                     &d_counts_, &d_djobs_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
-  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_};
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -473,8 +473,16 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   // per level.
   std::vector<uint8_t> active(I, 1), dbl(I, 0);
   std::vector<uint64_t> mj(I, 0), step(I, 1);
-  std::vector<uint32_t> cand, exact, jobv;
-  TRY(ensure(d_djobs_, 6 * I * 4 + 64));
+  // Exact block counts (and instance-relative ranks in d_rank_) of the
+  // instances scanned at the end of the previous round; cnt_ok marks them.
+  std::vector<uint64_t> cnt(I, 0);
+  std::vector<uint8_t> cnt_ok(I, 0);
+  std::vector<uint32_t> exact, scan;
+  TRY(ensure(d_djobs_, 4 * I * 4 + 64));
+  TRY(ensure_host(h_jobs_, 4 * I * 4 + 64));
+  TRY(ensure_host(h_desc_, I * sizeof(InstDesc)));
+  uint32_t* hj = h_jobs_.as<uint32_t>();
+  uint32_t* dj = d_djobs_.as<uint32_t>();
   while (m > 0) {
     if (any_auto && rounds == auto_rounds) {
       // instances still refining after auto_rounds rounds get the closure
@@ -492,9 +500,9 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     // doubling instances: this round's single closure level
     for (size_t i = 0; i < I; ++i) {
       if (!dbl[i] || !active[i]) continue;
-      const uint32_t cnt = (uint32_t)inst_rows_[i].size();
+      const uint32_t nrows = (uint32_t)inst_rows_[i].size();
       uint32_t lvl = (uint32_t)floor_log2_u64(mj[i] + 1);
-      if (lvl > cnt - 1) lvl = cnt - 1;
+      if (lvl > nrows - 1) lvl = nrows - 1;
       step[i] = 1ull << lvl;
       if (desc_[i].rows_off != row_base_[i] + lvl || desc_[i].kp != 1) {
         desc_[i].rows_off = row_base_[i] + lvl;
@@ -503,19 +511,24 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
       }
     }
     // Key mode per instance (see InstDesc): exact keys while
-    // (kp+1) * ceil(log2 B) fits in 31 bits, B = blocks before this round.
-    // Only instances still refining matter; their exact block counts and
-    // dense numbers come from a segmented scan over their own states.
-    cand.clear();
+    // (kp+1) * ceil(log2 B) fits in 31 bits, B = blocks before this round
+    // (exact, from the scan at the end of the previous round).  Round 1
+    // takes its keys from the accept bits.
+    exact.clear();
+    uint32_t eb_max = 0;
     for (size_t i = 0; i < I; ++i) {
       const uint64_t kp1 = desc_[i].kp + 1ull;
       uint32_t eb = 0, ds = 0;
       if (active[i]) {
         if (rounds == 0) {
           if (kp1 <= 31) { eb = 1; ds = 1; }
-        } else if (kp1 * std::max<uint32_t>(1, ceil_log2_u64(ub[i])) <= 31) {
-          cand.push_back((uint32_t)i);
-          continue;  // decided below from the exact count
+        } else if (cnt_ok[i]) {
+          const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(std::max<uint64_t>(cnt[i], 1)));
+          if (kp1 * bits <= 31) {
+            eb = bits;
+            exact.push_back((uint32_t)i);
+            eb_max = std::max(eb_max, eb);
+          }
         }
       }
       if (desc_[i].ebits != eb || desc_[i].dsrc != ds) {
@@ -524,70 +537,29 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
         dirty = true;
       }
     }
-    if (!cand.empty()) {
-      const uint32_t nj = (uint32_t)cand.size();
-      jobv.assign(3 * nj, 0);
-      uint32_t tiles = 0;
-      double states = 0;
-      for (uint32_t j = 0; j < nj; ++j) {
-        jobv[j] = cand[j];
-        jobv[nj + j] = tiles;
-        tiles += (in_[cand[j]].n + kScanTile - 1) / kScanTile;
-        states += in_[cand[j]].n;
+    if (!exact.empty()) {
+      // dense numbers from the ranks of the previous scan
+      dense_width = eb_max <= 8 ? 1 : (eb_max <= 16 ? 2 : 4);
+      const uint32_t ne = (uint32_t)exact.size();
+      uint32_t wgs = 0;
+      double es = 0;
+      for (uint32_t j = 0; j < ne; ++j) {
+        hj[j] = exact[j];
+        hj[ne + j] = wgs;
+        wgs += (in_[exact[j]].n + kRowTile - 1) / kRowTile;
+        es += in_[exact[j]].n;
       }
-      TRY(ensure(d_status_, ((size_t)tiles + 1) * 8));
-      uint32_t* dj = d_djobs_.as<uint32_t>();
-      HIP(hipMemcpyAsync(dj, jobv.data(), 2 * nj * 4, hipMemcpyHostToDevice, s));
-      launch_prep_scan(d_status_.as<unsigned long long>(), tiles, d_ctrl_.as<Ctrl>(), s);
-      prof.begin(s, "scan_jobs", 8.0 * states);
-      launch_scan_jobs(d_desc_.as<InstDesc>(), dj, dj + nj, nj, tiles, d_block_.as<uint32_t>(),
-                       d_rank_.as<uint32_t>(), d_counts_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                       d_status_.as<unsigned long long>(), s);
+      TRY(ensure(d_dense_, N * 4));
+      HIP(hipMemcpyAsync(dj, hj, 2 * ne * 4, hipMemcpyHostToDevice, s));
+      prof.begin(s, "dense", (8.0 + dense_width) * es);
+      launch_dense_jobs(d_desc_.as<InstDesc>(), dj, dj + ne, ne, wgs, d_block_.as<uint32_t>(),
+                        d_rank_.as<uint32_t>(), d_dense_.p, dense_width, s);
       prof.end(s);
-      HIP(hipGetLastError());
-      HIP(hipMemcpyAsync(h_counts_.p, d_counts_.p, nj * 4, hipMemcpyDeviceToHost, s));
-      HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-      HIP(hipStreamSynchronize(s));
-      prof.collect();
-      if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
-      exact.clear();
-      uint32_t eb_max = 0;
-      for (uint32_t j = 0; j < nj; ++j) {
-        const uint32_t i = cand[j];
-        const uint64_t B = std::max<uint64_t>(h_counts_.as<uint32_t>()[j], 1);
-        ub[i] = B;
-        const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
-        const uint32_t eb = ((desc_[i].kp + 1ull) * bits <= 31) ? bits : 0u;
-        if (eb) { exact.push_back(i); eb_max = std::max(eb_max, eb); }
-        if (desc_[i].ebits != eb || desc_[i].dsrc != 0) {
-          desc_[i].ebits = eb;
-          desc_[i].dsrc = 0;
-          dirty = true;
-        }
-      }
-      if (!exact.empty()) {
-        dense_width = eb_max <= 8 ? 1 : (eb_max <= 16 ? 2 : 4);
-        const uint32_t ne = (uint32_t)exact.size();
-        uint32_t* dj2 = dj + 2 * nj;
-        jobv.assign(2 * ne, 0);
-        uint32_t wgs = 0;
-        double es = 0;
-        for (uint32_t j = 0; j < ne; ++j) {
-          jobv[j] = exact[j];
-          jobv[ne + j] = wgs;
-          wgs += (in_[exact[j]].n + kRowTile - 1) / kRowTile;
-          es += in_[exact[j]].n;
-        }
-        TRY(ensure(d_dense_, N * 4));
-        HIP(hipMemcpyAsync(dj2, jobv.data(), 2 * ne * 4, hipMemcpyHostToDevice, s));
-        prof.begin(s, "dense", (8.0 + dense_width) * es);
-        launch_dense_jobs(d_desc_.as<InstDesc>(), dj2, dj2 + ne, ne, wgs, d_block_.as<uint32_t>(),
-                          d_rank_.as<uint32_t>(), d_dense_.p, dense_width, s);
-        prof.end(s);
-      }
     }
-    if (dirty)
-      HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    if (dirty) {
+      std::memcpy(h_desc_.p, desc_.data(), I * sizeof(InstDesc));
+      HIP(hipMemcpyAsync(d_desc_.p, h_desc_.p, I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+    }
     const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * m));
     const uint64_t tsize = 1ull << tbits;
     TRY(ensure(d_table_, tsize * sizeof(Slot)));
@@ -618,6 +590,40 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     prof.end(s);
     launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
                      d_ctrl_.as<Ctrl>(), s);
+    // Exact block counts for the next round, queued before the one sync of
+    // the round: instances that were refining before this round and whose
+    // next signature could fit 31 bits, B <= min(n, B^(kp+1)) after it.
+    scan.clear();
+    for (size_t i = 0; i < I; ++i) {
+      if (!active[i]) continue;
+      const uint64_t B = cnt_ok[i] ? std::max<uint64_t>(cnt[i], 1) : ub[i];
+      const uint64_t kp1 = desc_[i].kp + 1ull;
+      const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
+      const uint64_t nb = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
+      if (kp1 * std::max<uint32_t>(1, ceil_log2_u64(nb)) <= 31) scan.push_back((uint32_t)i);
+    }
+    const uint32_t ns = (uint32_t)scan.size();
+    if (ns) {
+      uint32_t* hs = hj + 2 * I;
+      uint32_t* ds = dj + 2 * I;
+      uint32_t tiles = 0;
+      double states = 0;
+      for (uint32_t j = 0; j < ns; ++j) {
+        hs[j] = scan[j];
+        hs[ns + j] = tiles;
+        tiles += (in_[scan[j]].n + kScanTile - 1) / kScanTile;
+        states += in_[scan[j]].n;
+      }
+      TRY(ensure(d_status_, ((size_t)tiles + 1) * 8));
+      HIP(hipMemcpyAsync(ds, hs, 2 * ns * 4, hipMemcpyHostToDevice, s));
+      launch_prep_scan(d_status_.as<unsigned long long>(), tiles, d_ctrl_.as<Ctrl>(), s);
+      prof.begin(s, "scan_jobs", 8.0 * states);
+      launch_scan_jobs(d_desc_.as<InstDesc>(), ds, ds + ns, ns, tiles, d_block_.as<uint32_t>(),
+                       d_rank_.as<uint32_t>(), d_counts_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                       d_status_.as<unsigned long long>(), s);
+      prof.end(s);
+      HIP(hipMemcpyAsync(h_counts_.p, d_counts_.p, ns * 4, hipMemcpyDeviceToHost, s));
+    }
     HIP(hipGetLastError());
     HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
@@ -625,11 +631,17 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     prof.collect();
     const Ctrl c = *h_ctrl_.as<Ctrl>();
     if (c.fault) return DFAMIN_E_INTERNAL;
+    std::fill(cnt_ok.begin(), cnt_ok.end(), 0);
+    for (uint32_t j = 0; j < ns; ++j) {
+      cnt[scan[j]] = h_counts_.as<uint32_t>()[j];
+      cnt_ok[scan[j]] = 1;
+    }
     if (prof.enabled() && std::getenv("DFAMIN_TRACE"))
-      std::fprintf(stderr, "[dfamin] round %llu: m=%llu table=2^%u next=%u changed=%u collision=%u\n",
+      std::fprintf(stderr, "[dfamin] round %llu: m=%llu table=2^%u next=%u changed=%u collision=%u exact=%zu\n",
                    (unsigned long long)rounds + 1, (unsigned long long)m, tbits, c.m_next, c.any_changed,
-                   c.collision);
+                   c.collision, exact.size());
     if (c.collision) {
+      // the partition is unchanged, so the counts just taken still hold
       if (++retries > kMaxSaltRetries) return DFAMIN_E_INTERNAL;
       salt = mix64(salt + 0x9E3779B97F4A7C15ull);
       continue;
@@ -642,6 +654,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
       const uint64_t kp1 = desc_[i].kp + 1ull;
       const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(ub[i]));
       ub[i] = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
+      if (cnt_ok[i]) ub[i] = std::max<uint64_t>(cnt[i], 1);
       mj[i] += dbl[i] ? step[i] : 1;
       active[i] = rc[i] == rounds;
     }
