@@ -225,6 +225,10 @@ def main():
     ap.add_argument("--requests", type=int, default=400, help="serving: measured requests")
     ap.add_argument("--pool", type=int, default=128, help="serving: distinct pre-generated requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / saturation")
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests of the serving leg in the default run (0: none)")
+    ap.add_argument("--serving-pool", type=int, default=64,
+                    help="distinct requests of the serving leg in the default run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (for scaling "
                          "rocprofv3 FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -354,6 +358,13 @@ def main():
     batched = None
     if not args.no_batch and args.workload == "plain_large":
         batched = batched_vs_plain(ctx, args.seed)
+    serving = None
+    if args.serving_requests and args.workload == "plain_large":
+        sctx = dfamin.dfamin_create(0)
+        serving = serving_run(sctx, args.seed, args.serving_requests, args.serving_pool, args.load)
+        serving["workload"] = ("serving: Poisson stream, n log-uniform in [2^8, 2^22], |Sigma| in 2..16, "
+                               "20% permuted chains, closure auto")
+        sctx.close()
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
@@ -375,6 +386,7 @@ def main():
                     for s in stats],
         "end_to_end": end_to_end,
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     ctx.close()

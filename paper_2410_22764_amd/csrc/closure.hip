@@ -65,7 +65,7 @@ int build_closure_levels(std::vector<ClosureSpec>& specs, const ClosureScratch& 
     }
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     if (hipMemcpyAsync(h_flags, d_flags, jobs.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+        stream_wait(s) != hipSuccess)
       return DFAMIN_E_DEVICE;
     flags = h_flags;
   }

@@ -243,7 +243,7 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
       DevBuf nb;
       TRY(ensure(nb, (base + words) * 4));
       HIP(hipMemcpyAsync(nb.p, d_closure_.p, base * 4, hipMemcpyDeviceToDevice, s));
-      HIP(hipStreamSynchronize(s));
+      HIP(stream_wait(s));
       const uint64_t old = reinterpret_cast<uint64_t>(d_closure_.p);
       const uint64_t nw = reinterpret_cast<uint64_t>(nb.p);
       for (auto& rl : inst_rows_)
@@ -339,7 +339,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     HIP(hipGetLastError());
   }
   HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
-  HIP(hipStreamSynchronize(s));
+  HIP(stream_wait(s));
   prof.collect();
   bool any_bad = false;
   nonid_.assign(I, {});
@@ -627,7 +627,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     HIP(hipGetLastError());
     HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
     HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
-    HIP(hipStreamSynchronize(s));
+    HIP(stream_wait(s));
     prof.collect();
     const Ctrl c = *h_ctrl_.as<Ctrl>();
     if (c.fault) return DFAMIN_E_INTERNAL;
@@ -679,7 +679,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   HIP(hipGetLastError());
   HIP(hipMemcpyAsync(h_results_.p, d_results_.p, I * sizeof(ResultDev), hipMemcpyDeviceToHost, s));
   HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-  HIP(hipStreamSynchronize(s));
+  HIP(stream_wait(s));
   prof.collect();
   if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
   const ResultDev* r = h_results_.as<ResultDev>();

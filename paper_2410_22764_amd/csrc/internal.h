@@ -15,6 +15,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <chrono>
 #include <stdint.h>
 
 namespace dfamin {
@@ -80,6 +82,20 @@ static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 // Bounds on device-side waiting and probing: hitting one sets Ctrl::fault,
 // the kernel finishes, and the host reports DFAMIN_E_INTERNAL.
 constexpr uint32_t kMaxSpin = 1u << 22;
+
+// Host-side wait for a stream.  Round loops wait for a few microseconds of
+// queued work many times per call; a blocking wait's wake-up costs tens of
+// microseconds each time, so short waits poll the stream and only waits
+// beyond 2 ms fall back to the blocking call.
+inline hipError_t stream_wait(hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (true) {
+    const hipError_t e = hipStreamQuery(s);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000))
+      return hipStreamSynchronize(s);
+  }
+}
 
 // One row of n entries handled by a row job (validation, closure level).
 struct RowJob {

@@ -110,32 +110,53 @@ __device__ uint32_t lookback_wave0(unsigned long long* status, uint32_t tile, ui
   return excl;
 }
 
-// Exclusive rank of each flagged item inside a tile of kScanItems sub-tiles of
-// kBlock items (item e of thread t is element e*kBlock + t of the tile), via
-// one 64-lane ballot per sub-tile and wave.  s_cnt: LDS of kScanItems*4 words.
-__device__ __forceinline__ uint32_t tile_ballot_scan(const bool (&f)[kScanItems],
-                                                     uint32_t (&rank)[kScanItems],
-                                                     uint32_t* s_cnt) {
+// Tile scan: a tile holds kScanItems x kBlock items, item e of thread t being
+// element e*kBlock + t.  Each thread passes its flags as a bit mask (bit e =
+// item e); one 64-lane ballot per item and wave goes to LDS, and wave 0 turns
+// the kScanItems*kWaves ballot counts (in element order) into exclusive
+// offsets.  Flags, ballots and offsets stay out of registers, so the scan
+// kernels keep a high occupancy.  Returns the tile's flag count; tile_rank()
+// gives an item's exclusive rank afterwards.
+constexpr int kWaves = kBlock / 64;
+constexpr int kTileWords = kScanItems * kWaves;
+static_assert(kTileWords == 128, "wave 0 scans two ballot counts per lane");
+static_assert(kScanItems <= 32, "flags are a 32-bit mask per thread");
+
+struct TileScanLds {
+  unsigned long long mask[kTileWords];
+  uint32_t off[kTileWords + 1];
+};
+
+__device__ __forceinline__ uint32_t tile_ballot_count(uint32_t fbits, TileScanLds& t) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t within[kScanItems];
 #pragma unroll
   for (int e = 0; e < kScanItems; ++e) {
-    unsigned long long mask = __ballot(f[e]);
-    within[e] = __popcll(mask & lt);
-    if (lane == 0) s_cnt[e * 4 + wave] = __popcll(mask);
+    const unsigned long long m = __ballot((fbits >> e) & 1u);
+    if (lane == 0) t.mask[e * kWaves + wave] = m;
   }
   __syncthreads();
-  uint32_t acc = 0;
+  if (wave == 0) {
+    const uint32_t c0 = __popcll(t.mask[2 * lane]), c1 = __popcll(t.mask[2 * lane + 1]);
+    uint32_t v = c0 + c1;
 #pragma unroll
-  for (int e = 0; e < kScanItems; ++e) {
-#pragma unroll
-    for (uint32_t w = 0; w < 4; ++w) {
-      if (w == wave) rank[e] = acc + within[e];
-      acc += s_cnt[e * 4 + w];
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t u = __shfl_up(v, off, 64);
+      if ((int)lane >= off) v += u;
     }
+    const uint32_t excl = v - c0 - c1;
+    t.off[2 * lane] = excl;
+    t.off[2 * lane + 1] = excl + c0;
+    if (lane == 63) t.off[kTileWords] = v;
   }
-  return acc;
+  __syncthreads();
+  return t.off[kTileWords];
+}
+
+__device__ __forceinline__ uint32_t tile_rank(const TileScanLds& t, int e) {
+  const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int w = e * kWaves + (int)wave;
+  return t.off[w] + (uint32_t)__popcll(t.mask[w] & lt);
 }
 
 // Workgroup -> job by binary search over the exclusive workgroup prefix.
@@ -580,7 +601,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   // written, but every tile still takes part in the look-back so that no
   // workgroup can wait for one that left early.
   __shared__ uint32_t s_tile, s_prefix, s_coll;
-  __shared__ uint32_t s_cnt[kScanItems * 4];
+  __shared__ TileScanLds s_scan;
   if (threadIdx.x == 0) {
     s_tile = atomicAdd(&ctrl->tile_counter, 1u);
     s_coll = ctrl->collision;
@@ -589,23 +610,18 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   const uint32_t tile = s_tile;
   const bool coll = s_coll != 0;
   const uint32_t base = tile * kScanTile;
-  bool f[kScanItems];
-  uint32_t gs[kScanItems];
-#pragma unroll
+  uint32_t fb = 0;
+#pragma unroll 8
   for (int e = 0; e < kScanItems; ++e) {
     const uint32_t j = base + e * kBlock + threadIdx.x;
-    f[e] = false;
-    gs[e] = 0;
     if (j < m && !coll) {
       const uint32_t g = act[j];
-      gs[e] = g;
       block[g] = nb[j];
       const uint32_t i = BATCH ? inst_of[g] : 0u;
-      f[e] = keep[j] && changed_inst[i] && !(dead && dead[i]);
+      if (keep[j] && changed_inst[i] && !(dead && dead[i])) fb |= 1u << e;
     }
   }
-  uint32_t rank[kScanItems];
-  const uint32_t total = tile_ballot_scan(f, rank, s_cnt);
+  const uint32_t total = tile_ballot_count(fb, s_scan);
   if (threadIdx.x < 64) {
     const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl);
     if (threadIdx.x == 0) {
@@ -615,9 +631,9 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
-#pragma unroll
+  // kept states are re-read from act (the tile was just read: cache hits)
   for (int e = 0; e < kScanItems; ++e)
-    if (f[e]) act_next[pre + rank[e]] = gs[e];
+    if ((fb >> e) & 1u) act_next[pre + tile_rank(s_scan, e)] = act[base + e * kBlock + threadIdx.x];
 }
 
 __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
@@ -652,19 +668,18 @@ __global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict
                                                       Ctrl* __restrict__ ctrl,
                                                       unsigned long long* __restrict__ scan_status) {
   __shared__ uint32_t s_tile, s_prefix;
-  __shared__ uint32_t s_cnt[kScanItems * 4];
+  __shared__ TileScanLds s_scan;
   if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tile_counter, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
   const uint32_t base = tile * kScanTile;
-  bool f[kScanItems];
-#pragma unroll
+  uint32_t fb = 0;
+#pragma unroll 8
   for (int e = 0; e < kScanItems; ++e) {
     const uint32_t g = base + e * kBlock + threadIdx.x;
-    f[e] = (g < N) && (block[g] == g);
+    if (g < N && block[g] == g) fb |= 1u << e;
   }
-  uint32_t r[kScanItems];
-  const uint32_t total = tile_ballot_scan(f, r, s_cnt);
+  const uint32_t total = tile_ballot_count(fb, s_scan);
   if (threadIdx.x < 64) {
     const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl);
     if (threadIdx.x == 0) {
@@ -674,10 +689,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
-#pragma unroll
   for (int e = 0; e < kScanItems; ++e) {
     const uint32_t g = base + e * kBlock + threadIdx.x;
-    if (g < N) rank[g] = pre + r[e];
+    if (g < N) rank[g] = pre + tile_rank(s_scan, e);
   }
 }
 
@@ -844,7 +858,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict
                                                       Ctrl* __restrict__ ctrl,
                                                       unsigned long long* __restrict__ scan_status) {
   __shared__ uint32_t s_tile, s_job, s_prefix;
-  __shared__ uint32_t s_cnt[kScanItems * 4];
+  __shared__ TileScanLds s_scan;
   if (threadIdx.x == 0) {
     const uint32_t t = atomicAdd(&ctrl->tile_counter, 1u);
     uint32_t lo = 0, hi = njobs;
@@ -859,14 +873,13 @@ __global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict
   const uint32_t tile = s_tile, j = s_job;
   const InstDesc D = desc[slot[j]];
   const uint32_t base = (tile - job_tile_off[j]) * kScanTile;
-  bool f[kScanItems];
-#pragma unroll
+  uint32_t fb = 0;
+#pragma unroll 8
   for (int e = 0; e < kScanItems; ++e) {
     const uint32_t q = base + e * kBlock + threadIdx.x;
-    f[e] = (q < D.n) && (block[D.state_off + q] == D.state_off + q);
+    if (q < D.n && block[D.state_off + q] == D.state_off + q) fb |= 1u << e;
   }
-  uint32_t r[kScanItems];
-  const uint32_t total = tile_ballot_scan(f, r, s_cnt);
+  const uint32_t total = tile_ballot_count(fb, s_scan);
   if (threadIdx.x < 64) {
     const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl, job_tile_off[j]);
     if (threadIdx.x == 0) {
@@ -876,10 +889,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
-#pragma unroll
   for (int e = 0; e < kScanItems; ++e) {
     const uint32_t q = base + e * kBlock + threadIdx.x;
-    if (q < D.n) rank[D.state_off + q] = pre + r[e];
+    if (q < D.n) rank[D.state_off + q] = pre + tile_rank(s_scan, e);
   }
 }
 

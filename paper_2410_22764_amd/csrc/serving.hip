@@ -338,7 +338,7 @@ struct Serving::Impl {
     arena.reset(cap);
     slots.assign(kSlots, nullptr);
     desc.assign(kSlots, InstDesc{});
-    return hipStreamSynchronize(stream) == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
+    return stream_wait(stream) == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
   }
 
   void release_resident(Resident* r) {
@@ -492,7 +492,7 @@ struct Serving::Impl {
                      s_wg.as<uint32_t>(), s_flags.as<uint32_t>(), stream);
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     if (hipMemcpyAsync(h_flags.p, s_flags.p, jobs.size() * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess)
+        stream_wait(stream) != hipSuccess)
       return DFAMIN_E_DEVICE;
     const uint32_t* f = h_flags.as<uint32_t>();
     std::vector<Resident*> ok, need_closure;
@@ -568,7 +568,7 @@ struct Serving::Impl {
                      static_cast<uint32_t*>(d_act), stream);
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     // host vectors must outlive the asynchronous copies
-    if (hipStreamSynchronize(stream) != hipSuccess) return DFAMIN_E_DEVICE;
+    if (stream_wait(stream) != hipSuccess) return DFAMIN_E_DEVICE;
     m = am;
     return DFAMIN_OK;
   }
@@ -615,7 +615,7 @@ struct Serving::Impl {
       if (hipMemcpyAsync(h_results.p, d_results, nj * sizeof(ResultDev), hipMemcpyDeviceToHost, stream) !=
               hipSuccess ||
           hipMemcpyAsync(h_ctrl.p, d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-          hipStreamSynchronize(stream) != hipSuccess)
+          stream_wait(stream) != hipSuccess)
         return DFAMIN_E_DEVICE;
       if (h_ctrl.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
       const ResultDev* res = h_results.as<ResultDev>();
@@ -651,7 +651,7 @@ struct Serving::Impl {
         const uint32_t one = 1;
         if (hipMemcpyAsync(static_cast<uint32_t*>(d_dead) + s, &one, 4, hipMemcpyHostToDevice, stream) !=
                 hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess)
+            stream_wait(stream) != hipSuccess)
           return DFAMIN_E_DEVICE;
         dirty = true;
       }
@@ -685,7 +685,7 @@ struct Serving::Impl {
         if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
         if (hipMemcpyAsync(h_ctrl.p, d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
             hipMemcpyAsync(h_last.p, d_last, kSlots * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess)
+            stream_wait(stream) != hipSuccess)
           return DFAMIN_E_DEVICE;
         const Ctrl c = *h_ctrl.as<Ctrl>();
         if (c.fault) return DFAMIN_E_INTERNAL;
