@@ -177,6 +177,17 @@ int dfamin_set_profiling(dfamin_ctx *ctx, int on);
  * entries available (may exceed cap), or a negative status. */
 int dfamin_get_kernel_stats(dfamin_ctx *ctx, dfamin_kernel_stat *stats, int cap);
 
+/* ---- tuning ------------------------------------------------------------- */
+/* Signature-kernel tile: variant 0, 1 or 2 processes 256, 512 or 1024 states
+ * per workgroup (1, 2 or 4 per thread, with an LDS pre-grouping table of
+ * twice as many slots).  With variant = -1 (the default) the context tunes
+ * itself: the first round of each size class (log2 of the active states,
+ * key mode, dense width; classes of at least 2^18 states) runs every
+ * variant once, timed with HIP events, and later rounds of that class use
+ * the fastest.  0..2 force one variant (results never depend on it).
+ * Returns DFAMIN_E_INVAL for a null ctx or another value; clears the cache. */
+int dfamin_set_tuning(dfamin_ctx *ctx, int variant);
+
 #ifdef __cplusplus
 }
 #endif

@@ -196,6 +196,10 @@ void dfamin_destroy(dfamin_ctx* ctx) {
   if (ctx->c.h_in.p) (void)hipHostFree(ctx->c.h_in.p);
   if (ctx->c.h_out.p) (void)hipHostFree(ctx->c.h_out.p);
   if (ctx->c.stream) (void)hipStreamSynchronize(ctx->c.stream);
+  if (ctx->c.tuner.have_events) {
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t e : ctx->c.tuner.ev) (void)hipEventDestroy(e);
+  }
   hipStream_t s = ctx->c.stream;
   delete ctx;
   if (s) (void)hipStreamDestroy(s);
@@ -324,6 +328,13 @@ const char* dfamin_status_str(int status) {
 int dfamin_set_profiling(dfamin_ctx* ctx, int on) {
   if (!ctx) return DFAMIN_E_INVAL;
   ctx->c.prof.set_enabled(on != 0);
+  return DFAMIN_OK;
+}
+
+int dfamin_set_tuning(dfamin_ctx* ctx, int variant) {
+  if (!ctx || variant < -1 || variant >= dfamin::kSigVariants) return DFAMIN_E_INVAL;
+  ctx->c.tuner.forced = variant;
+  ctx->c.tuner.best.clear();
   return DFAMIN_OK;
 }
 

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/dfamin.h"
@@ -109,6 +110,15 @@ class Engine {
   HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_;
 };
 
+// Signature-tile autotuner state of a context: a forced variant, or the
+// fastest variant measured per size class.
+struct Tuner {
+  int forced = -1;
+  std::map<uint32_t, int> best;
+  hipEvent_t ev[2 * kSigVariants] = {};
+  bool have_events = false;
+};
+
 // The object behind dfamin_ctx.
 class Serving;
 class Context {
@@ -118,6 +128,7 @@ class Context {
   uint64_t used = 0;
   hipStream_t stream = nullptr;  // internal stream for host-input calls
   Profiler prof;
+  Tuner tuner;
   Engine engine{this};
   // staging for host-input calls
   DevBuf in_delta, in_accept, in_out;

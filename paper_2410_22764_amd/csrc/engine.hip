@@ -516,6 +516,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     // takes its keys from the accept bits.
     exact.clear();
     uint32_t eb_max = 0;
+    bool any_hash = false;
     for (size_t i = 0; i < I; ++i) {
       const uint64_t kp1 = desc_[i].kp + 1ull;
       uint32_t eb = 0, ds = 0;
@@ -531,6 +532,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
           }
         }
       }
+      if (active[i] && eb == 0) any_hash = true;
       if (desc_[i].ebits != eb || desc_[i].dsrc != ds) {
         desc_[i].ebits = eb;
         desc_[i].dsrc = ds;
@@ -567,15 +569,60 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     const double md = (double)m;
     const double inst_b = batch ? 4.0 : 0.0;
 
-    prof.begin(s, "clear_table", 8.0 * (double)tsize);
-    launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
-    prof.end(s);
-    prof.begin(s, "signature", md * sig_bytes());
-    launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
-                     d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt,
-                     d_ctrl_.as<Ctrl>(), s);
-    prof.end(s);
+    // Signature tile: forced, cached for this size class, or tuned now by
+    // running every variant once on a freshly cleared table (the last run's
+    // table and slot ids are as valid as any other's).
+    Tuner& tu = ctx_->tuner;
+    const uint32_t tkey = (batch ? 1u : 0u) | (any_hash ? 2u : 0u) | ((uint32_t)dense_width << 2) |
+                          (ceil_log2_u64(m) << 8);
+    int variant = kSigDefaultVariant;
+    bool tuned_now = false;
+    if (tu.forced >= 0) {
+      variant = tu.forced;
+    } else if (m >= kTuneMinStates) {
+      auto it = tu.best.find(tkey);
+      if (it != tu.best.end()) {
+        variant = it->second;
+      } else {
+        if (!tu.have_events) {
+          for (hipEvent_t& e : tu.ev) HIP(hipEventCreate(&e));
+          tu.have_events = true;
+        }
+        for (int v = 0; v < kSigVariants; ++v) {
+          launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+          HIP(hipEventRecord(tu.ev[2 * v], s));
+          launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                           d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
+                           d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
+                           v, s);
+          HIP(hipEventRecord(tu.ev[2 * v + 1], s));
+        }
+        HIP(hipGetLastError());
+        HIP(hipEventSynchronize(tu.ev[2 * kSigVariants - 1]));
+        float best_ms = 0;
+        for (int v = 0; v < kSigVariants; ++v) {
+          float ms = 0;
+          HIP(hipEventElapsedTime(&ms, tu.ev[2 * v], tu.ev[2 * v + 1]));
+          if (v == 0 || ms < best_ms) { best_ms = ms; variant = v; }
+        }
+        tu.best[tkey] = variant;
+        tuned_now = true;
+        if (std::getenv("DFAMIN_TRACE"))
+          std::fprintf(stderr, "[dfamin] tuned class 0x%x (m=%llu): variant %d, %.3f ms\n", tkey,
+                       (unsigned long long)m, variant, best_ms);
+      }
+    }
+    if (!tuned_now) {
+      prof.begin(s, "clear_table", 8.0 * (double)tsize);
+      launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+      prof.end(s);
+      prof.begin(s, "signature", md * sig_bytes());
+      launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                       d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
+                       d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
+                       variant, s);
+      prof.end(s);
+    }
     prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
     launch_resolve(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                    d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),

@@ -24,9 +24,12 @@ namespace dfamin {
 constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
 constexpr int kScanItems = 32;        // items per thread in scan / compaction tiles
 constexpr int kScanTile = kBlock * kScanItems;
-constexpr int kSigItems = 2;          // states per thread in the signature kernel
-constexpr int kSigTile = kBlock * kSigItems;
-constexpr int kLocalSlots = 2 * kSigTile;  // LDS hash slots per signature workgroup
+// Signature kernel variants: 1, 2 or 4 states per thread (256, 512 or 1024
+// states per workgroup, an LDS table of twice as many slots).  The variant is
+// picked per size class by the engine's autotuner.
+constexpr int kSigVariants = 3;
+constexpr int kSigDefaultVariant = 1;
+constexpr uint64_t kTuneMinStates = 1ull << 18;  // smaller rounds use the default
 constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
 
 // Per-instance descriptor (device copy).  64 bytes.
@@ -141,7 +144,7 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s);
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
-                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, hipStream_t s);
+                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s);
 // dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
 // instance's blocks in order of least member, dense_width bytes wide (every
 // number must fit).

@@ -416,27 +416,29 @@ __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint6
 // (slot id) + 8 (one hash-slot update per local group, upper bound).  Exact
 // mode: the same without the record, with dense numbers (or accept bits)
 // gathered instead of block ids.
-template <bool BATCH, int DW>
+template <bool BATCH, int DW, int SI>
 __global__ __launch_bounds__(kBlock) void k_signature(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
     const uint32_t* __restrict__ block, const void* __restrict__ dense,
     Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
     Ctrl* __restrict__ ctrl) {
-  __shared__ unsigned long long lkey[kLocalSlots];
-  __shared__ uint32_t lmin[kLocalSlots], lcnt[kLocalSlots], lslot[kLocalSlots];
-  for (uint32_t s = threadIdx.x; s < kLocalSlots; s += kBlock) {
+  // SI states per thread; an LDS table of twice the tile's states
+  constexpr uint32_t kTile = kBlock * SI, kSlots = 2 * kTile;
+  __shared__ unsigned long long lkey[kSlots];
+  __shared__ uint32_t lmin[kSlots], lcnt[kSlots], lslot[kSlots];
+  for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
     lkey[s] = 0ull;
     lmin[s] = 0xffffffffu;
     lcnt[s] = 0u;
   }
   __syncthreads();
-  uint64_t h[kSigItems];
-  uint32_t frag[kSigItems], lp[kSigItems], jj[kSigItems], gg[kSigItems], glo[kSigItems], ghi[kSigItems];
-  bool valid[kSigItems];
+  uint64_t h[SI];
+  uint32_t frag[SI], lp[SI], jj[SI], gg[SI], glo[SI], ghi[SI];
+  bool valid[SI];
 #pragma unroll
-  for (int e = 0; e < kSigItems; ++e) {
-    const uint32_t j = blockIdx.x * kSigTile + e * kBlock + threadIdx.x;
+  for (int e = 0; e < SI; ++e) {
+    const uint32_t j = blockIdx.x * kTile + e * kBlock + threadIdx.x;
     jj[e] = j;
     gg[e] = 0;
     glo[e] = 0;
@@ -511,11 +513,11 @@ __global__ __launch_bounds__(kBlock) void k_signature(
       frag[e] = (uint32_t)(hh >> 32) | 1u;
       lk = hh | (1ull << 63);  // hash keys and exact keys (< 2^32) never meet
     }
-    uint32_t p = (uint32_t)h[e] & (kLocalSlots - 1);
+    uint32_t p = (uint32_t)h[e] & (kSlots - 1);
     while (true) {
       const unsigned long long prev = atomicCAS(&lkey[p], 0ull, lk);
       if (prev == 0ull || prev == lk) break;
-      p = (p + 1) & (kLocalSlots - 1);
+      p = (p + 1) & (kSlots - 1);
     }
     lp[e] = p;
     atomicMin(&lmin[p], g);
@@ -524,13 +526,13 @@ __global__ __launch_bounds__(kBlock) void k_signature(
   __syncthreads();
   const uint64_t mask = (1ull << tbits) - 1ull;
 #pragma unroll
-  for (int e = 0; e < kSigItems; ++e) {
+  for (int e = 0; e < SI; ++e) {
     if (valid[e] && lmin[lp[e]] == gg[e])
       lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], gg[e], lcnt[lp[e]] > 1u, glo[e], ghi[e], ctrl);
   }
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < kSigItems; ++e)
+  for (int e = 0; e < SI; ++e)
     if (valid[e]) slot_of[jj[e]] = lslot[lp[e]];
 }
 
@@ -1009,20 +1011,37 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) 
 }
 
 namespace {
+template <bool BATCH, int SI>
+void launch_signature_si(int dw, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
+                         const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
+                         const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
+                         Ctrl* ctrl, hipStream_t s) {
+  const dim3 grid(grid_for(m, kBlock * SI));
+  if (dw == 1)
+    hipLaunchKernelGGL((k_signature<BATCH, 1, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+                       block, dense, table, tbits, slot_of, salt, ctrl);
+  else if (dw == 2)
+    hipLaunchKernelGGL((k_signature<BATCH, 2, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+                       block, dense, table, tbits, slot_of, salt, ctrl);
+  else
+    hipLaunchKernelGGL((k_signature<BATCH, 4, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
+                       block, dense, table, tbits, slot_of, salt, ctrl);
+}
+
 template <bool BATCH>
-void launch_signature_w(int dw, dim3 grid, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
+void launch_signature_w(int dw, int variant, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                         const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                         const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
                         Ctrl* ctrl, hipStream_t s) {
-  if (dw == 1)
-    hipLaunchKernelGGL((k_signature<BATCH, 1>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl);
-  else if (dw == 2)
-    hipLaunchKernelGGL((k_signature<BATCH, 2>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl);
+  if (variant == 0)
+    launch_signature_si<BATCH, 1>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
+                                  ctrl, s);
+  else if (variant == 2)
+    launch_signature_si<BATCH, 4>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
+                                  ctrl, s);
   else
-    hipLaunchKernelGGL((k_signature<BATCH, 4>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl);
+    launch_signature_si<BATCH, 2>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
+                                  ctrl, s);
 }
 
 template <bool BATCH>
@@ -1041,14 +1060,13 @@ void launch_dense_w(int dw, uint32_t N, const uint32_t* inst_of, const InstDesc*
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
-                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, hipStream_t s) {
+                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s) {
   if (!m) return;
-  const dim3 grid(grid_for(m, kSigTile));
   if (batch)
-    launch_signature_w<true>(dense_width, grid, act, m, inst_of, desc, rows, block, dense, table, tbits,
+    launch_signature_w<true>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
                              slot_of, salt, ctrl, s);
   else
-    launch_signature_w<false>(dense_width, grid, act, m, inst_of, desc, rows, block, dense, table, tbits,
+    launch_signature_w<false>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
                               slot_of, salt, ctrl, s);
 }
 

@@ -34,6 +34,7 @@ EXPORTS = [
     "dfamin_create", "dfamin_destroy", "dfamin_minimize", "dfamin_minimize_device",
     "dfamin_minimize_batch", "dfamin_minimize_batch_device", "dfamin_submit", "dfamin_wait",
     "dfamin_cancel", "dfamin_status_str", "dfamin_set_profiling", "dfamin_get_kernel_stats",
+    "dfamin_set_tuning",
 ]
 
 
@@ -113,6 +114,8 @@ def load():
     lib.dfamin_set_profiling.restype = i32
     lib.dfamin_get_kernel_stats.argtypes = [vp, P(KernelStat), i32]
     lib.dfamin_get_kernel_stats.restype = i32
+    lib.dfamin_set_tuning.argtypes = [vp, i32]
+    lib.dfamin_set_tuning.restype = i32
     _lib = lib
     return lib
 
@@ -278,6 +281,14 @@ def dfamin_set_profiling(ctx, on=True):
     rc = load().dfamin_set_profiling(ctx.handle, 1 if on else 0)
     if rc != DFAMIN_OK:
         raise DfaminError(rc, "dfamin_set_profiling")
+
+
+def dfamin_set_tuning(ctx, variant=-1):
+    """-1: tune the signature tile per size class; 0, 1, 2: force 256, 512
+    or 1024 states per workgroup."""
+    rc = load().dfamin_set_tuning(ctx.handle, int(variant))
+    if rc != DFAMIN_OK:
+        raise DfaminError(rc, "dfamin_set_tuning")
 
 
 def dfamin_get_kernel_stats(ctx):

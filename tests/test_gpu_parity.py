@@ -272,3 +272,23 @@ def test_device_entry_point_with_torch_buffers(ctx):
     got = out.cpu().numpy().view(np.uint32)
     want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
     assert res["num_blocks"] == nb and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, -1])
+def test_signature_tile_variants_identical(ctx, variant):
+    """Every signature tile (256, 512, 1024 states per workgroup) and the
+    autotuned choice give the oracle's partition; sizes straddle each tile
+    and the tuning threshold (2^18 active states)."""
+    from paper_2410_22764_amd import dfamin
+    dfamin.dfamin_set_tuning(ctx, variant)
+    try:
+        for n, k in [(1, 2), (255, 2), (257, 3), (1023, 1), (1025, 4), (70001, 2), (300007, 3)]:
+            _check(ctx, W.random_dfa(n, k, seed=n + variant))
+        _check(ctx, W.permuted_chain_dfa(300000, 2, 4), "auto")
+        dfas = W.batch_mixed(seed=5, count=40, n_min=16, n_max=20000)
+        outs, results = dfamin.dfamin_minimize_batch(ctx, dfas, {"closure": "auto"})
+        for d, o, r in zip(dfas, outs, results):
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert r["num_blocks"] == nb and np.array_equal(o, want), d.name
+    finally:
+        dfamin.dfamin_set_tuning(ctx, -1)
