@@ -31,6 +31,19 @@ WORKLOADS = {
                          desc="random complete DFA, n=16384, |Sigma|=2, uniform delta, Bernoulli(0.5) accepting"),
     "deep_chain": dict(kind="chain", n=1 << 20, k=2, closure="on",
                        desc="chain DFA, n=2^20, |Sigma|=2 (second letter the identity), closure on"),
+    "fib30": dict(kind="fib", m=30, closure="auto",
+                  desc="Fib_30 of the paper's Table 2: unary, 2,178,309 states, accepting where the "
+                       "Fibonacci word w_31 has a 1",
+                  paper={"system": "NVIDIA TITAN RTX (Table 2)", "transPR_ms": 1109.3, "transPR_iterations": 914,
+                         "naivePR_ms": 141601.0, "sortPR": "timed out"}),
+    "bitsplitter23": dict(kind="bitsplitter", m=23, closure="auto",
+                          desc="B_23 of the paper's Table 2: 2^23 states, 22 letters",
+                          paper={"system": "NVIDIA TITAN RTX (Table 2)", "sortPR_ms": 5612.7,
+                                 "sortPR_iterations": 22, "transPR_ms": 1612.1, "naivePR_ms": 170.3}),
+    "bitsplitter26": dict(kind="bitsplitter", m=26, closure="auto",
+                          desc="B_26 of the paper's Table 2: 2^26 states, 25 letters",
+                          paper={"system": "NVIDIA TITAN RTX (Table 2)", "sortPR_ms": 59203.8,
+                                 "sortPR_iterations": 25, "transPR": "out of memory", "naivePR_ms": 1541.5}),
     "batch_mixed": dict(kind="batch", closure="auto",
                         desc="4096 DFAs, n log-uniform in [64, 65536], |Sigma| in 2..8, 25% permuted chains, "
                              "closure auto, one batched call per step"),
@@ -67,7 +80,28 @@ def make_input(spec, seed):
     from paper_2410_22764_amd import workloads as W
     if spec["kind"] == "random":
         return W.random_dfa(spec["n"], spec["k"], seed)
+    if spec["kind"] == "fib":
+        return W.fib_dfa(spec["m"])
+    if spec["kind"] == "bitsplitter":
+        return W.bitsplitter_dfa(spec["m"])
     return W.chain_dfa(spec["n"], spec["k"])
+
+
+def copy_peak_gbps(reps=5, mib=1024):
+    """Device-to-device copy rate on this GPU (bytes read + written / time)."""
+    import torch
+    src = torch.ones((mib << 20) // 4, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(spec, seed, budget_s=20.0):
@@ -78,6 +112,10 @@ def cpu_baseline(spec, seed, budget_s=20.0):
     n = spec.get("n", 0)
     if spec["kind"] == "random":
         d = W.random_dfa(min(n, 1 << 22), spec["k"], seed)
+    elif spec["kind"] == "fib":
+        d = W.fib_dfa(spec["m"])
+    elif spec["kind"] == "bitsplitter":
+        d = W.bitsplitter_dfa(min(spec["m"], 20))
     elif spec["kind"] == "batch":
         d = W.random_dfa(1 << 20, 5, seed)  # mean |Sigma| of the batch
     else:
@@ -297,6 +335,8 @@ def main():
         trans = d.n * d.k
         cfg = {"workload": f"{args.workload}: {spec['desc']}", "n": d.n, "k": d.k, "seed": args.seed,
                "closure": spec["closure"], "parallelism": "single GPU"}
+        if "paper" in spec:
+            cfg["paper_context"] = spec["paper"]
 
         def step():
             return dfamin.dfamin_minimize_device(ctx, d.n, d.k, delta.data_ptr(), accept.data_ptr(), d.q0,
@@ -350,11 +390,18 @@ def main():
         per_launch_ms = top["total_ms"] / max(top["launches"], 1)
         per_launch_bytes = top["alg_bytes"] / max(top["launches"], 1)
         achieved = per_launch_bytes / (per_launch_ms * 1e-3) / 1e9 if per_launch_ms > 0 else 0.0
+        traffic = load_traffic(top["name"], args.workload)
         roofline = {"bound": "hbm", "kernel": top["name"], "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": load_traffic(top["name"], args.workload),
+                    "traffic": traffic,
                     "avg_launch_us": round(per_launch_ms * 1e3, 2),
                     "alg_bytes_per_launch": round(per_launch_bytes)}
+        if traffic:
+            # measured HBM bytes per launch over the same launch time
+            roofline["traffic_GBps"] = round(traffic / (per_launch_ms * 1e-3) / 1e9, 1)
+            roofline["traffic_frac"] = round(roofline["traffic_GBps"] / HBM_PEAK_GBS, 4)
+        if not args.no_batch:
+            roofline["copy_GBps"] = round(copy_peak_gbps(), 1)
     batched = None
     if not args.no_batch and args.workload == "plain_large":
         batched = batched_vs_plain(ctx, args.seed)

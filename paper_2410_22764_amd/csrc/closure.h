@@ -17,27 +17,36 @@ struct ClosureSpec {
   uint32_t n = 0;
   const uint32_t* delta = nullptr;  // letter-major input rows (device)
   std::vector<uint32_t> letters;     // letters to close (non-identity ones)
-  uint32_t L = 0;                    // levels 1..L are built
-  uint32_t* storage = nullptr;       // letters.size() * L * n words (device)
+  uint32_t L = 0;                    // levels 1..L at most
 };
 
 // Scratch the builder may grow: ensure(buffer_index, bytes) returns the
 // device pointer (index 0: jobs, 1: job offsets, 2: flags, 3: per-workgroup
 // flags) or nullptr when memory runs out; host_flags(bytes) a pinned host
-// buffer.
+// buffer.  level_storage(bytes) returns device memory for a batch of closure
+// rows that must stay valid while the rows are used, or nullptr to stop
+// building (out of memory or over the caller's cap): the levels built so far
+// are kept, which is sound because any subset of closure letters preserves
+// the equivalence.
 struct ClosureScratch {
   std::function<void*(int, size_t)> ensure;
   std::function<void*(size_t)> host_flags;
+  std::function<void*(size_t)> level_storage;
 };
 
-// Builds levels 1..L of every letter of every spec with one launch per level
-// (dst[q] = src[src[q]]), then fills rows[w] with the device addresses of
-// the rows each instance keeps: per letter, levels 0..l-1 where l is the
-// first level that equals its predecessor or is the identity (every later
-// level would be equal to it, so it cannot split any further block).
+// Builds closure levels (dst[q] = src[src[q]]) for every letter of every
+// spec, level by level, one launch per level for all of them.  A letter
+// stops at the first level that equals its predecessor or is the identity
+// (every later level would equal it, so it cannot split any further block);
+// its rows are levels 0..l-1.  Levels are computed in batches of 1, 2, 4, ...
+// between host checks of those flags, and storage is requested per batch
+// for the letters still open, so letters that stop early cost one level.
+// Fills rows[w] with the device addresses of the rows instance w keeps and
+// depth[w] with the closure depth reached (L unless storage ran out).
 // Returns 0, or a negative DFAMIN_E_* code.
 int build_closure_levels(std::vector<ClosureSpec>& specs, const ClosureScratch& scratch,
-                         hipStream_t s, std::vector<std::vector<uint64_t>>& rows);
+                         hipStream_t s, std::vector<std::vector<uint64_t>>& rows,
+                         std::vector<uint32_t>& depth);
 
 inline uint32_t floor_log2_u32(uint32_t n) {
   uint32_t L = 0;

@@ -101,11 +101,12 @@ class Engine {
   std::vector<uint8_t> has_closure_;
   std::vector<uint32_t> row_base_;                // first row of each instance in rows_
   uint64_t N_ = 0;
-  uint64_t closure_used_ = 0;
+  std::vector<DevBuf> closure_bufs_;  // closure level storage, reused across calls
+  size_t closure_cursor_ = 0;
   // device buffers
   DevBuf d_desc_, d_rows_, d_jobs_, d_joboff_, d_flags_, d_inst_off_, d_minF_, d_minN_;
   DevBuf d_inst_of_, d_block_, d_act_, d_act2_, d_slot_of_, d_nb_, d_keep_, d_rank_;
-  DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_, d_closure_;
+  DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
   HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_;
 };

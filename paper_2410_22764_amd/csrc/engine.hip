@@ -120,10 +120,12 @@ Engine::~Engine() {
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
-                    &d_results_, &d_ctrl_, &d_closure_, &d_wgflags_, &d_part_, &d_dense_,
+                    &d_results_, &d_ctrl_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_counts_, &d_djobs_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
+  for (DevBuf& b : closure_bufs_)
+    if (b.p) (void)hipFree(b.p);
   HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
@@ -133,10 +135,11 @@ uint64_t Engine::device_bytes() const {
   const DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                           &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
-                          &d_results_, &d_ctrl_, &d_closure_, &d_wgflags_, &d_part_, &d_dense_,
+                          &d_results_, &d_ctrl_, &d_wgflags_, &d_part_, &d_dense_,
                           &d_counts_, &d_djobs_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
+  for (const DevBuf& b : closure_bufs_) t += b.cap;
   return t;
 }
 
@@ -220,12 +223,13 @@ int Engine::upload_layout(hipStream_t s) {
   return DFAMIN_OK;
 }
 
-// Partial transitive closure (Algorithm 5) for the listed instances; the
-// level storage is appended to this call's closure buffer.
+// Partial transitive closure (Algorithm 5) for the listed instances.  Level
+// storage comes from this call's list of level buffers, at most half of the
+// context's remaining budget: a closure cut short by that cap keeps the levels
+// it has (any subset of closure letters is sound).
 int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts,
                           hipStream_t s) {
   std::vector<ClosureSpec> specs(which.size());
-  uint64_t words = 0;
   for (size_t w = 0; w < which.size(); ++w) {
     const uint32_t i = which[w];
     uint32_t l = floor_log2_u32(in_[i].n);
@@ -234,33 +238,9 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
     specs[w].delta = in_[i].delta;
     specs[w].letters = nonid_[i];
     specs[w].L = l;
-    words += (uint64_t)nonid_[i].size() * l * in_[i].n;
   }
-  const uint64_t base = closure_used_;
-  if (words && d_closure_.cap < (base + words) * 4) {
-    if (base != 0) {
-      // keep the rows of earlier closures of this call valid
-      DevBuf nb;
-      TRY(ensure(nb, (base + words) * 4));
-      HIP(hipMemcpyAsync(nb.p, d_closure_.p, base * 4, hipMemcpyDeviceToDevice, s));
-      HIP(stream_wait(s));
-      const uint64_t old = reinterpret_cast<uint64_t>(d_closure_.p);
-      const uint64_t nw = reinterpret_cast<uint64_t>(nb.p);
-      for (auto& rl : inst_rows_)
-        for (auto& r : rl)
-          if (r >= old && r < old + base * 4) r = r - old + nw;
-      (void)hipFree(d_closure_.p);
-      ctx_->used -= d_closure_.cap;
-      d_closure_ = nb;
-    } else {
-      TRY(ensure(d_closure_, words * 4));
-    }
-  }
-  uint64_t off = base;
-  for (auto& sp : specs) {
-    sp.storage = d_closure_.as<uint32_t>() + off;
-    off += (uint64_t)sp.letters.size() * sp.L * sp.n;
-  }
+  const uint64_t cap = ctx_->budget > ctx_->used ? (ctx_->budget - ctx_->used) / 2 : 0;
+  uint64_t taken = 0;
   ClosureScratch scratch;
   DevBuf* bufs[4] = {&d_jobs_, &d_joboff_, &d_flags_, &d_wgflags_};
   scratch.ensure = [&](int b, size_t bytes) -> void* {
@@ -269,13 +249,23 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
   scratch.host_flags = [&](size_t bytes) -> void* {
     return ensure_host(h_flags_, bytes) == DFAMIN_OK ? h_flags_.p : nullptr;
   };
+  scratch.level_storage = [&](size_t bytes) -> void* {
+    if (taken + bytes > cap) return nullptr;
+    if (closure_cursor_ == closure_bufs_.size()) closure_bufs_.emplace_back();
+    DevBuf& b = closure_bufs_[closure_cursor_];
+    if (ensure(b, bytes) != DFAMIN_OK) return nullptr;
+    ++closure_cursor_;
+    taken += bytes;
+    return b.p;
+  };
   std::vector<std::vector<uint64_t>> rows;
+  std::vector<uint32_t> depth;
   if (ctx_->prof.enabled()) {
     double bytes = 0;
     for (auto& sp : specs) bytes += 12.0 * sp.letters.size() * sp.L * sp.n;
     ctx_->prof.begin(s, "closure", bytes);
   }
-  const int rc = build_closure_levels(specs, scratch, s, rows);
+  const int rc = build_closure_levels(specs, scratch, s, rows, depth);
   if (ctx_->prof.enabled()) {
     ctx_->prof.end(s);
     ctx_->prof.collect();
@@ -283,10 +273,9 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
   if (rc != DFAMIN_OK) return rc;
   for (size_t w = 0; w < which.size(); ++w) {
     inst_rows_[which[w]] = rows[w];
-    levels_[which[w]] = specs[w].L;
+    levels_[which[w]] = depth[w];
     has_closure_[which[w]] = 1;
   }
-  closure_used_ = base + words;
   return DFAMIN_OK;
 }
 
@@ -302,7 +291,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
   if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
   N_ = N;
-  closure_used_ = 0;
+  closure_cursor_ = 0;
   Profiler& prof = ctx_->prof;
 
   // ---- 1. validation + identity letters: one row job per (instance, letter)
@@ -562,7 +551,16 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
       std::memcpy(h_desc_.p, desc_.data(), I * sizeof(InstDesc));
       HIP(hipMemcpyAsync(d_desc_.p, h_desc_.p, I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
     }
-    const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * m));
+    // Table: twice the number of groups this round can form, at most m.  An
+    // exact-key instance forms at most 2^((kp+1) * ebits) groups.
+    uint64_t groups = 0;
+    for (size_t i = 0; i < I && groups < m; ++i) {
+      if (!active[i]) continue;
+      const uint64_t width = (desc_[i].kp + 1ull) * desc_[i].ebits;
+      groups += (desc_[i].ebits && width < 32) ? std::min<uint64_t>(in_[i].n, 1ull << width) : in_[i].n;
+    }
+    groups = std::min<uint64_t>(groups, m);
+    const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * groups));
     const uint64_t tsize = 1ull << tbits;
     TRY(ensure(d_table_, tsize * sizeof(Slot)));
     const uint32_t ntiles = (uint32_t)((m + kScanTile - 1) / kScanTile);

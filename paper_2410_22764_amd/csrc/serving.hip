@@ -176,8 +176,8 @@ struct Resident {
   void* d_accept = nullptr;
   void* d_out = nullptr;
   void* d_sig = nullptr;
-  void* d_closure = nullptr;
-  size_t sz_delta = 0, sz_accept = 0, sz_out = 0, sz_sig = 0, sz_closure = 0;
+  std::vector<std::pair<void*, size_t>> closure_bufs;  // closure level storage
+  size_t sz_delta = 0, sz_accept = 0, sz_out = 0, sz_sig = 0;
   std::vector<uint32_t> nonid;
   std::vector<uint64_t> rows;
   uint32_t rounds = 0;
@@ -346,7 +346,7 @@ struct Serving::Impl {
     pool.free(r->d_accept, r->sz_accept);
     pool.free(r->d_out, r->sz_out);
     pool.free(r->d_sig, r->sz_sig);
-    pool.free(r->d_closure, r->sz_closure);
+    for (auto& cb : r->closure_bufs) pool.free(cb.first, cb.second);
     arena.release(r->off, r->req->n);
     slots[r->slot] = nullptr;
     desc[r->slot] = InstDesc{};
@@ -418,33 +418,32 @@ struct Serving::Impl {
     return sc;
   }
 
-  // Closure (Algorithm 5) for the given residents; swaps their signature
-  // buffers for ones sized to the new letter count.
+  // Closure (Algorithm 5) for the given residents, one resident at a time so
+  // that each one's level storage comes from the pool in its own pieces (and
+  // goes back at retire); swaps their signature buffers for ones sized to the
+  // new letter count.
   int build_closures(const std::vector<Resident*>& rs) {
-    std::vector<ClosureSpec> specs(rs.size());
-    for (size_t w = 0; w < rs.size(); ++w) {
-      Resident* r = rs[w];
+    for (Resident* r : rs) {
+      std::vector<ClosureSpec> specs(1);
       uint32_t L = floor_log2_u32(r->req->n);
       if (r->req->opts.max_levels && r->req->opts.max_levels < L) L = r->req->opts.max_levels;
-      specs[w].n = r->req->n;
-      specs[w].delta = static_cast<const uint32_t*>(r->d_delta);
-      specs[w].letters = r->nonid;
-      specs[w].L = L;
-      const size_t words = (size_t)r->nonid.size() * L * r->req->n;
-      if (words) {
-        r->sz_closure = words * 4;
-        r->d_closure = pool.alloc(r->sz_closure);
-        if (!r->d_closure) return DFAMIN_E_NOMEM;
-      }
-      specs[w].storage = static_cast<uint32_t*>(r->d_closure);
-      r->levels = L;
-    }
-    std::vector<std::vector<uint64_t>> rows;
-    int rc = build_closure_levels(specs, scratch(), stream, rows);
-    if (rc != DFAMIN_OK) return rc;
-    for (size_t w = 0; w < rs.size(); ++w) {
-      Resident* r = rs[w];
-      r->rows = rows[w];
+      specs[0].n = r->req->n;
+      specs[0].delta = static_cast<const uint32_t*>(r->d_delta);
+      specs[0].letters = r->nonid;
+      specs[0].L = L;
+      ClosureScratch sc = scratch();
+      sc.level_storage = [this, r](size_t bytes) -> void* {
+        if (pool.live() + bytes > pool.budget()) return nullptr;
+        void* p = pool.alloc(bytes);
+        if (p) r->closure_bufs.emplace_back(p, bytes);
+        return p;
+      };
+      std::vector<std::vector<uint64_t>> rows;
+      std::vector<uint32_t> depth;
+      int rc = build_closure_levels(specs, sc, stream, rows, depth);
+      if (rc != DFAMIN_OK) return rc;
+      r->rows = rows[0];
+      r->levels = depth[0];
       r->closure = true;
       pool.free(r->d_sig, r->sz_sig);
       r->sz_sig = (size_t)r->req->n * (r->rows.size() + 1) * 4;

@@ -71,3 +71,31 @@ def test_plain_single_seeds(ctx):
         out, res = dfamin.dfamin_minimize(ctx, d, "auto")
         assert res["num_blocks"] == e["num_blocks"] and digest(out) == e["sha"]
         assert res["refine_rounds"] == e["refine_rounds"]
+
+
+@pytest.mark.parametrize("m", [20, 23, 26])
+def test_table2_bitsplitters(ctx, m):
+    """B_m at the sizes of the paper's Table 2 (B_24..B_26 ran out of memory
+    there with the closure).  Closed forms: 2^m classes, all singletons (so
+    the canonical output is the identity), m - 1 refining rounds.  Every
+    closure level above 0 equals level 0 (a_j applied twice is a_j), so the
+    closure keeps only the m - 1 letters."""
+    from paper_2410_22764_amd import dfamin
+    print(f"[case] B_{m}", flush=True)
+    d = W.bitsplitter_dfa(m)
+    out, res = dfamin.dfamin_minimize(ctx, d, "auto")
+    assert res["num_blocks"] == 2 ** m
+    assert np.array_equal(out, np.arange(2 ** m, dtype=np.uint32))
+    assert res["refine_rounds"] == m - 1
+    assert res["closure_letters"] == m - 1 and res["closure_levels"] == m
+
+
+def test_table2_fib30(ctx):
+    """Fib_30 (2,178,309 states, unary): every state is its own class."""
+    from paper_2410_22764_amd import dfamin
+    print("[case] Fib_30", flush=True)
+    d = W.fib_dfa(30)
+    assert d.n == 2178309
+    out, res = dfamin.dfamin_minimize(ctx, d, "auto")
+    assert res["num_blocks"] == d.n
+    assert np.array_equal(out, np.arange(d.n, dtype=np.uint32))
