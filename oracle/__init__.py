@@ -57,6 +57,8 @@ def _load():
     lib.oracle_moore_partial.restype = ctypes.c_int
     lib.oracle_moore_from.argtypes = [u32, u32, _U32P, _U32P, u32, _U32P, _U32P, _U32P]
     lib.oracle_moore_from.restype = ctypes.c_int
+    lib.oracle_naive.argtypes = [u32, u32, _U32P, _U8P, u32, _U32P, _U32P, _U32P]
+    lib.oracle_naive.restype = ctypes.c_int
     lib.oracle_closure.argtypes = [u32, u32, _U32P, u32, _U32P]
     lib.oracle_closure.restype = ctypes.c_int
     lib.oracle_floor_log2.argtypes = [u32]
@@ -151,6 +153,23 @@ def moore_from(n, k, delta, init, max_rounds=0):
     _check(_load().oracle_moore_from(n, k, dp, ip, max_rounds, out.ctypes.data_as(_U32P),
                                      ctypes.byref(nb), ctypes.byref(rr)), "moore_from")
     return out, nb.value, rr.value
+
+
+def naive(n, k, delta, accept, max_iter=0):
+    """Algorithm 2 (naivePR): (canonical blocks, count, while-loop iterations)."""
+    d, dp = _u32(delta)
+    a, ap = _u8(accept)
+    out = np.empty(n, np.uint32)
+    nb, it = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_load().oracle_naive(n, k, dp, ap, max_iter, out.ctypes.data_as(_U32P),
+                                ctypes.byref(nb), ctypes.byref(it)), "naive")
+    return out, nb.value, it.value
+
+
+def naive_closure(n, k, delta, accept, L=None, max_iter=0):
+    """The paper's transPR: naivePR on the closure automaton (alphabet Sigma^T)."""
+    rows = closure(n, k, delta, L)
+    return naive(n, rows.shape[0], rows.reshape(-1), accept, max_iter)
 
 
 def closure(n, k, delta, L=None):

@@ -314,6 +314,72 @@ int oracle_moore_from(uint32_t n, uint32_t k, const uint32_t *delta,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Algorithm 2 (naivePR, Section 3.2): blocks are named by a leader state.
+ * Every iteration, each state q that differs from its leader L = block[q]
+ * in some successor block (block[delta(q,a)] != block[delta(L,a)]) takes
+ * part in electing new_leader[L]; then every such state moves to block
+ * new_leader[L].  The paper elects by concurrent writes (any writer may
+ * win); here the least candidate wins, which keeps every leader the least
+ * member of its block and makes the iteration count reproducible.  Both
+ * phases read the partition of the start of the iteration (the synchronous
+ * parallel step the algorithm is written for).  *iterations counts the
+ * while-loop iterations including the last, which finds the partition
+ * stable.  The initial leaders are the least accepting and the least
+ * non-accepting state. */
+int oracle_naive(uint32_t n, uint32_t k, const uint32_t *delta,
+                 const uint8_t *accept, uint32_t max_iter, uint32_t *out,
+                 uint32_t *num_blocks, uint32_t *iterations) {
+  int rc = check_args(n, k, delta, accept, out);
+  if (rc) return rc;
+  uint32_t *block = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint32_t *new_leader = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint8_t *differs = (uint8_t *)malloc(n);
+  if (!block || !new_leader || !differs) {
+    free(block); free(new_leader); free(differs);
+    return -2;
+  }
+  uint32_t qf = n, qn = n;
+  for (uint32_t q = 0; q < n; ++q) {
+    if (ACC(accept, q)) { if (qf == n) qf = q; }
+    else if (qn == n) qn = q;
+  }
+  for (uint32_t q = 0; q < n; ++q) {
+    block[q] = ACC(accept, q) ? qf : qn;
+    new_leader[q] = UINT32_MAX;
+  }
+  uint32_t iter = 0;
+  int stable = 0;
+  while (!stable) {
+    if (max_iter && iter >= max_iter) {
+      free(block); free(new_leader); free(differs);
+      return -3;
+    }
+    ++iter;
+    stable = 1;
+    /* phase 1: compare with the leader, elect the new leader */
+    for (uint32_t q = 0; q < n; ++q) {
+      const uint32_t L = block[q];
+      differs[q] = 0;
+      for (uint32_t a = 0; a < k; ++a)
+        if (block[delta[(size_t)a * n + q]] != block[delta[(size_t)a * n + L]]) differs[q] = 1;
+      if (differs[q] && q < new_leader[L]) new_leader[L] = q;
+    }
+    /* phase 2: split the differing states from their leader */
+    for (uint32_t q = 0; q < n; ++q) {
+      if (!differs[q]) continue;
+      block[q] = new_leader[block[q]];
+      stable = 0;
+    }
+    for (uint32_t q = 0; q < n; ++q) new_leader[q] = UINT32_MAX;
+  }
+  const uint32_t c = oracle_canonicalize(n, block, out);
+  if (num_blocks) *num_blocks = c;
+  if (iterations) *iterations = iter;
+  free(block); free(new_leader); free(differs);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Algorithm 5, closure part: level 0 is delta; level i is level i-1
  * applied twice (pointer jumping). */
 int oracle_closure(uint32_t n, uint32_t k, const uint32_t *delta, uint32_t L,

@@ -67,6 +67,16 @@ int oracle_moore_from(uint32_t n, uint32_t k, const uint32_t *delta,
                       const uint32_t *init, uint32_t max_rounds, uint32_t *out,
                       uint32_t *num_blocks, uint32_t *refine_rounds);
 
+/* Algorithm 2 (naivePR, Section 3.2): leader-based refinement.  Blocks are
+ * named by a leader state; every iteration, the states that differ from
+ * their leader in some successor block elect a new leader (here: the least
+ * of them) and move to its block.  *iterations = while-loop iterations,
+ * the final one (that finds the partition stable) included.  Fails with -3
+ * if more than max_iter iterations would run (0 = no cap). */
+int oracle_naive(uint32_t n, uint32_t k, const uint32_t *delta,
+                 const uint8_t *accept, uint32_t max_iter, uint32_t *out,
+                 uint32_t *num_blocks, uint32_t *iterations);
+
 /* Partial transitive closure of the paper's Algorithm 5 (Section 3.4):
  * rows[(a*(L+1) + i)*n + q] = delta^T(q, a^(2^i)) for a < k, 0 <= i <= L,
  * where level 0 is delta itself and level i applies level i-1 twice.

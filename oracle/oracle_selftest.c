@@ -23,7 +23,7 @@ uint64_t oracle_exhaustive_check(uint32_t n, uint32_t k, uint64_t *mismatches) {
   uint32_t nk = n * k;
   uint32_t delta[12];
   uint8_t acc[1];
-  uint32_t o1[8], o2[8], o3[8], o4[8];
+  uint32_t o1[8], o2[8], o3[8], o4[8], o5[8];
   uint64_t checked = 0, bad = 0;
   memset(delta, 0, sizeof(delta));
   for (;;) {
@@ -38,6 +38,11 @@ uint64_t oracle_exhaustive_check(uint32_t n, uint32_t k, uint64_t *mismatches) {
                !memcmp(o2, o3, n * sizeof(uint32_t));
       /* Moore refines at most n-2 times for n >= 2, never for n = 1. */
       if (r > (n >= 2 ? n - 2 : 0)) ok = 0;
+      /* Algorithm 2 reaches the same partition; each of its iterations
+       * but the last adds at least one block, so it runs at most n. */
+      uint32_t c5 = 0, it5 = 0;
+      int e5 = oracle_naive(n, k, delta, acc, 0, o5, &c5, &it5);
+      ok = ok && !e5 && c5 == c1 && !memcmp(o1, o5, n * sizeof(uint32_t)) && it5 >= 1 && it5 <= n;
       if (n <= 4) {
         int e4 = oracle_word_equivalence(n, k, delta, acc, o4, &c4);
         ok = ok && !e4 && c4 == c1 && !memcmp(o1, o4, n * sizeof(uint32_t));

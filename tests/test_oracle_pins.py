@@ -347,3 +347,66 @@ def test_bad_input_rejected():
     bad[5] = 10
     with pytest.raises(oracle.OracleError):
         oracle.hopcroft(d.n, d.k, bad, d.accept)
+
+
+# ---- Algorithm 2 (naivePR) --------------------------------------------------
+
+def test_table2_naive_iterations_fib20():
+    """Table 2 prints 17,710 naivePR iterations for Fib_20 (N = 17,711): the
+    oracle's Algorithm 2 runs exactly that many while-loop iterations (the
+    last one finds the partition stable) and reaches the minimal size."""
+    r = [x for x in _read_rows("table2.csv") if x["name"] == "Fib_20"][0]
+    d = W.fib_dfa(20)
+    out, nb, it = oracle.naive(d.n, d.k, d.delta, d.accept)
+    assert it == int(r["iter_naive"]) == 17710
+    assert nb == int(r["size_output"])
+    want, _ = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+    assert np.array_equal(out, want)
+
+
+@pytest.mark.parametrize("m", [4, 6, 8, 10, 12, 14])
+def test_naive_fib_iterations_closed_form(m):
+    """Fib_m: one state splits off per iteration, N - 1 iterations in all
+    (the pattern of Table 2's naivePR column)."""
+    d = W.fib_dfa(m)
+    out, nb, it = oracle.naive(d.n, d.k, d.delta, d.accept)
+    assert nb == d.n and it == d.n - 1
+
+
+def test_table2_naive_iterations_bitsplitters():
+    """Table 2 prints m - 1 naivePR iterations for B_m; counting the final
+    iteration that finds the partition stable (the convention the Fib rows
+    of the same table follow) gives m."""
+    for r in _read_rows("table2.csv"):
+        if not r["name"].startswith("B_"):
+            continue
+        m = int(r["name"].split("_")[1])
+        assert int(r["iter_naive"]) == m - 1
+        if m <= 15:
+            d = W.bitsplitter_dfa(m)
+            out, nb, it = oracle.naive(d.n, d.k, d.delta, d.accept)
+            assert nb == 2 ** m and it == m
+            assert np.array_equal(out, np.arange(2 ** m))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_naive_matches_hopcroft_on_random_and_coarse(seed):
+    n = [1, 2, 50, 333, 1000, 4097, 5000, 2500][seed]
+    k = 1 + seed % 4
+    d = W.random_dfa(n, k, seed + 100)
+    if seed % 2:
+        acc = np.zeros(n, bool)
+        acc[:: 7] = True
+        d.accept = W.pack_accept(acc)
+    want, nbw = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+    out, nb, it = oracle.naive(d.n, d.k, d.delta, d.accept)
+    assert nb == nbw and np.array_equal(out, want)
+    assert 1 <= it <= max(n, 1)
+    out2, nb2, _ = oracle.naive_closure(d.n, d.k, d.delta, d.accept)
+    assert np.array_equal(out2, want)
+
+
+def test_naive_iteration_cap():
+    d = W.chain_dfa(40, 1)
+    with pytest.raises(Exception):
+        oracle.naive(d.n, d.k, d.delta, d.accept, max_iter=10)
