@@ -76,11 +76,25 @@ typedef struct {
 #define DFAMIN_CLOSURE_ON    1u  /* build Sigma^T before the first round */
 #define DFAMIN_CLOSURE_AUTO  2u  /* refine on Sigma; build Sigma^T if still refining after auto_rounds rounds */
 
+/* Refinement method. */
+#define DFAMIN_METHOD_SIGNATURE 0u  /* signature rounds (Section 3.3, Algorithm 4): each round groups
+                                       equal (own block, successor blocks) signatures */
+#define DFAMIN_METHOD_LEADER    1u  /* leader-based rounds (Section 3.2, Algorithm 2, naivePR): each round
+                                       splits off the states that differ from their block's leader; with
+                                       closure ON this is the paper's transPR (Algorithm 5) */
+
+/* Flags. */
+#define DFAMIN_FLAG_NO_GRAPH 1u     /* leader rounds: launch kernels directly instead of replaying a
+                                       captured HIP graph of rounds (same results) */
+
 typedef struct {
   uint32_t closure;      /* DFAMIN_CLOSURE_*; a zeroed struct means OFF */
   uint32_t max_levels;   /* closure levels 0..L with L = min(floor(log2 n), max_levels); 0 = no cap */
   uint32_t auto_rounds;  /* AUTO: plain rounds before the closure is built; 0 = default (8) */
   uint32_t max_rounds;   /* give up with DFAMIN_E_INTERNAL after this many rounds; 0 = n + 1 */
+  uint32_t method;       /* DFAMIN_METHOD_*; 0 = signature rounds.  The serving entry points
+                            (dfamin_submit) accept DFAMIN_METHOD_SIGNATURE only */
+  uint32_t flags;        /* DFAMIN_FLAG_* bits; 0 = none */
 } dfamin_opts;
 
 typedef struct {

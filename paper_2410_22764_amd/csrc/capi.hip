@@ -30,7 +30,9 @@ int check_dfa_shape(const dfamin_dfa* d) {
 }
 
 int check_opts(const dfamin_opts* o) {
-  if (o && o->closure > DFAMIN_CLOSURE_AUTO) return DFAMIN_E_INVAL;
+  if (o && (o->closure > DFAMIN_CLOSURE_AUTO || o->method > DFAMIN_METHOD_LEADER ||
+            (o->flags & ~DFAMIN_FLAG_NO_GRAPH)))
+    return DFAMIN_E_INVAL;
   return DFAMIN_OK;
 }
 
@@ -290,6 +292,7 @@ int dfamin_submit(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin_opts
   if (!ctx || !ticket) return DFAMIN_E_INVAL;
   int rc = check_dfa_shape(host_dfa);
   if (rc == DFAMIN_OK) rc = check_opts(opts);
+  if (rc == DFAMIN_OK && opts && opts->method != DFAMIN_METHOD_SIGNATURE) rc = DFAMIN_E_INVAL;
   if (rc != DFAMIN_OK) return rc;
   if (!ctx->c.serving) {
     ctx->c.serving = new (std::nothrow) dfamin::Serving(&ctx->c);

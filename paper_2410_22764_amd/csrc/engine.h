@@ -87,6 +87,8 @@ class Engine {
   int ensure(DevBuf& b, size_t bytes);
   int ensure_host(HostBuf& b, size_t bytes);
   int build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts, hipStream_t s);
+  int signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
+  int leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
   int upload_layout(hipStream_t s);
   int check_hip(hipError_t e);
 
@@ -109,6 +111,19 @@ class Engine {
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
   HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_;
+  // captured leader-election rounds, reused while pointers and sizes match
+  struct GraphKey {
+    uint32_t n, ninst, parity;
+    const void *inst_of, *desc, *rows, *block, *nl0, *nl1, *differs, *changed, *refine, *ctrl;
+    hipStream_t stream;
+    bool operator==(const GraphKey& o) const {
+      return n == o.n && ninst == o.ninst && parity == o.parity && inst_of == o.inst_of && desc == o.desc &&
+             rows == o.rows && block == o.block && nl0 == o.nl0 && nl1 == o.nl1 && differs == o.differs &&
+             changed == o.changed && refine == o.refine && ctrl == o.ctrl && stream == o.stream;
+    }
+  };
+  GraphKey graph_key_{};
+  hipGraphExec_t graph_exec_ = nullptr;
 };
 
 // Signature-tile autotuner state of a context: a forced variant, or the

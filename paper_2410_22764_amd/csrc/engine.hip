@@ -117,6 +117,7 @@ int Profiler::copy_stats(dfamin_kernel_stat* out, int cap) const {
 
 // ------------------------------------------------------------------ Engine
 Engine::~Engine() {
+  if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
@@ -279,153 +280,14 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
   return DFAMIN_OK;
 }
 
-int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
-                std::vector<InstOutcome>& res) {
-  in_ = in;
+// Signature rounds (Algorithm 4, Section 3.3) over the active states until no
+// instance splits a block.
+int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s) {
   const size_t I = in_.size();
-  res.assign(I, InstOutcome{});
-  if (I == 0) return DFAMIN_OK;
   const bool batch = I > 1;
-  uint64_t N = 0;
-  uint32_t nmax = 0;
-  for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
-  if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
-  N_ = N;
-  closure_cursor_ = 0;
+  const uint64_t N = N_;
   Profiler& prof = ctx_->prof;
-
-  // ---- 1. validation + identity letters: one row job per (instance, letter)
-  std::vector<RowJob> jobs;
-  std::vector<uint32_t> joboff, job_inst;
-  uint32_t wgs = 0;
-  for (size_t i = 0; i < I; ++i)
-    for (uint32_t a = 0; a < in_[i].k; ++a) {
-      RowJob J;
-      J.src = reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n;
-      J.dst = 0;
-      J.n = in_[i].n;
-      J.flag_idx = (uint32_t)jobs.size();
-      joboff.push_back(wgs);
-      wgs += (J.n + kRowTile - 1) / kRowTile;
-      jobs.push_back(J);
-      job_inst.push_back((uint32_t)i);
-    }
-  TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
-  TRY(ensure(d_joboff_, joboff.size() * 4));
-  TRY(ensure(d_flags_, jobs.size() * 4));
-  TRY(ensure(d_wgflags_, (size_t)wgs * 4));
-  TRY(ensure_host(h_flags_, jobs.size() * 4));
-  HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
-  HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
-  HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
-  {
-    double bytes = 0;
-    for (auto& x : in_) bytes += 4.0 * x.n * x.k;
-    prof.begin(s, "validate", bytes);
-    launch_row_check(d_jobs_.as<RowJob>(), d_joboff_.as<uint32_t>(), (uint32_t)jobs.size(), wgs,
-                     d_wgflags_.as<uint32_t>(), d_flags_.as<uint32_t>(), s);
-    prof.end(s);
-    HIP(hipGetLastError());
-  }
-  HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
-  HIP(stream_wait(s));
-  prof.collect();
-  bool any_bad = false;
-  nonid_.assign(I, {});
-  {
-    const uint32_t* f = h_flags_.as<uint32_t>();
-    for (size_t j = 0; j < jobs.size(); ++j)
-      if (f[j] & kFlagBad) { res[job_inst[j]].status = DFAMIN_E_BAD_DFA; any_bad = true; }
-    // jobs are ordered (instance, letter): job j of instance i is letter j - first(i)
-    size_t j = 0;
-    for (size_t i = 0; i < I; ++i) {
-      std::vector<uint32_t> letters;
-      for (uint32_t a = 0; a < in_[i].k; ++a, ++j)
-        if (f[j] & kFlagNonId) letters.push_back(a);
-      nonid_[i] = letters;
-    }
-  }
-  if (any_bad) return DFAMIN_E_BAD_DFA;
-
-  // ---- 2. descriptors and signature letters
-  desc_.assign(I, InstDesc{});
-  inst_rows_.assign(I, {});
-  levels_.assign(I, 0);
-  has_closure_.assign(I, 0);
-  {
-    uint64_t off = 0;
-    for (size_t i = 0; i < I; ++i) {
-      InstDesc& D = desc_[i];
-      D.state_off = (uint32_t)off;
-      D.n = in_[i].n;
-      D.k = in_[i].k;
-      D.q0 = in_[i].q0;
-      D.accept = reinterpret_cast<uint64_t>(in_[i].accept);
-      D.out = reinterpret_cast<uint64_t>(in_[i].out);
-      off += in_[i].n;
-      for (uint32_t a : nonid_[i])
-        inst_rows_[i].push_back(reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n);
-    }
-  }
-  {
-    std::vector<uint32_t> on;
-    for (size_t i = 0; i < I; ++i)
-      if (in_[i].closure == DFAMIN_CLOSURE_ON) on.push_back((uint32_t)i);
-    if (!on.empty()) TRY(build_closure(on, opts, s));
-  }
-
-  // ---- 3. buffers sized for N
-  TRY(ensure(d_block_, N * 4));
-  TRY(ensure(d_act_, N * 4));
-  TRY(ensure(d_act2_, N * 4));
-  TRY(ensure(d_slot_of_, N * 4));
-  TRY(ensure(d_nb_, N * 4));
-  TRY(ensure(d_keep_, N));
-  TRY(ensure(d_rank_, (N + 1) * 4));
-  const uint64_t max_tiles = (N + kScanTile - 1) / kScanTile + 1;
-  TRY(ensure(d_status_, max_tiles * 8));
-  TRY(ensure(d_changed_, I * 4));
-  TRY(ensure(d_refine_, I * 4));
-  TRY(ensure(d_minF_, I * 4));
-  TRY(ensure(d_minN_, I * 4));
-  TRY(ensure(d_results_, I * sizeof(ResultDev)));
-  TRY(ensure(d_ctrl_, sizeof(Ctrl)));
-  TRY(ensure(d_inst_off_, I * 4));
-  if (batch) TRY(ensure(d_inst_of_, N * 4));
-  TRY(ensure(d_counts_, I * 4));
-  TRY(ensure_host(h_ctrl_, sizeof(Ctrl)));
-  TRY(ensure_host(h_results_, I * sizeof(ResultDev)));
-  TRY(ensure_host(h_counts_, I * 4));
-  TRY(upload_layout(s));
-  // workgroup offsets of the per-instance init jobs
-  std::vector<uint32_t> inst_off(I);
-  uint32_t init_wgs = 0;
-  for (size_t i = 0; i < I; ++i) {
-    inst_off[i] = init_wgs;
-    init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
-  }
-  HIP(hipMemcpyAsync(d_inst_off_.p, inst_off.data(), I * 4, hipMemcpyHostToDevice, s));
-  TRY(ensure(d_part_, (size_t)init_wgs * 8));
-  HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
-  HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
-  HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
-
-  // ---- 4. initial partition {F, Q\F}
-  prof.begin(s, "init_minmax", (double)N / 8.0);
-  launch_init_minmax(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
-                     d_part_.as<unsigned long long>(), d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(), s);
-  prof.end(s);
-  prof.begin(s, "init_block", (8.125 + (batch ? 4.0 : 0.0)) * (double)N);
-  launch_init_block(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
-                    d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(),
-                    batch ? d_inst_of_.as<uint32_t>() : nullptr, d_block_.as<uint32_t>(),
-                    d_act_.as<uint32_t>(), s);
-  prof.end(s);
-  HIP(hipGetLastError());
-
-  // ---- 5. rounds
   const uint32_t auto_rounds = opts.auto_rounds ? opts.auto_rounds : kDefaultAutoRounds;
-  const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
   bool any_auto = false;
   for (auto& x : in_) any_auto |= (x.closure == DFAMIN_CLOSURE_AUTO);
   uint64_t m = N;
@@ -706,6 +568,265 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
     std::swap(cur, nxt);
     m = c.m_next;
     if (!c.any_changed) break;
+  }
+
+  return DFAMIN_OK;
+}
+
+// Leader-election rounds (Algorithm 2, Section 3.2) over all states.  Rounds
+// are queued ahead of the host -- each one returns at once after a round that
+// split nothing (ctrl->stop) -- and, unless DFAMIN_FLAG_NO_GRAPH is set or
+// kernels are being profiled, replayed from a captured HIP graph of
+// kGraphRounds rounds (kernels only).  With closure AUTO, auto_rounds rounds
+// run on Sigma first; instances that split a block in every one of them then
+// get the closure letters (the paper's transPR is closure ON with this method).
+int Engine::leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s) {
+  const size_t I = in_.size();
+  const bool batch = I > 1;
+  const uint32_t N = (uint32_t)N_;
+  Profiler& prof = ctx_->prof;
+  uint32_t* nl[2] = {d_nb_.as<uint32_t>(), d_slot_of_.as<uint32_t>()};
+  uint8_t* differs = d_keep_.as<uint8_t>();
+  HIP(hipMemsetAsync(nl[0], 0xff, (size_t)N * 4, s));
+  HIP(hipMemsetAsync(nl[1], 0xff, (size_t)N * 4, s));
+  uint64_t queued = 0;  // rounds queued so far: round r uses nl[r & 1]
+  // the kernels' algorithmic bytes per state and round (no early exit)
+  double kbar = 0;
+  for (size_t i = 0; i < I; ++i) kbar += (double)desc_[i].n * desc_[i].kp;
+  kbar = N ? kbar / N : 0.0;
+  auto queue_direct = [&](uint64_t count) {
+    for (uint64_t c = 0; c < count; ++c, ++queued) {
+      prof.begin(s, "leader_round", (double)N * (4.0 + 16.0 * kbar + 1.0 + 9.0 + (batch ? 4.0 : 0.0)));
+      launch_naive_round(batch, N, (uint32_t)I, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                         d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), nl[queued & 1], nl[(queued + 1) & 1],
+                         differs, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), d_ctrl_.as<Ctrl>(), s);
+      prof.end(s);
+    }
+  };
+  auto read_ctrl = [&](Ctrl& c) -> int {
+    HIP(hipGetLastError());
+    HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
+    HIP(stream_wait(s));
+    prof.collect();
+    c = *h_ctrl_.as<Ctrl>();
+    if (c.fault) return DFAMIN_E_INTERNAL;
+    if (c.iterations > max_rounds) return DFAMIN_E_INTERNAL;
+    return DFAMIN_OK;
+  };
+  Ctrl c{};
+  bool any_auto = false;
+  for (auto& x : in_) any_auto |= (x.closure == DFAMIN_CLOSURE_AUTO);
+  if (any_auto) {
+    const uint32_t auto_rounds = opts.auto_rounds ? opts.auto_rounds : kDefaultAutoRounds;
+    queue_direct(auto_rounds);
+    TRY(read_ctrl(c));
+    if (!c.stop) {
+      const uint32_t* rc = h_results_.as<uint32_t>();
+      std::vector<uint32_t> which;
+      for (size_t i = 0; i < I; ++i)
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && rc[i] == c.iterations) which.push_back((uint32_t)i);
+      if (!which.empty()) {
+        TRY(build_closure(which, opts, s));
+        TRY(upload_layout(s));
+      }
+    }
+  }
+  const bool graphs = !(opts.flags & DFAMIN_FLAG_NO_GRAPH) && !prof.enabled() && s != nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (graphs && !c.stop) {
+    // capture kGraphRounds rounds starting at this parity, or reuse the
+    // graph of an earlier call with the same pointers and sizes
+    const GraphKey key{N, (uint32_t)I, (uint32_t)(queued & 1), d_inst_of_.p, d_desc_.p, d_rows_.p, d_block_.p,
+                       nl[0], nl[1], differs, d_changed_.p, d_refine_.p, d_ctrl_.p, s};
+    if (graph_exec_ && graph_key_ == key) {
+      exec = graph_exec_;
+    } else {
+      if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+      graph_exec_ = nullptr;
+      hipGraph_t g = nullptr;
+      HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      const uint64_t q0 = queued;
+      for (uint32_t r = 0; r < kGraphRounds; ++r)
+        launch_naive_round(batch, N, (uint32_t)I, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                           d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), nl[(q0 + r) & 1],
+                           nl[(q0 + r + 1) & 1], differs, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(),
+                           d_ctrl_.as<Ctrl>(), s);
+      const hipError_t ce = hipStreamEndCapture(s, &g);
+      if (ce != hipSuccess || !g) return check_hip(ce != hipSuccess ? ce : hipErrorUnknown);
+      const hipError_t ie = hipGraphInstantiate(&graph_exec_, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP(ie);
+      graph_key_ = key;
+      exec = graph_exec_;
+    }
+  }
+  // queue batches of rounds; the host checks less and less often
+  uint32_t per_check = 1;
+  while (!c.stop) {
+    for (uint32_t b = 0; b < per_check; ++b) {
+      if (exec) {
+        HIP(hipGraphLaunch(exec, s));
+        queued += kGraphRounds;
+      } else {
+        queue_direct(kGraphRounds);
+      }
+    }
+    TRY(read_ctrl(c));
+    per_check = std::min<uint32_t>(per_check * 2, 64);
+  }
+  return DFAMIN_OK;
+}
+
+int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+                std::vector<InstOutcome>& res) {
+  in_ = in;
+  const size_t I = in_.size();
+  res.assign(I, InstOutcome{});
+  if (I == 0) return DFAMIN_OK;
+  const bool batch = I > 1;
+  uint64_t N = 0;
+  uint32_t nmax = 0;
+  for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
+  if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
+  N_ = N;
+  closure_cursor_ = 0;
+  Profiler& prof = ctx_->prof;
+
+  // ---- 1. validation + identity letters: one row job per (instance, letter)
+  std::vector<RowJob> jobs;
+  std::vector<uint32_t> joboff, job_inst;
+  uint32_t wgs = 0;
+  for (size_t i = 0; i < I; ++i)
+    for (uint32_t a = 0; a < in_[i].k; ++a) {
+      RowJob J;
+      J.src = reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n;
+      J.dst = 0;
+      J.n = in_[i].n;
+      J.flag_idx = (uint32_t)jobs.size();
+      joboff.push_back(wgs);
+      wgs += (J.n + kRowTile - 1) / kRowTile;
+      jobs.push_back(J);
+      job_inst.push_back((uint32_t)i);
+    }
+  TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
+  TRY(ensure(d_joboff_, joboff.size() * 4));
+  TRY(ensure(d_flags_, jobs.size() * 4));
+  TRY(ensure(d_wgflags_, (size_t)wgs * 4));
+  TRY(ensure_host(h_flags_, jobs.size() * 4));
+  HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
+  HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
+  HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
+  {
+    double bytes = 0;
+    for (auto& x : in_) bytes += 4.0 * x.n * x.k;
+    prof.begin(s, "validate", bytes);
+    launch_row_check(d_jobs_.as<RowJob>(), d_joboff_.as<uint32_t>(), (uint32_t)jobs.size(), wgs,
+                     d_wgflags_.as<uint32_t>(), d_flags_.as<uint32_t>(), s);
+    prof.end(s);
+    HIP(hipGetLastError());
+  }
+  HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
+  HIP(stream_wait(s));
+  prof.collect();
+  bool any_bad = false;
+  nonid_.assign(I, {});
+  {
+    const uint32_t* f = h_flags_.as<uint32_t>();
+    for (size_t j = 0; j < jobs.size(); ++j)
+      if (f[j] & kFlagBad) { res[job_inst[j]].status = DFAMIN_E_BAD_DFA; any_bad = true; }
+    // jobs are ordered (instance, letter): job j of instance i is letter j - first(i)
+    size_t j = 0;
+    for (size_t i = 0; i < I; ++i) {
+      std::vector<uint32_t> letters;
+      for (uint32_t a = 0; a < in_[i].k; ++a, ++j)
+        if (f[j] & kFlagNonId) letters.push_back(a);
+      nonid_[i] = letters;
+    }
+  }
+  if (any_bad) return DFAMIN_E_BAD_DFA;
+
+  // ---- 2. descriptors and signature letters
+  desc_.assign(I, InstDesc{});
+  inst_rows_.assign(I, {});
+  levels_.assign(I, 0);
+  has_closure_.assign(I, 0);
+  {
+    uint64_t off = 0;
+    for (size_t i = 0; i < I; ++i) {
+      InstDesc& D = desc_[i];
+      D.state_off = (uint32_t)off;
+      D.n = in_[i].n;
+      D.k = in_[i].k;
+      D.q0 = in_[i].q0;
+      D.accept = reinterpret_cast<uint64_t>(in_[i].accept);
+      D.out = reinterpret_cast<uint64_t>(in_[i].out);
+      off += in_[i].n;
+      for (uint32_t a : nonid_[i])
+        inst_rows_[i].push_back(reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n);
+    }
+  }
+  {
+    std::vector<uint32_t> on;
+    for (size_t i = 0; i < I; ++i)
+      if (in_[i].closure == DFAMIN_CLOSURE_ON) on.push_back((uint32_t)i);
+    if (!on.empty()) TRY(build_closure(on, opts, s));
+  }
+
+  // ---- 3. buffers sized for N
+  TRY(ensure(d_block_, N * 4));
+  TRY(ensure(d_act_, N * 4));
+  TRY(ensure(d_act2_, N * 4));
+  TRY(ensure(d_slot_of_, N * 4));
+  TRY(ensure(d_nb_, N * 4));
+  TRY(ensure(d_keep_, N));
+  TRY(ensure(d_rank_, (N + 1) * 4));
+  const uint64_t max_tiles = (N + kScanTile - 1) / kScanTile + 1;
+  TRY(ensure(d_status_, max_tiles * 8));
+  TRY(ensure(d_changed_, I * 4));
+  TRY(ensure(d_refine_, I * 4));
+  TRY(ensure(d_minF_, I * 4));
+  TRY(ensure(d_minN_, I * 4));
+  TRY(ensure(d_results_, I * sizeof(ResultDev)));
+  TRY(ensure(d_ctrl_, sizeof(Ctrl)));
+  TRY(ensure(d_inst_off_, I * 4));
+  if (batch) TRY(ensure(d_inst_of_, N * 4));
+  TRY(ensure(d_counts_, I * 4));
+  TRY(ensure_host(h_ctrl_, sizeof(Ctrl)));
+  TRY(ensure_host(h_results_, I * sizeof(ResultDev)));
+  TRY(ensure_host(h_counts_, I * 4));
+  TRY(upload_layout(s));
+  // workgroup offsets of the per-instance init jobs
+  std::vector<uint32_t> inst_off(I);
+  uint32_t init_wgs = 0;
+  for (size_t i = 0; i < I; ++i) {
+    inst_off[i] = init_wgs;
+    init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
+  }
+  HIP(hipMemcpyAsync(d_inst_off_.p, inst_off.data(), I * 4, hipMemcpyHostToDevice, s));
+  TRY(ensure(d_part_, (size_t)init_wgs * 8));
+  HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
+  HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
+  HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
+
+  // ---- 4. initial partition {F, Q\F}
+  prof.begin(s, "init_minmax", (double)N / 8.0);
+  launch_init_minmax(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
+                     d_part_.as<unsigned long long>(), d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(), s);
+  prof.end(s);
+  prof.begin(s, "init_block", (8.125 + (batch ? 4.0 : 0.0)) * (double)N);
+  launch_init_block(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
+                    d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(),
+                    batch ? d_inst_of_.as<uint32_t>() : nullptr, d_block_.as<uint32_t>(),
+                    d_act_.as<uint32_t>(), s);
+  prof.end(s);
+  HIP(hipGetLastError());
+
+  // ---- 5. rounds
+  {
+    const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
+    TRY(opts.method == DFAMIN_METHOD_LEADER ? leader_rounds(opts, max_rounds, s)
+                                            : signature_rounds(opts, max_rounds, s));
   }
 
   // ---- 6. canonical numbering and emission

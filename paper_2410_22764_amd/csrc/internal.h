@@ -30,6 +30,7 @@ constexpr int kScanTile = kBlock * kScanItems;
 constexpr int kSigVariants = 3;
 constexpr int kSigDefaultVariant = 1;
 constexpr uint64_t kTuneMinStates = 1ull << 18;  // smaller rounds use the default
+constexpr uint32_t kGraphRounds = 16;  // leader-election rounds per captured graph
 constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
 
 // Per-instance descriptor (device copy).  64 bytes.
@@ -76,7 +77,9 @@ struct Ctrl {
   uint32_t collision;     // two different signatures shared a hash this round
   uint32_t m_next;        // active states for the next round
   uint32_t fault;         // a bounded device wait or probe ran out (never expected)
-  uint32_t pad0[28];
+  uint32_t stop;          // leader-election rounds: no block split, later rounds do nothing
+  uint32_t iterations;    // leader-election rounds run (the one that found stability included)
+  uint32_t pad0[26];
   uint32_t tile_counter;  // dynamic tile ids for the look-back scans
   uint32_t pad1[31];
 };
@@ -167,6 +170,17 @@ void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
 // last (nullable) receives this round's per-instance changed flags.
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
                       Ctrl* ctrl, hipStream_t s);
+// One round of leader-based refinement (Algorithm 2, Section 3.2) over all
+// N states: elect (states that differ from their leader in a successor
+// block; the least of them becomes new_leader[leader]), move (they join the
+// new leader's block; resets next_leader for the following round), then
+// launch_round_end and a one-thread check that sets ctrl->stop when no
+// block split.  Every kernel returns at once when ctrl->stop is set, so
+// rounds can be queued (or replayed from a graph) ahead of the host.
+void launch_naive_round(bool batch, uint32_t N, uint32_t ninst, const uint32_t* inst_of,
+                        const InstDesc* desc, const uint64_t* rows, uint32_t* block, uint32_t* new_leader,
+                        uint32_t* next_leader, uint8_t* differs, uint32_t* changed_inst, uint32_t* refine_cnt,
+                        Ctrl* ctrl, hipStream_t s);
 // Instances joining a running set: like launch_init_block, with instance
 // ids slot[j] for job j and their states appended to act at act_off[j].
 void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,

@@ -655,6 +655,79 @@ __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
   }
 }
 
+// ------------------------------------------------ leader-based refinement
+// Algorithm 2 (Section 3.2).  A state q whose block leader L = block[q]
+// reaches a different block under some letter differs from L; the least
+// such state of L's block becomes new_leader[L] (the paper elects by a
+// concurrent write; the least candidate keeps leaders the least members of
+// their blocks).  Algorithmic bytes per state: 4 (block) + 8k' (delta'
+// entries of q and L) + 8k' (their successors' blocks) + 1 (flag), in the
+// worst case of no early exit.
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_naive_elect(uint32_t N, const uint32_t* __restrict__ inst_of,
+                                                        const InstDesc* __restrict__ desc,
+                                                        const uint64_t* __restrict__ rows,
+                                                        const uint32_t* __restrict__ block,
+                                                        uint32_t* __restrict__ new_leader,
+                                                        uint8_t* __restrict__ differs,
+                                                        const Ctrl* __restrict__ ctrl) {
+  if (ctrl->stop) return;
+  const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+  if (g >= N) return;
+  const uint32_t L = block[g];
+  uint8_t d = 0;
+  if (L != g) {
+    const uint32_t i = BATCH ? inst_of[g] : 0u;
+    const InstDesc D = desc[i];
+    const uint64_t* __restrict__ R = rows + D.rows_off;
+    const uint32_t q = g - D.state_off, l = L - D.state_off;
+    for (uint32_t r = 0; r < D.kp && !d; ++r) {
+      const uint32_t* __restrict__ row = reinterpret_cast<const uint32_t*>(R[r]);
+      if (block[D.state_off + row[q]] != block[D.state_off + row[l]]) d = 1;
+    }
+  }
+  differs[g] = d;
+  if (d) atomicMin(&new_leader[L], g);
+}
+
+// Differing states join their new leader's block.  Each thread reads and
+// writes only its own block entry, so the update is in place.  Resets the
+// other round's election array.  Algorithmic bytes per state: 1 + 4 + 4
+// (flag, block, next_leader reset) + 8 for a moving state.
+template <bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_naive_move(uint32_t N, const uint32_t* __restrict__ inst_of,
+                                                       uint32_t* __restrict__ block,
+                                                       const uint32_t* __restrict__ new_leader,
+                                                       uint32_t* __restrict__ next_leader,
+                                                       const uint8_t* __restrict__ differs,
+                                                       uint32_t* __restrict__ changed_inst,
+                                                       const Ctrl* __restrict__ ctrl) {
+  if (ctrl->stop) return;
+  const uint32_t g = blockIdx.x * kBlock + threadIdx.x;
+  bool moved = false;
+  uint32_t i = 0xffffffffu;
+  if (g < N) {
+    next_leader[g] = 0xffffffffu;
+    if (differs[g]) {
+      block[g] = new_leader[block[g]];
+      moved = true;
+      i = BATCH ? inst_of[g] : 0u;
+    }
+  }
+  const uint32_t lane = threadIdx.x & 63u;
+  const unsigned long long cm = __ballot(moved);
+  const int first = cm ? __builtin_ctzll(cm) : 0;
+  const uint32_t i0 = __shfl(i, first, 64);
+  if (moved && ((int)lane == first || i != i0)) changed_inst[i] = 1u;
+}
+
+__global__ void k_naive_check(Ctrl* __restrict__ ctrl) {
+  if (threadIdx.x != 0 || ctrl->stop) return;
+  ctrl->iterations += 1u;
+  if (ctrl->any_changed) ctrl->any_changed = 0u;
+  else ctrl->stop = 1u;
+}
+
 // ---------------------------------------------------------------- finalize
 __global__ __launch_bounds__(kBlock) void k_prep_scan(unsigned long long* __restrict__ scan_status,
                                                       uint32_t ntiles, Ctrl* __restrict__ ctrl) {
@@ -1180,6 +1253,26 @@ void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t nj
   if (!njobs) return;
   hipLaunchKernelGGL(k_results_jobs, dim3(grid_for(njobs, kBlock)), dim3(kBlock), 0, s, desc, slot, njobs,
                      totals, refine_cnt, res);
+}
+
+void launch_naive_round(bool batch, uint32_t N, uint32_t ninst, const uint32_t* inst_of,
+                        const InstDesc* desc, const uint64_t* rows, uint32_t* block, uint32_t* new_leader,
+                        uint32_t* next_leader, uint8_t* differs, uint32_t* changed_inst, uint32_t* refine_cnt,
+                        Ctrl* ctrl, hipStream_t s) {
+  const dim3 grid(grid_for(N, kBlock));
+  if (batch) {
+    hipLaunchKernelGGL(k_naive_elect<true>, grid, dim3(kBlock), 0, s, N, inst_of, desc, rows, block,
+                       new_leader, differs, ctrl);
+    hipLaunchKernelGGL(k_naive_move<true>, grid, dim3(kBlock), 0, s, N, inst_of, block, new_leader,
+                       next_leader, differs, changed_inst, ctrl);
+  } else {
+    hipLaunchKernelGGL(k_naive_elect<false>, grid, dim3(kBlock), 0, s, N, inst_of, desc, rows, block,
+                       new_leader, differs, ctrl);
+    hipLaunchKernelGGL(k_naive_move<false>, grid, dim3(kBlock), 0, s, N, inst_of, block, new_leader,
+                       next_leader, differs, changed_inst, ctrl);
+  }
+  launch_round_end(ninst, changed_inst, refine_cnt, nullptr, ctrl, s);
+  hipLaunchKernelGGL(k_naive_check, dim3(1), dim3(64), 0, s, ctrl);
 }
 
 void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s) {

@@ -46,7 +46,8 @@ class Dfa(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("closure", ctypes.c_uint32), ("max_levels", ctypes.c_uint32),
-                ("auto_rounds", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32)]
+                ("auto_rounds", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32),
+                ("method", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
 
 
 class Result(ctypes.Structure):
@@ -127,9 +128,14 @@ def status_str(code):
 dfamin_status_str = status_str
 
 
-def make_opts(closure="off", max_levels=0, auto_rounds=0, max_rounds=0):
+METHOD = {"signature": 0, "leader": 1}
+FLAG_NO_GRAPH = 1
+
+
+def make_opts(closure="off", max_levels=0, auto_rounds=0, max_rounds=0, method="signature", no_graph=False):
     c = CLOSURE[closure] if isinstance(closure, str) else int(closure)
-    return Opts(c, max_levels, auto_rounds, max_rounds)
+    m = METHOD[method] if isinstance(method, str) else int(method)
+    return Opts(c, max_levels, auto_rounds, max_rounds, m, FLAG_NO_GRAPH if no_graph else 0)
 
 
 def _opts(opts):
