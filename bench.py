@@ -31,6 +31,11 @@ WORKLOADS = {
                          desc="random complete DFA, n=16384, |Sigma|=2, uniform delta, Bernoulli(0.5) accepting"),
     "deep_chain": dict(kind="chain", n=1 << 20, k=2, closure="on",
                        desc="chain DFA, n=2^20, |Sigma|=2 (second letter the identity), closure on"),
+    "fib20": dict(kind="fib", m=20, closure="auto",
+                  desc="Fib_20 of the paper's Table 2: unary, 17,711 states",
+                  paper={"system": "NVIDIA TITAN RTX (Table 2)", "sortPR_ms": 3909.2, "sortPR_iterations": 17710,
+                         "transPR_ms": 1.7, "transPR_iterations": 14, "naivePR_ms": 308.8,
+                         "naivePR_iterations": 17710}),
     "fib30": dict(kind="fib", m=30, closure="auto",
                   desc="Fib_30 of the paper's Table 2: unary, 2,178,309 states, accepting where the "
                        "Fibonacci word w_31 has a 1",
@@ -256,6 +261,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="plain_large", choices=sorted(WORKLOADS))
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--method", default="signature", choices=["signature", "leader"],
+                    help="refinement rounds: signature (Algorithm 4) or leader election (Algorithm 2)")
+    ap.add_argument("--closure", default=None, choices=["off", "on", "auto"],
+                    help="override the workload's closure policy")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event kernel timing")
     ap.add_argument("--profile-steps", type=int, default=5, help="extra steps timed per kernel")
@@ -311,7 +320,8 @@ def main():
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     ctx = dfamin.dfamin_create(0)
-    opts = dict(closure=spec["closure"])
+    closure = args.closure or spec["closure"]
+    opts = dict(closure=closure, method=args.method)
     if spec["kind"] == "batch":
         from paper_2410_22764_amd import workloads as W
         batch = W.batch_mixed(seed=args.seed)
@@ -319,7 +329,7 @@ def main():
         trans = sum(x.n * x.k for x in batch)
         cfg = {"workload": f"{args.workload}: {spec['desc']}", "instances": len(batch),
                "states": sum(x.n for x in batch), "transitions": trans, "seed": args.seed,
-               "closure": spec["closure"], "parallelism": "single GPU"}
+               "closure": closure, "method": args.method, "parallelism": "single GPU"}
 
         def step():
             rs = dfamin.dfamin_minimize_batch_device(ctx, specs, outs, opts, stream.cuda_stream)
@@ -334,7 +344,7 @@ def main():
         out = torch.empty(d.n, dtype=torch.int32, device=dev)
         trans = d.n * d.k
         cfg = {"workload": f"{args.workload}: {spec['desc']}", "n": d.n, "k": d.k, "seed": args.seed,
-               "closure": spec["closure"], "parallelism": "single GPU"}
+               "closure": closure, "method": args.method, "parallelism": "single GPU"}
         if "paper" in spec:
             cfg["paper_context"] = spec["paper"]
 
