@@ -59,6 +59,8 @@ def _load():
     lib.oracle_moore_from.restype = ctypes.c_int
     lib.oracle_naive.argtypes = [u32, u32, _U32P, _U8P, u32, _U32P, _U32P, _U32P]
     lib.oracle_naive.restype = ctypes.c_int
+    lib.oracle_minimal_dfa.argtypes = [u32, u32, _U32P, _U8P, u32, _U32P, _U32P, _U8P, _U32P, _U32P]
+    lib.oracle_minimal_dfa.restype = ctypes.c_int
     lib.oracle_closure.argtypes = [u32, u32, _U32P, u32, _U32P]
     lib.oracle_closure.restype = ctypes.c_int
     lib.oracle_floor_log2.argtypes = [u32]
@@ -213,6 +215,21 @@ def reachable(n, k, delta, q0):
     mark = np.empty(n, np.uint8)
     cnt = _load().oracle_reachable(n, k, dp, q0, mark.ctypes.data_as(_U8P))
     return mark.astype(bool), int(cnt)
+
+
+def minimal_dfa(n, k, delta, accept, q0):
+    """Minimal DFA of the states reachable from q0:
+    (min_n, delta_min (k*min_n, letter-major), accept bitmap, q0_min, reachable count)."""
+    d, dp = _u32(delta)
+    a, ap = _u8(accept)
+    md = np.empty(max(k * n, 1), np.uint32)
+    ma = np.zeros(max((n + 7) // 8, 1), np.uint8)
+    mn, mq, nr = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+    _check(_load().oracle_minimal_dfa(n, k, dp, ap, q0, ctypes.byref(mn), md.ctypes.data_as(_U32P),
+                                      ma.ctypes.data_as(_U8P), ctypes.byref(mq), ctypes.byref(nr)),
+           "minimal_dfa")
+    m = mn.value
+    return m, md[: k * m].copy(), ma[: (m + 7) // 8].copy(), mq.value, nr.value
 
 
 def exhaustive_check(n, k):

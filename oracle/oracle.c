@@ -507,3 +507,54 @@ uint32_t oracle_reachable(uint32_t n, uint32_t k, const uint32_t *delta,
   free(queue);
   return tail;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The minimal DFA in the textbook sense (Section 2): the quotient by the
+ * equivalence of the states reachable from q0.  Its states are the classes
+ * that contain a reachable state, numbered by least member; from class c
+ * (least member r) letter a leads to the class of delta(r, a) -- the same
+ * class for every member, since the equivalence is a congruence; c is
+ * accepting iff r is; the initial state is the class of q0.  min_delta holds
+ * (*min_n) entries per letter, letter-major (capacity k*n); min_accept is an
+ * LSB-first bitmap (capacity ceil(n/8) bytes). */
+int oracle_minimal_dfa(uint32_t n, uint32_t k, const uint32_t *delta,
+                       const uint8_t *accept, uint32_t q0, uint32_t *min_n,
+                       uint32_t *min_delta, uint8_t *min_accept, uint32_t *min_q0,
+                       uint32_t *num_reachable) {
+  if (n == 0 || k == 0 || !delta || !accept || !min_n || !min_delta || !min_accept || !min_q0 || q0 >= n)
+    return -1;
+  uint32_t *cls = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint8_t *reach = (uint8_t *)malloc(n);
+  uint32_t *rep = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  uint32_t *rid = (uint32_t *)malloc(sizeof(uint32_t) * n);
+  if (!cls || !reach || !rep || !rid) {
+    free(cls); free(reach); free(rep); free(rid);
+    return -2;
+  }
+  uint32_t nb = 0;
+  int rc = oracle_hopcroft(n, k, delta, accept, cls, &nb);
+  if (rc) { free(cls); free(reach); free(rep); free(rid); return rc; }
+  const uint32_t nr = oracle_reachable(n, k, delta, q0, reach);
+  for (uint32_t c = 0; c < nb; ++c) { rep[c] = UINT32_MAX; rid[c] = UINT32_MAX; }
+  for (uint32_t q = 0; q < n; ++q)
+    if (rep[cls[q]] == UINT32_MAX) rep[cls[q]] = q;      /* least member */
+  for (uint32_t q = 0; q < n; ++q)
+    if (reach[q]) rid[cls[q]] = 1;                        /* class is kept */
+  uint32_t m = 0;
+  for (uint32_t c = 0; c < nb; ++c)
+    if (rid[c] != UINT32_MAX) rid[c] = m++;
+  memset(min_accept, 0, (m + 7) / 8);
+  for (uint32_t c = 0; c < nb; ++c) {
+    if (rid[c] == UINT32_MAX) continue;
+    const uint32_t r = rep[c];
+    for (uint32_t a = 0; a < k; ++a)
+      min_delta[(size_t)a * m + rid[c]] = rid[cls[delta[(size_t)a * n + r]]];
+    if (ACC(accept, r)) min_accept[rid[c] >> 3] |= (uint8_t)(1u << (rid[c] & 7));
+  }
+  *min_n = m;
+  *min_q0 = rid[cls[q0]];
+  if (num_reachable) *num_reachable = nr;
+  free(cls); free(reach); free(rep); free(rid);
+  return 0;
+}
+

@@ -108,6 +108,17 @@ int oracle_word_equivalence(uint32_t n, uint32_t k, const uint32_t *delta,
 uint32_t oracle_reachable(uint32_t n, uint32_t k, const uint32_t *delta,
                           uint32_t q0, uint8_t *mark);
 
+/* The minimal DFA in the textbook sense (Section 2): the quotient by the
+ * equivalence of the states reachable from q0.  States: the classes that
+ * contain a reachable state, numbered by least member.  min_delta:
+ * letter-major, (*min_n) entries per letter (capacity k*n); min_accept:
+ * LSB-first bitmap (capacity ceil(n/8)).  *num_reachable (may be NULL):
+ * input states reachable from q0. */
+int oracle_minimal_dfa(uint32_t n, uint32_t k, const uint32_t *delta,
+                       const uint8_t *accept, uint32_t q0, uint32_t *min_n,
+                       uint32_t *min_delta, uint8_t *min_accept, uint32_t *min_q0,
+                       uint32_t *num_reachable);
+
 /* Exhaustive cross-check over EVERY complete DFA with n states, k letters
  * and every accepting set: Hopcroft vs pair marking vs Moore (and word
  * enumeration when n <= 4).  Returns the number of DFAs checked; writes the

@@ -410,3 +410,84 @@ def test_naive_iteration_cap():
     d = W.chain_dfa(40, 1)
     with pytest.raises(Exception):
         oracle.naive(d.n, d.k, d.delta, d.accept, max_iter=10)
+
+
+# ---- the minimal DFA of the reachable part (Section 2) -----------------------
+
+def _same_language(d, m, dm, am, q0m):
+    """Product construction: two complete DFAs accept the same language iff
+    no pair reachable from (q0, q0') disagrees on acceptance."""
+    acc1 = d.accept_bool()
+    acc2 = np.unpackbits(am, bitorder="little")[:m].astype(bool) if m else np.zeros(0, bool)
+    rows1 = d.rows()
+    rows2 = dm.reshape(d.k, m)
+    seen = {(d.q0, q0m)}
+    stack = [(d.q0, q0m)]
+    while stack:
+        p, q = stack.pop()
+        if acc1[p] != acc2[q]:
+            return False
+        for a in range(d.k):
+            nxt = (int(rows1[a][p]), int(rows2[a][q]))
+            if nxt not in seen:
+                seen.add(nxt)
+                stack.append(nxt)
+    return True
+
+
+def _check_minimal(d):
+    m, dm, am, q0m, nr = oracle.minimal_dfa(d.n, d.k, d.delta, d.accept, d.q0)
+    assert 1 <= m <= d.n and 0 <= q0m < m and dm.size == d.k * m and (dm < m).all()
+    assert _same_language(d, m, dm, am, q0m)
+    # minimal: no two states equivalent, all reachable from the initial state
+    _, nbm = oracle.hopcroft(m, d.k, dm, am)
+    _, nrm = oracle.reachable(m, d.k, dm, q0m)
+    assert nbm == m and nrm == m
+    mark, nrr = oracle.reachable(d.n, d.k, d.delta, d.q0)
+    assert nr == nrr
+    return m, dm, am, q0m
+
+
+@pytest.mark.parametrize("n,k", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2)])
+def test_minimal_dfa_exhaustive(n, k):
+    """Every complete DFA with n states and k letters, every accepting set
+    and every initial state."""
+    import itertools
+    for delta in itertools.product(range(n), repeat=n * k):
+        for fm in range(1 << n):
+            acc = np.array([(fm >> q) & 1 for q in range(n)], bool)
+            for q0 in range(n):
+                d = W.from_rows(np.array(delta, np.uint32).reshape(k, n), acc, q0)
+                _check_minimal(d)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_minimal_dfa_random(seed):
+    n = [5, 40, 300, 1000, 5000, 20000][seed]
+    d = W.random_dfa(n, 1 + seed % 3, seed + 7)
+    d.q0 = (seed * 7919) % n
+    m, *_ = _check_minimal(d)
+    cls, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+    mark, _ = oracle.reachable(d.n, d.k, d.delta, d.q0)
+    assert m == len(set(cls[mark].tolist())) <= nb
+
+
+def test_minimal_dfa_closed_forms():
+    # chain from its first state: every state reachable and distinct
+    for d in [W.chain_dfa(500, 2), W.permuted_chain_dfa(700, 3, 2)]:
+        m, *_ = _check_minimal(d)
+        assert m == d.n
+    # Fib_m from state 0 (a cycle): the minimal size printed in Table 2
+    r = [x for x in _read_rows("table2.csv") if x["name"] == "Fib_20"][0]
+    d = W.fib_dfa(20)
+    m, *_ = _check_minimal(d)
+    assert m == int(r["size_output"]) == 17711
+    # B_m from state 0: no letter moves state 0, one reachable state
+    d = W.bitsplitter_dfa(10)
+    m, dm, am, q0m = _check_minimal(d)
+    assert m == 1 and q0m == 0 and (dm == 0).all()
+    # no accepting state: one rejecting state
+    d = W.random_dfa(100, 3, 5)
+    d.accept = W.pack_accept(np.zeros(100, bool))
+    m, dm, am, q0m = _check_minimal(d)
+    assert m == 1 and not am.any()
