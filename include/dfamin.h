@@ -160,6 +160,32 @@ int dfamin_minimize_batch_device(dfamin_ctx *ctx, uint32_t count, const dfamin_d
                                  const dfamin_opts *opts, uint32_t *const *dev_outs,
                                  dfamin_result *results, void *hip_stream);
 
+/* ---- the minimal DFA of the reachable part ------------------------------ */
+/* Section 2: the minimal DFA is the quotient, by the equivalence, of the
+ * states reachable from q0.  dfamin_minimize partitions ALL n states; this
+ * call also finds the states reachable from q0 (breadth first on the GPU)
+ * and emits the quotient automaton of their classes. */
+typedef struct {
+  uint32_t n;           /* states of the minimal DFA (classes holding a reachable state) */
+  uint32_t q0;          /* its initial state */
+  uint32_t num_blocks;  /* classes over all input states (as dfamin_result.num_blocks) */
+  uint32_t reachable;   /* input states reachable from q0 */
+  uint32_t bfs_levels;  /* breadth-first levels run; after 64 levels the closure letters join
+                           as extra edges (words over Sigma: same reachable set, fewer levels) */
+  uint32_t refine_rounds;  /* as dfamin_result */
+  uint32_t reserved[2];
+} dfamin_minimal;
+
+/* Minimize one DFA held in host memory and emit its minimal DFA.  States of
+ * the result are numbered by the least input state of their class; letter a
+ * from state s leads to min_delta[a * info->n + s] (letter-major); s accepts
+ * iff bit s of min_accept (LSB first) is set.  Caller-owned host buffers:
+ * min_delta with room for k*n entries, min_accept for ceil(n/8) bytes,
+ * `out` (may be NULL) for the n canonical class ids of dfamin_minimize.
+ * Errors as dfamin_minimize; buffers are not written on error. */
+int dfamin_minimal_dfa(dfamin_ctx *ctx, const dfamin_dfa *host_dfa, const dfamin_opts *opts,
+                       uint32_t *min_delta, uint8_t *min_accept, uint32_t *out, dfamin_minimal *info);
+
 /* ---- serving (continuous batching) -------------------------------------- */
 /* Queue a request.  The DFA (host memory) is copied before the call returns.
  * A background loop admits queued requests while their device footprint

@@ -221,6 +221,43 @@ int dfamin_minimize(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin_op
   return rc;
 }
 
+int dfamin_minimal_dfa(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin_opts* opts,
+                       uint32_t* min_delta, uint8_t* min_accept, uint32_t* out, dfamin_minimal* info) {
+  if (!ctx || !min_delta || !min_accept) return DFAMIN_E_INVAL;
+  int rc = check_dfa_shape(host_dfa);
+  if (rc == DFAMIN_OK) rc = check_opts(opts);
+  if (rc != DFAMIN_OK) return rc;
+  if ((rc = set_device(ctx->c)) != DFAMIN_OK) return rc;
+  std::vector<uint32_t> tmp;
+  if (!out) {
+    tmp.resize(host_dfa->n);
+    out = tmp.data();
+  }
+  uint32_t* outs[1] = {out};
+  dfamin_result r{};
+  const dfamin_opts o = opts_or_default(opts);
+  rc = run_host_batch(ctx->c, 1, host_dfa, o, outs, &r);
+  if (rc != DFAMIN_OK) return rc;
+  dfamin::MinimalInfo mi;
+  const uint32_t* d_delta = nullptr;
+  const uint8_t* d_acc = nullptr;
+  rc = ctx->c.engine.minimal_dfa(o, ctx->c.stream, r.num_blocks, r.initial_block, mi, &d_delta, &d_acc);
+  if (rc != DFAMIN_OK) return rc;
+  if (hipMemcpy(min_delta, d_delta, 4ull * host_dfa->k * mi.n, hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(min_accept, d_acc, ((size_t)mi.n + 7) / 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return DFAMIN_E_DEVICE;
+  if (info) {
+    *info = dfamin_minimal{};
+    info->n = mi.n;
+    info->q0 = mi.q0;
+    info->num_blocks = r.num_blocks;
+    info->reachable = mi.reachable;
+    info->bfs_levels = mi.bfs_levels;
+    info->refine_rounds = r.refine_rounds;
+  }
+  return DFAMIN_OK;
+}
+
 int dfamin_minimize_device(dfamin_ctx* ctx, const dfamin_dfa* dev_dfa, const dfamin_opts* opts,
                            uint32_t* dev_out, dfamin_result* result, void* hip_stream) {
   if (!ctx || !dev_out) return DFAMIN_E_INVAL;

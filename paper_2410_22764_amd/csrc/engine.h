@@ -66,6 +66,10 @@ struct InstInput {
   uint32_t* out;         // device, n entries
 };
 
+struct MinimalInfo {
+  uint32_t n = 0, q0 = 0, reachable = 0, bfs_levels = 0;
+};
+
 struct InstOutcome {
   uint32_t num_blocks = 0, initial_block = 0, refine_rounds = 0, rounds_executed = 0;
   uint32_t closure_levels = 0, closure_letters = 0;
@@ -88,6 +92,15 @@ class Engine {
   int ensure_host(HostBuf& b, size_t bytes);
   int build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts, hipStream_t s);
   int signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
+ public:
+  // After run() on one instance: the states reachable from q0 (breadth
+  // first; closure rows join as extra edges after 64 levels) and the
+  // quotient of their classes.  nb / initial_block: run()'s num_blocks and
+  // out[q0].  On return *min_delta (k*m entries, letter-major) and *min_acc
+  // (ceil(m/8) bytes) point into device buffers owned by the engine.
+  int minimal_dfa(const dfamin_opts& opts, hipStream_t s, uint32_t nb, uint32_t initial_block,
+                  MinimalInfo& info, const uint32_t** min_delta, const uint8_t** min_acc);
+ private:
   int leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
   int upload_layout(hipStream_t s);
   int check_hip(hipError_t e);
@@ -110,6 +123,7 @@ class Engine {
   DevBuf d_inst_of_, d_block_, d_act_, d_act2_, d_slot_of_, d_nb_, d_keep_, d_rank_;
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
+  DevBuf d_visit_, d_bfs_rows_, d_min_delta_, d_min_acc_;
   HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_;
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {

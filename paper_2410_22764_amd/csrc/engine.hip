@@ -122,7 +122,7 @@ Engine::~Engine() {
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
                     &d_results_, &d_ctrl_, &d_wgflags_, &d_part_, &d_dense_,
-                    &d_counts_, &d_djobs_};
+                    &d_counts_, &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf& b : closure_bufs_)
@@ -137,7 +137,7 @@ uint64_t Engine::device_bytes() const {
                           &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
                           &d_results_, &d_ctrl_, &d_wgflags_, &d_part_, &d_dense_,
-                          &d_counts_, &d_djobs_};
+                          &d_counts_, &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -675,6 +675,88 @@ int Engine::leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStrea
     TRY(read_ctrl(c));
     per_check = std::min<uint32_t>(per_check * 2, 64);
   }
+  return DFAMIN_OK;
+}
+
+int Engine::minimal_dfa(const dfamin_opts& opts, hipStream_t s, uint32_t nb, uint32_t initial_block,
+                        MinimalInfo& info, const uint32_t** min_delta, const uint8_t** min_acc) {
+  if (in_.size() != 1) return DFAMIN_E_INVAL;
+  const InstInput& x = in_[0];
+  const uint32_t n = x.n, k = x.k;
+  Profiler& prof = ctx_->prof;
+  const size_t words = ((size_t)n + 31) / 32;
+  TRY(ensure(d_visit_, words * 4));
+  TRY(ensure(d_min_delta_, (size_t)k * n * 4));
+  TRY(ensure(d_min_acc_, ((size_t)n + 7) / 8));
+  TRY(ensure_host(h_jobs_, 64));
+  uint32_t* visited = d_visit_.as<uint32_t>();
+  uint32_t* frontier = d_act_.as<uint32_t>();
+  uint32_t* next = d_act2_.as<uint32_t>();
+  uint32_t* counter = d_counts_.as<uint32_t>();
+  // start: visited = {q0}, frontier = [q0]
+  uint32_t* hj = h_jobs_.as<uint32_t>();
+  hj[0] = 1u << (x.q0 & 31u);
+  hj[1] = x.q0;
+  HIP(hipMemsetAsync(visited, 0, words * 4, s));
+  HIP(hipMemcpyAsync(visited + (x.q0 >> 5), &hj[0], 4, hipMemcpyHostToDevice, s));
+  HIP(hipMemcpyAsync(frontier, &hj[1], 4, hipMemcpyHostToDevice, s));
+  // the rows followed: the non-identity letters, then their closure levels
+  std::vector<uint64_t> rows = inst_rows_[0];
+  bool closure_used = has_closure_[0] != 0;
+  auto upload_rows = [&]() -> int {
+    TRY(ensure(d_bfs_rows_, std::max<size_t>(rows.size(), 1) * 8));
+    if (!rows.empty())
+      HIP(hipMemcpyAsync(d_bfs_rows_.p, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, s));
+    return DFAMIN_OK;
+  };
+  TRY(upload_rows());
+  uint32_t fcount = 1, reached = 1, levels = 0;
+  while (fcount) {
+    if (levels == kBfsLevelsBeforeClosure && !closure_used && !nonid_[0].empty()) {
+      // a long path: closure letters (words over Sigma) shorten it
+      TRY(build_closure({0u}, opts, s));
+      rows = inst_rows_[0];
+      closure_used = true;
+      TRY(upload_rows());
+    }
+    HIP(hipMemsetAsync(counter, 0, 4, s));
+    prof.begin(s, "bfs_level", 4.0 * fcount * (1.0 + 3.0 * rows.size()));
+    launch_bfs_level(d_bfs_rows_.as<uint64_t>(), (uint32_t)rows.size(), frontier, fcount, visited, next,
+                     counter, s);
+    prof.end(s);
+    HIP(hipGetLastError());
+    HIP(hipMemcpyAsync(&hj[2], counter, 4, hipMemcpyDeviceToHost, s));
+    HIP(stream_wait(s));
+    prof.collect();
+    fcount = hj[2];
+    reached += fcount;
+    ++levels;
+    std::swap(frontier, next);
+  }
+  // quotient of the reachable classes
+  uint32_t* sel = d_nb_.as<uint32_t>();
+  uint32_t* rid = d_rank_.as<uint32_t>();
+  uint32_t* rep = d_slot_of_.as<uint32_t>();
+  HIP(hipMemsetAsync(sel, 0xff, (size_t)nb * 4, s));
+  TRY(ensure(d_status_, ((size_t)(nb + kScanTile - 1) / kScanTile + 1) * 8));
+  prof.begin(s, "quotient", (double)n * 12.0 + (double)nb * (16.0 + 8.0 * k));
+  launch_quotient(n, k, nb, x.delta, x.accept, d_block_.as<uint32_t>(), x.out, visited, sel, rid, rep,
+                  d_min_delta_.as<uint32_t>(), d_keep_.as<uint8_t>(), d_min_acc_.as<uint8_t>(),
+                  d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), s);
+  prof.end(s);
+  HIP(hipGetLastError());
+  HIP(hipMemcpyAsync(&hj[3], rid + nb, 4, hipMemcpyDeviceToHost, s));
+  HIP(hipMemcpyAsync(&hj[4], rid + initial_block, 4, hipMemcpyDeviceToHost, s));
+  HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  HIP(stream_wait(s));
+  prof.collect();
+  if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
+  info.n = hj[3];
+  info.q0 = hj[4];
+  info.reachable = reached;
+  info.bfs_levels = levels;
+  *min_delta = d_min_delta_.as<uint32_t>();
+  *min_acc = d_min_acc_.as<uint8_t>();
   return DFAMIN_OK;
 }
 

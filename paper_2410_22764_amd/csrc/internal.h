@@ -31,6 +31,7 @@ constexpr int kSigVariants = 3;
 constexpr int kSigDefaultVariant = 1;
 constexpr uint64_t kTuneMinStates = 1ull << 18;  // smaller rounds use the default
 constexpr uint32_t kGraphRounds = 16;  // leader-election rounds per captured graph
+constexpr uint32_t kBfsLevelsBeforeClosure = 64;  // BFS levels before closure rows join
 constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
 
 // Per-instance descriptor (device copy).  64 bytes.
@@ -209,6 +210,20 @@ void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_
 void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,
                          const uint32_t* totals, const uint32_t* refine_cnt, ResultDev* res,
                          hipStream_t s);
+// One BFS level: frontier states follow every row; newly visited successors
+// are appended to next (next_count is the append counter).
+void launch_bfs_level(const uint64_t* rows, uint32_t nrows, const uint32_t* frontier, uint32_t fcount,
+                      uint32_t* visited, uint32_t* next, uint32_t* next_count, hipStream_t s);
+// The quotient of the reachable classes (single instance, state ids 0..n-1):
+// cls = canonical class per state (nb classes), visited = reachability
+// bitmap, block = least-member ids.  Writes rid[c] (dense number of kept
+// class c, rid[nb] = their count m), min_delta (letter-major, m per letter),
+// min_acc8 (one byte per state) and min_acc (LSB-first bitmap).  sel must
+// hold all ones for the nb classes.
+void launch_quotient(uint32_t n, uint32_t k, uint32_t nb, const uint32_t* delta, const uint8_t* accept,
+                     const uint32_t* block, const uint32_t* cls, const uint32_t* visited, uint32_t* sel,
+                     uint32_t* rid, uint32_t* rep, uint32_t* min_delta, uint8_t* min_acc8, uint8_t* min_acc,
+                     Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s);
 void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s);
 void launch_scan_reps(const uint32_t* block, uint32_t N, uint32_t* rank, Ctrl* ctrl,
                       unsigned long long* scan_status, hipStream_t s);

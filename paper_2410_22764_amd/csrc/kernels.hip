@@ -728,6 +728,90 @@ __global__ void k_naive_check(Ctrl* __restrict__ ctrl) {
   else ctrl->stop = 1u;
 }
 
+// ------------------------------------------- reachability and the quotient
+// One breadth-first level from q0 (Section 2: the minimal DFA keeps the
+// classes of reachable states): every frontier state follows each row; a
+// successor whose visited bit this thread sets first joins the next
+// frontier, one atomicAdd per row and wave.  Algorithmic bytes per frontier
+// state: 4 + per row 4 (entry) + 4 (visited word) + 4 (append).
+__global__ __launch_bounds__(kBlock) void k_bfs_level(const uint64_t* __restrict__ rows, uint32_t nrows,
+                                                      const uint32_t* __restrict__ frontier,
+                                                      uint32_t fcount, uint32_t* __restrict__ visited,
+                                                      uint32_t* __restrict__ next,
+                                                      uint32_t* __restrict__ next_count) {
+  const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = j < fcount;
+  const uint32_t q = valid ? frontier[j] : 0u;
+  const uint32_t lane = threadIdx.x & 63u;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (uint32_t r = 0; r < nrows; ++r) {
+    bool fresh = false;
+    uint32_t t = 0;
+    if (valid) {
+      t = reinterpret_cast<const uint32_t*>(rows[r])[q];
+      const uint32_t bit = 1u << (t & 31u);
+      if (!(visited[t >> 5] & bit)) fresh = !(atomicOr(&visited[t >> 5], bit) & bit);
+    }
+    const unsigned long long mask = __ballot(fresh);
+    if (!mask) continue;
+    uint32_t base = 0;
+    if (lane == (uint32_t)__builtin_ctzll(mask)) base = atomicAdd(next_count, (uint32_t)__popcll(mask));
+    base = __shfl(base, (int)__builtin_ctzll(mask), 64);
+    if (fresh) next[base + (uint32_t)__popcll(mask & lt)] = t;
+  }
+}
+
+// sel[c] = c for every class c that holds a reachable state (sel starts as
+// all ones), so that a scan over "sel[c] == c" numbers the kept classes.
+__global__ __launch_bounds__(kBlock) void k_mark_classes(uint32_t n, const uint32_t* __restrict__ visited,
+                                                         const uint32_t* __restrict__ cls,
+                                                         uint32_t* __restrict__ sel) {
+  const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+  if (q >= n) return;
+  if ((visited[q >> 5] >> (q & 31u)) & 1u) sel[cls[q]] = cls[q];
+}
+
+// rep[c] = least member of class c (block ids are least members).
+__global__ __launch_bounds__(kBlock) void k_class_reps(uint32_t n, const uint32_t* __restrict__ block,
+                                                       const uint32_t* __restrict__ cls,
+                                                       uint32_t* __restrict__ rep) {
+  const uint32_t q = blockIdx.x * kBlock + threadIdx.x;
+  if (q < n && block[q] == q) rep[cls[q]] = q;
+}
+
+// The quotient: kept class c becomes state s = rid[c]; letter a leads to
+// rid[class of delta(rep_c, a)] (the same class for every member of c); s
+// accepts iff rep_c does.  m = rid[nb] kept classes; min_delta is
+// letter-major with m entries per letter.
+__global__ __launch_bounds__(kBlock) void k_quotient(uint32_t nb, uint32_t n, uint32_t k,
+                                                     const uint32_t* __restrict__ delta,
+                                                     const uint8_t* __restrict__ accept,
+                                                     const uint32_t* __restrict__ cls,
+                                                     const uint32_t* __restrict__ sel,
+                                                     const uint32_t* __restrict__ rid,
+                                                     const uint32_t* __restrict__ rep,
+                                                     uint32_t* __restrict__ min_delta,
+                                                     uint8_t* __restrict__ min_acc) {
+  const uint32_t c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= nb || sel[c] != c) return;
+  const uint32_t m = rid[nb], s = rid[c], r = rep[c];
+  for (uint32_t a = 0; a < k; ++a) min_delta[(uint64_t)a * m + s] = rid[cls[delta[(uint64_t)a * n + r]]];
+  min_acc[s] = (accept[r >> 3] >> (r & 7u)) & 1u;
+}
+
+// LSB-first bitmap from one byte per state; m = *count.
+__global__ __launch_bounds__(kBlock) void k_pack_bits(const uint32_t* __restrict__ count,
+                                                      const uint8_t* __restrict__ bytes,
+                                                      uint8_t* __restrict__ bits) {
+  const uint32_t b = blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t m = *count;
+  if ((uint64_t)b * 8 >= m) return;
+  uint32_t v = 0;
+  for (uint32_t t = 0; t < 8; ++t)
+    if (b * 8 + t < m && bytes[b * 8 + t]) v |= 1u << t;
+  bits[b] = (uint8_t)v;
+}
+
 // ---------------------------------------------------------------- finalize
 __global__ __launch_bounds__(kBlock) void k_prep_scan(unsigned long long* __restrict__ scan_status,
                                                       uint32_t ntiles, Ctrl* __restrict__ ctrl) {
@@ -1273,6 +1357,27 @@ void launch_naive_round(bool batch, uint32_t N, uint32_t ninst, const uint32_t* 
   }
   launch_round_end(ninst, changed_inst, refine_cnt, nullptr, ctrl, s);
   hipLaunchKernelGGL(k_naive_check, dim3(1), dim3(64), 0, s, ctrl);
+}
+
+void launch_bfs_level(const uint64_t* rows, uint32_t nrows, const uint32_t* frontier, uint32_t fcount,
+                      uint32_t* visited, uint32_t* next, uint32_t* next_count, hipStream_t s) {
+  if (!fcount || !nrows) return;
+  hipLaunchKernelGGL(k_bfs_level, dim3(grid_for(fcount, kBlock)), dim3(kBlock), 0, s, rows, nrows, frontier,
+                     fcount, visited, next, next_count);
+}
+
+void launch_quotient(uint32_t n, uint32_t k, uint32_t nb, const uint32_t* delta, const uint8_t* accept,
+                     const uint32_t* block, const uint32_t* cls, const uint32_t* visited, uint32_t* sel,
+                     uint32_t* rid, uint32_t* rep, uint32_t* min_delta, uint8_t* min_acc8, uint8_t* min_acc,
+                     Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s) {
+  hipLaunchKernelGGL(k_mark_classes, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, visited, cls, sel);
+  launch_prep_scan(scan_status, (nb + kScanTile - 1) / kScanTile, ctrl, s);
+  launch_scan_reps(sel, nb, rid, ctrl, scan_status, s);
+  hipLaunchKernelGGL(k_class_reps, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, block, cls, rep);
+  hipLaunchKernelGGL(k_quotient, dim3(grid_for(nb, kBlock)), dim3(kBlock), 0, s, nb, n, k, delta, accept, cls,
+                     sel, rid, rep, min_delta, min_acc8);
+  hipLaunchKernelGGL(k_pack_bits, dim3(grid_for((n + 7) / 8, kBlock)), dim3(kBlock), 0, s, rid + nb, min_acc8,
+                     min_acc);
 }
 
 void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s) {

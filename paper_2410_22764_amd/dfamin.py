@@ -34,7 +34,7 @@ EXPORTS = [
     "dfamin_create", "dfamin_destroy", "dfamin_minimize", "dfamin_minimize_device",
     "dfamin_minimize_batch", "dfamin_minimize_batch_device", "dfamin_submit", "dfamin_wait",
     "dfamin_cancel", "dfamin_status_str", "dfamin_set_profiling", "dfamin_get_kernel_stats",
-    "dfamin_set_tuning",
+    "dfamin_set_tuning", "dfamin_minimal_dfa",
 ]
 
 
@@ -48,6 +48,15 @@ class Opts(ctypes.Structure):
     _fields_ = [("closure", ctypes.c_uint32), ("max_levels", ctypes.c_uint32),
                 ("auto_rounds", ctypes.c_uint32), ("max_rounds", ctypes.c_uint32),
                 ("method", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class Minimal(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("q0", ctypes.c_uint32), ("num_blocks", ctypes.c_uint32),
+                ("reachable", ctypes.c_uint32), ("bfs_levels", ctypes.c_uint32),
+                ("refine_rounds", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class Result(ctypes.Structure):
@@ -117,6 +126,8 @@ def load():
     lib.dfamin_get_kernel_stats.restype = i32
     lib.dfamin_set_tuning.argtypes = [vp, i32]
     lib.dfamin_set_tuning.restype = i32
+    lib.dfamin_minimal_dfa.argtypes = [vp, P(Dfa), P(Opts), vp, vp, vp, P(Minimal)]
+    lib.dfamin_minimal_dfa.restype = i32
     _lib = lib
     return lib
 
@@ -287,6 +298,23 @@ def dfamin_set_profiling(ctx, on=True):
     rc = load().dfamin_set_profiling(ctx.handle, 1 if on else 0)
     if rc != DFAMIN_OK:
         raise DfaminError(rc, "dfamin_set_profiling")
+
+
+def dfamin_minimal_dfa(ctx, dfa, opts=None):
+    """Minimal DFA of the states reachable from q0.  Returns (n_min,
+    delta_min (k*n_min, letter-major), accept bitmap, info dict with q0 etc.,
+    canonical class per input state)."""
+    s, keep = _host_dfa(dfa)
+    md = np.empty(max(dfa.k * dfa.n, 1), np.uint32)
+    ma = np.zeros(max((dfa.n + 7) // 8, 1), np.uint8)
+    out = np.empty(dfa.n, np.uint32)
+    info = Minimal()
+    rc = load().dfamin_minimal_dfa(ctx.handle, ctypes.byref(s), _opts(opts), md.ctypes.data, ma.ctypes.data,
+                                   out.ctypes.data, ctypes.byref(info))
+    if rc != DFAMIN_OK:
+        raise DfaminError(rc, "dfamin_minimal_dfa")
+    m = info.n
+    return m, md[: dfa.k * m].copy(), ma[: (m + 7) // 8].copy(), info.as_dict(), out
 
 
 def dfamin_set_tuning(ctx, variant=-1):

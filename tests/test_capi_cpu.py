@@ -41,6 +41,7 @@ def test_null_arguments_rejected_without_device_work():
     assert lib.dfamin_cancel(None, 1) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_set_profiling(None, 1) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_set_tuning(None, -1) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_minimal_dfa(None, None, None, None, None, None, None) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_create(0, 0, None) == dfamin.DFAMIN_E_INVAL
 
 
