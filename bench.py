@@ -415,6 +415,24 @@ def main():
     batched = None
     if not args.no_batch and args.workload == "plain_large":
         batched = batched_vs_plain(ctx, args.seed)
+    minimal = None
+    if spec["kind"] != "batch" and not args.no_batch:
+        # minimal DFA of the reachable part: host input, BFS + quotient on the GPU
+        print("[bench] minimal DFA", file=sys.stderr, flush=True)
+        dfamin.dfamin_minimal_dfa(ctx, d, opts)
+        dfamin.dfamin_set_profiling(ctx, True)
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            m_n, _, _, m_info, _ = dfamin.dfamin_minimal_dfa(ctx, d, opts)
+        tm = (time.perf_counter() - t0) / reps
+        mstats = {x["name"]: x for x in dfamin.dfamin_get_kernel_stats(ctx)}
+        dfamin.dfamin_set_profiling(ctx, False)
+        minimal = {"ms_end_to_end": round(1e3 * tm, 3), "states": m_n, "reachable": m_info["reachable"],
+                   "bfs_levels": m_info["bfs_levels"],
+                   "bfs_ms": round(mstats["bfs_level"]["total_ms"] / reps, 3) if "bfs_level" in mstats else None,
+                   "quotient_ms": round(mstats["quotient"]["total_ms"] / reps, 3) if "quotient" in mstats else None,
+                   "note": "host input and output (PCIe included); bfs/quotient: HIP-event kernel time"}
     serving = None
     if args.serving_requests and args.workload == "plain_large":
         sctx = dfamin.dfamin_create(0)
@@ -442,6 +460,7 @@ def main():
                      "GBps": round(s["alg_bytes"] / (s["total_ms"] * 1e-3) / 1e9, 1) if s["total_ms"] > 0 else None}
                     for s in stats],
         "end_to_end": end_to_end,
+        "minimal_dfa": minimal,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,

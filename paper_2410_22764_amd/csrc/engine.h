@@ -124,7 +124,8 @@ class Engine {
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
   DevBuf d_visit_, d_bfs_rows_, d_min_delta_, d_min_acc_;
-  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_;
+  DevBuf d_rb_;  // owns d_ctrl_, d_refine_ and d_counts_ (views into it, reset every run)
+  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_, h_rb_;
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {
     uint32_t n, ninst, parity;

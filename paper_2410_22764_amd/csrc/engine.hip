@@ -120,14 +120,14 @@ Engine::~Engine() {
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
-                    &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
-                    &d_results_, &d_ctrl_, &d_wgflags_, &d_part_, &d_dense_,
-                    &d_counts_, &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
+                    &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
+                    &d_results_, &d_wgflags_, &d_part_, &d_dense_,
+                    &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf& b : closure_bufs_)
     if (b.p) (void)hipFree(b.p);
-  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_};
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_, &h_rb_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -135,9 +135,9 @@ Engine::~Engine() {
 uint64_t Engine::device_bytes() const {
   const DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                           &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
-                          &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_refine_,
-                          &d_results_, &d_ctrl_, &d_wgflags_, &d_part_, &d_dense_,
-                          &d_counts_, &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
+                          &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
+                          &d_results_, &d_wgflags_, &d_part_, &d_dense_,
+                          &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -334,6 +334,13 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   TRY(ensure_host(h_desc_, I * sizeof(InstDesc)));
   uint32_t* hj = h_jobs_.as<uint32_t>();
   uint32_t* dj = d_djobs_.as<uint32_t>();
+  // job lists already on the device (uploaded again only when they change)
+  std::vector<uint32_t> up_dense, up_scan;
+  auto upload_if_changed = [&](std::vector<uint32_t>& last, const uint32_t* h, uint32_t* d, size_t words) {
+    if (last.size() == words && std::equal(last.begin(), last.end(), h)) return DFAMIN_OK;
+    last.assign(h, h + words);
+    return check_hip(hipMemcpyAsync(d, h, words * 4, hipMemcpyHostToDevice, s));
+  };
   while (m > 0) {
     if (any_auto && rounds == auto_rounds) {
       // instances still refining after auto_rounds rounds get the closure
@@ -403,7 +410,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         es += in_[exact[j]].n;
       }
       TRY(ensure(d_dense_, N * 4));
-      HIP(hipMemcpyAsync(dj, hj, 2 * ne * 4, hipMemcpyHostToDevice, s));
+      TRY(upload_if_changed(up_dense, hj, dj, 2 * ne));
       prof.begin(s, "dense", (8.0 + dense_width) * es);
       launch_dense_jobs(d_desc_.as<InstDesc>(), dj, dj + ne, ne, wgs, d_block_.as<uint32_t>(),
                         d_rank_.as<uint32_t>(), d_dense_.p, dense_width, s);
@@ -425,7 +432,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * groups));
     const uint64_t tsize = 1ull << tbits;
     TRY(ensure(d_table_, tsize * sizeof(Slot)));
-    const uint32_t ntiles = (uint32_t)((m + kScanTile - 1) / kScanTile);
+    const int citems = scan_items_for(m);
+    const uint32_t ntiles = scan_tiles(m, citems);
     const double md = (double)m;
     const double inst_b = batch ? 4.0 : 0.0;
 
@@ -493,10 +501,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     prof.begin(s, "compact", md * (4 + inst_b + 4 + 1 + 4));
     launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
                    d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(),
-                   nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), s);
+                   nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), citems, s);
     prof.end(s);
-    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
-                     d_ctrl_.as<Ctrl>(), s);
     // Exact block counts for the next round, queued before the one sync of
     // the round: instances that were refining before this round and whose
     // next signature could fit 31 bits, B <= min(n, B^(kp+1)) after it.
@@ -510,37 +516,44 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       if (kp1 * std::max<uint32_t>(1, ceil_log2_u64(nb)) <= 31) scan.push_back((uint32_t)i);
     }
     const uint32_t ns = (uint32_t)scan.size();
+    uint32_t* hs = hj + 2 * I;
+    uint32_t* ds = dj + 2 * I;
+    uint32_t stiles = 0;
+    double sstates = 0;
+    int sitems = kScanItemsSmall;
     if (ns) {
-      uint32_t* hs = hj + 2 * I;
-      uint32_t* ds = dj + 2 * I;
-      uint32_t tiles = 0;
-      double states = 0;
+      for (uint32_t j = 0; j < ns; ++j) sstates += in_[scan[j]].n;
+      sitems = scan_items_for((uint64_t)sstates);
       for (uint32_t j = 0; j < ns; ++j) {
         hs[j] = scan[j];
-        hs[ns + j] = tiles;
-        tiles += (in_[scan[j]].n + kScanTile - 1) / kScanTile;
-        states += in_[scan[j]].n;
+        hs[ns + j] = stiles;
+        stiles += scan_tiles(in_[scan[j]].n, sitems);
       }
-      TRY(ensure(d_status_, ((size_t)tiles + 1) * 8));
-      HIP(hipMemcpyAsync(ds, hs, 2 * ns * 4, hipMemcpyHostToDevice, s));
-      launch_prep_scan(d_status_.as<unsigned long long>(), tiles, d_ctrl_.as<Ctrl>(), s);
-      prof.begin(s, "scan_jobs", 8.0 * states);
-      launch_scan_jobs(d_desc_.as<InstDesc>(), ds, ds + ns, ns, tiles, d_block_.as<uint32_t>(),
+      TRY(ensure(d_status_, ((size_t)stiles + 1) * 8));
+    }
+    // round counters; also clears the scan status for the count scan
+    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
+                     d_ctrl_.as<Ctrl>(), s, ns ? d_status_.as<unsigned long long>() : nullptr, stiles);
+    if (ns) {
+      TRY(upload_if_changed(up_scan, hs, ds, 2 * ns));
+      prof.begin(s, "scan_jobs", 8.0 * sstates);
+      launch_scan_jobs(d_desc_.as<InstDesc>(), ds, ds + ns, ns, stiles, d_block_.as<uint32_t>(),
                        d_rank_.as<uint32_t>(), d_counts_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                       d_status_.as<unsigned long long>(), s);
+                       d_status_.as<unsigned long long>(), sitems, s);
       prof.end(s);
-      HIP(hipMemcpyAsync(h_counts_.p, d_counts_.p, ns * 4, hipMemcpyDeviceToHost, s));
     }
     HIP(hipGetLastError());
-    HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
+    // one copy: control block, refine counters, and the counts just scanned
+    HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl) + 4 * I + 4 * (size_t)ns, hipMemcpyDeviceToHost, s));
     HIP(stream_wait(s));
     prof.collect();
-    const Ctrl c = *h_ctrl_.as<Ctrl>();
+    const Ctrl c = *h_rb_.as<Ctrl>();
+    const uint32_t* h_refine = reinterpret_cast<const uint32_t*>(h_rb_.as<char>() + sizeof(Ctrl));
+    const uint32_t* h_cnt = h_refine + I;
     if (c.fault) return DFAMIN_E_INTERNAL;
     std::fill(cnt_ok.begin(), cnt_ok.end(), 0);
     for (uint32_t j = 0; j < ns; ++j) {
-      cnt[scan[j]] = h_counts_.as<uint32_t>()[j];
+      cnt[scan[j]] = h_cnt[j];
       cnt_ok[scan[j]] = 1;
     }
     if (prof.enabled() && std::getenv("DFAMIN_TRACE"))
@@ -554,7 +567,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       continue;
     }
     ++rounds;
-    const uint32_t* rc = h_results_.as<uint32_t>();
+    const uint32_t* rc = h_refine;
     for (size_t i = 0; i < I; ++i) {
       if (!active[i]) continue;
       // a round maps each block to at most B^(kp+1) signatures
@@ -605,11 +618,10 @@ int Engine::leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStrea
   };
   auto read_ctrl = [&](Ctrl& c) -> int {
     HIP(hipGetLastError());
-    HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
-    HIP(hipMemcpyAsync(h_results_.p, d_refine_.p, I * 4, hipMemcpyDeviceToHost, s));
+    HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl) + 4 * I, hipMemcpyDeviceToHost, s));
     HIP(stream_wait(s));
     prof.collect();
-    c = *h_ctrl_.as<Ctrl>();
+    c = *h_rb_.as<Ctrl>();
     if (c.fault) return DFAMIN_E_INTERNAL;
     if (c.iterations > max_rounds) return DFAMIN_E_INTERNAL;
     return DFAMIN_OK;
@@ -622,7 +634,7 @@ int Engine::leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStrea
     queue_direct(auto_rounds);
     TRY(read_ctrl(c));
     if (!c.stop) {
-      const uint32_t* rc = h_results_.as<uint32_t>();
+      const uint32_t* rc = reinterpret_cast<const uint32_t*>(h_rb_.as<char>() + sizeof(Ctrl));
       std::vector<uint32_t> which;
       for (size_t i = 0; i < I; ++i)
         if (in_[i].closure == DFAMIN_CLOSURE_AUTO && rc[i] == c.iterations) which.push_back((uint32_t)i);
@@ -738,7 +750,7 @@ int Engine::minimal_dfa(const dfamin_opts& opts, hipStream_t s, uint32_t nb, uin
   uint32_t* rid = d_rank_.as<uint32_t>();
   uint32_t* rep = d_slot_of_.as<uint32_t>();
   HIP(hipMemsetAsync(sel, 0xff, (size_t)nb * 4, s));
-  TRY(ensure(d_status_, ((size_t)(nb + kScanTile - 1) / kScanTile + 1) * 8));
+  TRY(ensure(d_status_, ((size_t)scan_tiles(nb, scan_items_for(nb)) + 1) * 8));
   prof.begin(s, "quotient", (double)n * 12.0 + (double)nb * (16.0 + 8.0 * k));
   launch_quotient(n, k, nb, x.delta, x.accept, d_block_.as<uint32_t>(), x.out, visited, sel, rid, rep,
                   d_min_delta_.as<uint32_t>(), d_keep_.as<uint8_t>(), d_min_acc_.as<uint8_t>(),
@@ -863,17 +875,24 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   TRY(ensure(d_nb_, N * 4));
   TRY(ensure(d_keep_, N));
   TRY(ensure(d_rank_, (N + 1) * 4));
-  const uint64_t max_tiles = (N + kScanTile - 1) / kScanTile + 1;
+  const uint64_t max_tiles = scan_tiles(N, kScanItemsSmall) + 1;
   TRY(ensure(d_status_, max_tiles * 8));
   TRY(ensure(d_changed_, I * 4));
-  TRY(ensure(d_refine_, I * 4));
+  // control block, per-instance refine counters and block counts share one
+  // allocation so that a round's results come back in one copy
+  TRY(ensure(d_rb_, sizeof(Ctrl) + 8 * I));
+  d_ctrl_.p = d_rb_.p;
+  d_ctrl_.cap = sizeof(Ctrl);
+  d_refine_.p = static_cast<char*>(d_rb_.p) + sizeof(Ctrl);
+  d_refine_.cap = 4 * I;
+  d_counts_.p = static_cast<char*>(d_rb_.p) + sizeof(Ctrl) + 4 * I;
+  d_counts_.cap = 4 * I;
+  TRY(ensure_host(h_rb_, sizeof(Ctrl) + 8 * I));
   TRY(ensure(d_minF_, I * 4));
   TRY(ensure(d_minN_, I * 4));
   TRY(ensure(d_results_, I * sizeof(ResultDev)));
-  TRY(ensure(d_ctrl_, sizeof(Ctrl)));
   TRY(ensure(d_inst_off_, I * 4));
   if (batch) TRY(ensure(d_inst_of_, N * 4));
-  TRY(ensure(d_counts_, I * 4));
   TRY(ensure_host(h_ctrl_, sizeof(Ctrl)));
   TRY(ensure_host(h_results_, I * sizeof(ResultDev)));
   TRY(ensure_host(h_counts_, I * 4));
@@ -912,11 +931,12 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   }
 
   // ---- 6. canonical numbering and emission
-  const uint32_t ntilesN = (uint32_t)((N + kScanTile - 1) / kScanTile);
+  const int fitems = scan_items_for(N);
+  const uint32_t ntilesN = scan_tiles(N, fitems);
   launch_prep_scan(d_status_.as<unsigned long long>(), ntilesN, d_ctrl_.as<Ctrl>(), s);
   prof.begin(s, "scan_reps", 8.0 * (double)N);
   launch_scan_reps(d_block_.as<uint32_t>(), (uint32_t)N, d_rank_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                   d_status_.as<unsigned long long>(), s);
+                   d_status_.as<unsigned long long>(), fitems, s);
   prof.end(s);
   prof.begin(s, "emit", (12.0 + (batch ? 4.0 : 0.0)) * (double)N);
   launch_emit(batch, (uint32_t)N, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),

@@ -22,8 +22,17 @@
 namespace dfamin {
 
 constexpr int kBlock = 256;           // threads per workgroup (4 wave64)
-constexpr int kScanItems = 32;        // items per thread in scan / compaction tiles
-constexpr int kScanTile = kBlock * kScanItems;
+// Scan / compaction tiles: 8 items per thread (2,048 per tile) for small
+// launches, 32 (8,192 per tile) from 2^20 elements on, where the per-tile
+// cost of the look-back dominates.  Callers size tile counts and status
+// arrays with the same choice.
+constexpr int kScanItemsSmall = 8;
+constexpr int kScanItemsLarge = 32;
+inline int scan_items_for(uint64_t elems) { return elems >= (1ull << 20) ? kScanItemsLarge : kScanItemsSmall; }
+inline uint32_t scan_tile(int items) { return (uint32_t)kBlock * (uint32_t)items; }
+inline uint32_t scan_tiles(uint64_t elems, int items) {
+  return (uint32_t)((elems + scan_tile(items) - 1) / scan_tile(items));
+}
 // Signature kernel variants: 1, 2 or 4 states per thread (256, 512 or 1024
 // states per workgroup, an LDS table of twice as many slots).  The variant is
 // picked per size class by the engine's autotuner.
@@ -167,10 +176,11 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
-                    unsigned long long* scan_status, hipStream_t s);
+                    unsigned long long* scan_status, int items, hipStream_t s);
 // last (nullable) receives this round's per-instance changed flags.
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
-                      Ctrl* ctrl, hipStream_t s);
+                      Ctrl* ctrl, hipStream_t s, unsigned long long* clear_status = nullptr,
+                      uint32_t clear_tiles = 0);
 // One round of leader-based refinement (Algorithm 2, Section 3.2) over all
 // N states: elect (states that differ from their leader in a successor
 // block; the least of them becomes new_leader[leader]), move (they join the
@@ -197,7 +207,8 @@ void launch_init_minmax_slots(const InstDesc* desc, const uint32_t* slot, const 
 // results.  job_tile_off: scan tiles (kScanTile states) per job, prefix.
 void launch_scan_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_tile_off,
                       uint32_t njobs, uint32_t total_tiles, const uint32_t* block, uint32_t* rank,
-                      uint32_t* totals, Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s);
+                      uint32_t* totals, Ctrl* ctrl, unsigned long long* scan_status, int items,
+                      hipStream_t s);
 void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
                       uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
                       hipStream_t s);
@@ -226,7 +237,7 @@ void launch_quotient(uint32_t n, uint32_t k, uint32_t nb, const uint32_t* delta,
                      Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s);
 void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ctrl, hipStream_t s);
 void launch_scan_reps(const uint32_t* block, uint32_t N, uint32_t* rank, Ctrl* ctrl,
-                      unsigned long long* scan_status, hipStream_t s);
+                      unsigned long long* scan_status, int items, hipStream_t s);
 void launch_emit(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
                  const uint32_t* block, const uint32_t* rank, hipStream_t s);
 void launch_results(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,

@@ -24,6 +24,8 @@
 // address is hammered by thousands of workgroups.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace dfamin {
 
 namespace {
@@ -110,49 +112,64 @@ __device__ uint32_t lookback_wave0(unsigned long long* status, uint32_t tile, ui
   return excl;
 }
 
-// Tile scan: a tile holds kScanItems x kBlock items, item e of thread t being
+// Tile scan: a tile holds ITEMS x kBlock items, item e of thread t being
 // element e*kBlock + t.  Each thread passes its flags as a bit mask (bit e =
 // item e); one 64-lane ballot per item and wave goes to LDS, and wave 0 turns
-// the kScanItems*kWaves ballot counts (in element order) into exclusive
+// the ITEMS*kWaves ballot counts (in element order) into exclusive
 // offsets.  Flags, ballots and offsets stay out of registers, so the scan
 // kernels keep a high occupancy.  Returns the tile's flag count; tile_rank()
 // gives an item's exclusive rank afterwards.
 constexpr int kWaves = kBlock / 64;
-constexpr int kTileWords = kScanItems * kWaves;
-static_assert(kTileWords == 128, "wave 0 scans two ballot counts per lane");
-static_assert(kScanItems <= 32, "flags are a 32-bit mask per thread");
 
+template <int ITEMS>
 struct TileScanLds {
-  unsigned long long mask[kTileWords];
-  uint32_t off[kTileWords + 1];
+  static constexpr int kWords = ITEMS * kWaves;
+  static_assert(ITEMS <= 32, "flags are a 32-bit mask per thread");
+  unsigned long long mask[kWords];
+  uint32_t off[kWords + 1];
 };
 
-__device__ __forceinline__ uint32_t tile_ballot_count(uint32_t fbits, TileScanLds& t) {
+template <int ITEMS>
+__device__ __forceinline__ uint32_t tile_ballot_count(uint32_t fbits, TileScanLds<ITEMS>& t) {
+  constexpr int W = TileScanLds<ITEMS>::kWords;
+  constexpr int PER = (W + 63) / 64;  // ballot counts per lane of wave 0
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int e = 0; e < kScanItems; ++e) {
+  for (int e = 0; e < ITEMS; ++e) {
     const unsigned long long m = __ballot((fbits >> e) & 1u);
     if (lane == 0) t.mask[e * kWaves + wave] = m;
   }
   __syncthreads();
   if (wave == 0) {
-    const uint32_t c0 = __popcll(t.mask[2 * lane]), c1 = __popcll(t.mask[2 * lane + 1]);
-    uint32_t v = c0 + c1;
+    uint32_t c[PER];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int w = (int)lane * PER + i;
+      c[i] = (w < W) ? (uint32_t)__popcll(t.mask[w]) : 0u;
+      sum += c[i];
+    }
+    uint32_t v = sum;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const uint32_t u = __shfl_up(v, off, 64);
       if ((int)lane >= off) v += u;
     }
-    const uint32_t excl = v - c0 - c1;
-    t.off[2 * lane] = excl;
-    t.off[2 * lane + 1] = excl + c0;
-    if (lane == 63) t.off[kTileWords] = v;
+    uint32_t excl = v - sum;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int w = (int)lane * PER + i;
+      if (w < W) t.off[w] = excl;
+      excl += c[i];
+    }
+    if (lane == 63) t.off[W] = v;
   }
   __syncthreads();
-  return t.off[kTileWords];
+  return t.off[W];
 }
 
-__device__ __forceinline__ uint32_t tile_rank(const TileScanLds& t, int e) {
+template <int ITEMS>
+__device__ __forceinline__ uint32_t tile_rank(const TileScanLds<ITEMS>& t, int e) {
   const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int w = e * kWaves + (int)wave;
@@ -592,7 +609,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
 // instance split this round.  Algorithmic bytes per active state: 4 (act)
 // [+4 inst_of] + 4 (new id) + 1 (keep) + 4 (block write) + 4 per kept state
 // (next active list).
-template <bool BATCH>
+template <bool BATCH, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_compact(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const uint32_t* __restrict__ nb, const uint8_t* __restrict__ keep,
@@ -603,7 +620,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   // written, but every tile still takes part in the look-back so that no
   // workgroup can wait for one that left early.
   __shared__ uint32_t s_tile, s_prefix, s_coll;
-  __shared__ TileScanLds s_scan;
+  __shared__ TileScanLds<ITEMS> s_scan;
   if (threadIdx.x == 0) {
     s_tile = atomicAdd(&ctrl->tile_counter, 1u);
     s_coll = ctrl->collision;
@@ -611,10 +628,10 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   __syncthreads();
   const uint32_t tile = s_tile;
   const bool coll = s_coll != 0;
-  const uint32_t base = tile * kScanTile;
+  const uint32_t base = tile * (kBlock * ITEMS);
   uint32_t fb = 0;
 #pragma unroll 8
-  for (int e = 0; e < kScanItems; ++e) {
+  for (int e = 0; e < ITEMS; ++e) {
     const uint32_t j = base + e * kBlock + threadIdx.x;
     if (j < m && !coll) {
       const uint32_t g = act[j];
@@ -623,27 +640,35 @@ __global__ __launch_bounds__(kBlock) void k_compact(
       if (keep[j] && changed_inst[i] && !(dead && dead[i])) fb |= 1u << e;
     }
   }
-  const uint32_t total = tile_ballot_count(fb, s_scan);
+  const uint32_t total = tile_ballot_count<ITEMS>(fb, s_scan);
   if (threadIdx.x < 64) {
     const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl);
     if (threadIdx.x == 0) {
       s_prefix = excl;
-      if (base + kScanTile >= m && tile < gridDim.x) atomicExch(&ctrl->m_next, excl + total);
+      if (base + kBlock * ITEMS >= m && tile < gridDim.x) atomicExch(&ctrl->m_next, excl + total);
     }
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
   // kept states are re-read from act (the tile was just read: cache hits)
-  for (int e = 0; e < kScanItems; ++e)
-    if ((fb >> e) & 1u) act_next[pre + tile_rank(s_scan, e)] = act[base + e * kBlock + threadIdx.x];
+  for (int e = 0; e < ITEMS; ++e)
+    if ((fb >> e) & 1u) act_next[pre + tile_rank<ITEMS>(s_scan, e)] = act[base + e * kBlock + threadIdx.x];
 }
 
+// Per-instance round counters; optionally also clears clear_tiles scan
+// status words and the tile counter for a look-back scan queued next.
 __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
                                                       uint32_t* __restrict__ changed_inst,
                                                       uint32_t* __restrict__ refine_cnt,
                                                       uint32_t* __restrict__ last,
-                                                      Ctrl* __restrict__ ctrl) {
+                                                      Ctrl* __restrict__ ctrl,
+                                                      unsigned long long* __restrict__ clear_status,
+                                                      uint32_t clear_tiles) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (clear_status) {
+    if (i < clear_tiles) store_status(&clear_status[i], 0ull);
+    if (i == 0) atomicExch(&ctrl->tile_counter, 0u);
+  }
   const uint32_t ch = (i < ninst) ? changed_inst[i] : 0u;
   if (__any(ch != 0u) && (threadIdx.x & 63u) == 0) ctrl->any_changed = 1u;
   if (i >= ninst) return;
@@ -822,35 +847,36 @@ __global__ __launch_bounds__(kBlock) void k_prep_scan(unsigned long long* __rest
 
 // rank[g] = number of block representatives (block[x] == x) with x < g;
 // rank[N] = their total.  Algorithmic bytes: 8 per state.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_scan_reps(const uint32_t* __restrict__ block,
                                                       uint32_t N, uint32_t* __restrict__ rank,
                                                       Ctrl* __restrict__ ctrl,
                                                       unsigned long long* __restrict__ scan_status) {
   __shared__ uint32_t s_tile, s_prefix;
-  __shared__ TileScanLds s_scan;
+  __shared__ TileScanLds<ITEMS> s_scan;
   if (threadIdx.x == 0) s_tile = atomicAdd(&ctrl->tile_counter, 1u);
   __syncthreads();
   const uint32_t tile = s_tile;
-  const uint32_t base = tile * kScanTile;
+  const uint32_t base = tile * (kBlock * ITEMS);
   uint32_t fb = 0;
 #pragma unroll 8
-  for (int e = 0; e < kScanItems; ++e) {
+  for (int e = 0; e < ITEMS; ++e) {
     const uint32_t g = base + e * kBlock + threadIdx.x;
     if (g < N && block[g] == g) fb |= 1u << e;
   }
-  const uint32_t total = tile_ballot_count(fb, s_scan);
+  const uint32_t total = tile_ballot_count<ITEMS>(fb, s_scan);
   if (threadIdx.x < 64) {
     const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl);
     if (threadIdx.x == 0) {
       s_prefix = excl;
-      if (base + kScanTile >= N) rank[N] = excl + total;
+      if (base + kBlock * ITEMS >= N) rank[N] = excl + total;
     }
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
-  for (int e = 0; e < kScanItems; ++e) {
+  for (int e = 0; e < ITEMS; ++e) {
     const uint32_t g = base + e * kBlock + threadIdx.x;
-    if (g < N) rank[g] = pre + tile_rank(s_scan, e);
+    if (g < N) rank[g] = pre + tile_rank<ITEMS>(s_scan, e);
   }
 }
 
@@ -1007,6 +1033,7 @@ __global__ __launch_bounds__(kBlock) void k_init_join(const InstDesc* __restrict
 // --------------------------------------------------- per-instance numbering
 // Segmented version of k_scan_reps over the instances slot[j]: every job
 // starts its own prefix at 0.  Algorithmic bytes: 8 per state.
+template <int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict__ desc,
                                                       const uint32_t* __restrict__ slot,
                                                       const uint32_t* __restrict__ job_tile_off,
@@ -1017,7 +1044,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict
                                                       Ctrl* __restrict__ ctrl,
                                                       unsigned long long* __restrict__ scan_status) {
   __shared__ uint32_t s_tile, s_job, s_prefix;
-  __shared__ TileScanLds s_scan;
+  __shared__ TileScanLds<ITEMS> s_scan;
   if (threadIdx.x == 0) {
     const uint32_t t = atomicAdd(&ctrl->tile_counter, 1u);
     uint32_t lo = 0, hi = njobs;
@@ -1031,26 +1058,26 @@ __global__ __launch_bounds__(kBlock) void k_scan_jobs(const InstDesc* __restrict
   __syncthreads();
   const uint32_t tile = s_tile, j = s_job;
   const InstDesc D = desc[slot[j]];
-  const uint32_t base = (tile - job_tile_off[j]) * kScanTile;
+  const uint32_t base = (tile - job_tile_off[j]) * (kBlock * ITEMS);
   uint32_t fb = 0;
 #pragma unroll 8
-  for (int e = 0; e < kScanItems; ++e) {
+  for (int e = 0; e < ITEMS; ++e) {
     const uint32_t q = base + e * kBlock + threadIdx.x;
     if (q < D.n && block[D.state_off + q] == D.state_off + q) fb |= 1u << e;
   }
-  const uint32_t total = tile_ballot_count(fb, s_scan);
+  const uint32_t total = tile_ballot_count<ITEMS>(fb, s_scan);
   if (threadIdx.x < 64) {
     const uint32_t excl = lookback_wave0(scan_status, tile, total, ctrl, job_tile_off[j]);
     if (threadIdx.x == 0) {
       s_prefix = excl;
-      if (base + kScanTile >= D.n) totals[j] = excl + total;
+      if (base + kBlock * ITEMS >= D.n) totals[j] = excl + total;
     }
   }
   __syncthreads();
   const uint32_t pre = s_prefix;
-  for (int e = 0; e < kScanItems; ++e) {
+  for (int e = 0; e < ITEMS; ++e) {
     const uint32_t q = base + e * kBlock + threadIdx.x;
-    if (q < D.n) rank[D.state_off + q] = pre + tile_rank(s_scan, e);
+    if (q < D.n) rank[D.state_off + q] = pre + tile_rank<ITEMS>(s_scan, e);
   }
 }
 
@@ -1262,22 +1289,32 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
-                    unsigned long long* scan_status, hipStream_t s) {
+                    unsigned long long* scan_status, int items, hipStream_t s) {
   if (!m) return;
-  const uint32_t grid = grid_for(m, kScanTile);
-  if (batch)
-    hipLaunchKernelGGL(k_compact<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, nb, keep,
-                       changed_inst, dead, block, act_next, ctrl, scan_status);
-  else
-    hipLaunchKernelGGL(k_compact<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, nb, keep,
-                       changed_inst, dead, block, act_next, ctrl, scan_status);
+  const dim3 grid(scan_tiles(m, items));
+  if (items == kScanItemsLarge) {
+    if (batch)
+      hipLaunchKernelGGL((k_compact<true, kScanItemsLarge>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+    else
+      hipLaunchKernelGGL((k_compact<false, kScanItemsLarge>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+  } else {
+    if (batch)
+      hipLaunchKernelGGL((k_compact<true, kScanItemsSmall>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+    else
+      hipLaunchKernelGGL((k_compact<false, kScanItemsSmall>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+  }
 }
 
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
-                      Ctrl* ctrl, hipStream_t s) {
-  if (!ninst) return;
-  hipLaunchKernelGGL(k_round_end, dim3(grid_for(ninst, kBlock)), dim3(kBlock), 0, s, ninst,
-                     changed_inst, refine_cnt, last, ctrl);
+                      Ctrl* ctrl, hipStream_t s, unsigned long long* clear_status, uint32_t clear_tiles) {
+  const uint32_t threads = std::max(ninst, clear_status ? clear_tiles : 0u);
+  if (!threads) return;
+  hipLaunchKernelGGL(k_round_end, dim3(grid_for(threads, kBlock)), dim3(kBlock), 0, s, ninst,
+                     changed_inst, refine_cnt, last, ctrl, clear_status, clear_tiles);
 }
 
 void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
@@ -1301,10 +1338,15 @@ void launch_init_minmax_slots(const InstDesc* desc, const uint32_t* slot, const 
 
 void launch_scan_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_tile_off,
                       uint32_t njobs, uint32_t total_tiles, const uint32_t* block, uint32_t* rank,
-                      uint32_t* totals, Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s) {
+                      uint32_t* totals, Ctrl* ctrl, unsigned long long* scan_status, int items,
+                      hipStream_t s) {
   if (!total_tiles) return;
-  hipLaunchKernelGGL(k_scan_jobs, dim3(total_tiles), dim3(kBlock), 0, s, desc, slot, job_tile_off, njobs,
-                     block, rank, totals, ctrl, scan_status);
+  if (items == kScanItemsLarge)
+    hipLaunchKernelGGL(k_scan_jobs<kScanItemsLarge>, dim3(total_tiles), dim3(kBlock), 0, s, desc, slot,
+                       job_tile_off, njobs, block, rank, totals, ctrl, scan_status);
+  else
+    hipLaunchKernelGGL(k_scan_jobs<kScanItemsSmall>, dim3(total_tiles), dim3(kBlock), 0, s, desc, slot,
+                       job_tile_off, njobs, block, rank, totals, ctrl, scan_status);
 }
 
 void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
@@ -1371,8 +1413,9 @@ void launch_quotient(uint32_t n, uint32_t k, uint32_t nb, const uint32_t* delta,
                      uint32_t* rid, uint32_t* rep, uint32_t* min_delta, uint8_t* min_acc8, uint8_t* min_acc,
                      Ctrl* ctrl, unsigned long long* scan_status, hipStream_t s) {
   hipLaunchKernelGGL(k_mark_classes, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, visited, cls, sel);
-  launch_prep_scan(scan_status, (nb + kScanTile - 1) / kScanTile, ctrl, s);
-  launch_scan_reps(sel, nb, rid, ctrl, scan_status, s);
+  const int items = scan_items_for(nb);
+  launch_prep_scan(scan_status, scan_tiles(nb, items), ctrl, s);
+  launch_scan_reps(sel, nb, rid, ctrl, scan_status, items, s);
   hipLaunchKernelGGL(k_class_reps, dim3(grid_for(n, kBlock)), dim3(kBlock), 0, s, n, block, cls, rep);
   hipLaunchKernelGGL(k_quotient, dim3(grid_for(nb, kBlock)), dim3(kBlock), 0, s, nb, n, k, delta, accept, cls,
                      sel, rid, rep, min_delta, min_acc8);
@@ -1386,10 +1429,15 @@ void launch_prep_scan(unsigned long long* scan_status, uint32_t ntiles, Ctrl* ct
 }
 
 void launch_scan_reps(const uint32_t* block, uint32_t N, uint32_t* rank, Ctrl* ctrl,
-                      unsigned long long* scan_status, hipStream_t s) {
+                      unsigned long long* scan_status, int items, hipStream_t s) {
   if (!N) return;
-  hipLaunchKernelGGL(k_scan_reps, dim3(grid_for(N, kScanTile)), dim3(kBlock), 0, s, block, N, rank, ctrl,
-                     scan_status);
+  const dim3 grid(scan_tiles(N, items));
+  if (items == kScanItemsLarge)
+    hipLaunchKernelGGL(k_scan_reps<kScanItemsLarge>, grid, dim3(kBlock), 0, s, block, N, rank, ctrl,
+                       scan_status);
+  else
+    hipLaunchKernelGGL(k_scan_reps<kScanItemsSmall>, grid, dim3(kBlock), 0, s, block, N, rank, ctrl,
+                       scan_status);
 }
 
 void launch_emit(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,

@@ -313,7 +313,7 @@ struct Serving::Impl {
     d_act = dmalloc(cap * 4); d_act2 = dmalloc(cap * 4);
     d_slot_of = dmalloc(cap * 4); d_nb = dmalloc(cap * 4);
     d_keep = dmalloc(cap); d_rank = dmalloc(cap * 4 + 4);
-    d_status = dmalloc(((cap + kScanTile - 1) / kScanTile + kSlots + 1) * 8);
+    d_status = dmalloc(((size_t)scan_tiles(cap, kScanItemsSmall) + kSlots + 1) * 8);
     table_cap = 1ull << std::max<uint32_t>(9, ceil_log2_u64(2 * cap));
     d_table = dmalloc(table_cap * sizeof(Slot));
     d_desc = dmalloc(kSlots * sizeof(InstDesc));
@@ -581,11 +581,14 @@ struct Serving::Impl {
       const size_t nj = live.size();
       std::vector<uint32_t> slot_ids, tileoff, wgoff;
       uint32_t tiles = 0, wgs = 0;
+      uint64_t states = 0;
+      for (Resident* r : live) states += r->req->n;
+      const int items = scan_items_for(states);
       for (Resident* r : live) {
         slot_ids.push_back(r->slot);
         tileoff.push_back(tiles);
         wgoff.push_back(wgs);
-        tiles += (r->req->n + kScanTile - 1) / kScanTile;
+        tiles += scan_tiles(r->req->n, items);
         wgs += (r->req->n + kRowTile - 1) / kRowTile;
       }
       if (!grow(s_aux, nj * 4 * 3)) return DFAMIN_E_NOMEM;
@@ -598,7 +601,7 @@ struct Serving::Impl {
       launch_scan_jobs(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, tiles,
                        static_cast<uint32_t*>(d_block), static_cast<uint32_t*>(d_rank),
                        static_cast<uint32_t*>(d_totals), static_cast<Ctrl*>(d_ctrl),
-                       static_cast<unsigned long long*>(d_status), stream);
+                       static_cast<unsigned long long*>(d_status), items, stream);
       launch_emit_jobs(static_cast<InstDesc*>(d_desc), d_sl, d_sl + 2 * nj, (uint32_t)nj, wgs,
                        static_cast<uint32_t*>(d_block), static_cast<uint32_t*>(d_rank), stream);
       launch_results_jobs(static_cast<InstDesc*>(d_desc), d_sl, (uint32_t)nj,
@@ -662,7 +665,8 @@ struct Serving::Impl {
         const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2ull * m));
         const uint64_t tsize = 1ull << tbits;
         if (tsize > table_cap) return DFAMIN_E_INTERNAL;
-        const uint32_t ntiles = (m + kScanTile - 1) / kScanTile;
+        const int citems = scan_items_for(m);
+        const uint32_t ntiles = scan_tiles(m, citems);
         uint32_t* act = static_cast<uint32_t*>(d_act);
         uint32_t* nxt = static_cast<uint32_t*>(d_act2);
         launch_clear_table(static_cast<Slot*>(d_table), tsize, static_cast<Ctrl*>(d_ctrl), stream);
@@ -678,7 +682,7 @@ struct Serving::Impl {
         launch_compact(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<uint32_t*>(d_nb),
                        static_cast<uint8_t*>(d_keep), static_cast<uint32_t*>(d_changed),
                        static_cast<uint32_t*>(d_dead), static_cast<uint32_t*>(d_block), nxt,
-                       static_cast<Ctrl*>(d_ctrl), static_cast<unsigned long long*>(d_status), stream);
+                       static_cast<Ctrl*>(d_ctrl), static_cast<unsigned long long*>(d_status), citems, stream);
         launch_round_end(kSlots, static_cast<uint32_t*>(d_changed), static_cast<uint32_t*>(d_refine),
                          static_cast<uint32_t*>(d_last), static_cast<Ctrl*>(d_ctrl), stream);
         if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
