@@ -757,32 +757,38 @@ __global__ void k_naive_check(Ctrl* __restrict__ ctrl) {
 // One breadth-first level from q0 (Section 2: the minimal DFA keeps the
 // classes of reachable states): every frontier state follows each row; a
 // successor whose visited bit this thread sets first joins the next
-// frontier, one atomicAdd per row and wave.  Algorithmic bytes per frontier
-// state: 4 + per row 4 (entry) + 4 (visited word) + 4 (append).
+// frontier.  New states are staged in LDS and appended with one global
+// atomicAdd per workgroup and chunk of rows.  Algorithmic bytes per
+// frontier state: 4 + per row 4 (entry) + 4 (visited word) + 4 (append).
+constexpr uint32_t kBfsRowChunk = 8;
 __global__ __launch_bounds__(kBlock) void k_bfs_level(const uint64_t* __restrict__ rows, uint32_t nrows,
                                                       const uint32_t* __restrict__ frontier,
                                                       uint32_t fcount, uint32_t* __restrict__ visited,
                                                       uint32_t* __restrict__ next,
                                                       uint32_t* __restrict__ next_count) {
+  __shared__ uint32_t s_new[kBlock * kBfsRowChunk];
+  __shared__ uint32_t s_cnt, s_base;
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   const bool valid = j < fcount;
   const uint32_t q = valid ? frontier[j] : 0u;
-  const uint32_t lane = threadIdx.x & 63u;
-  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (uint32_t r = 0; r < nrows; ++r) {
-    bool fresh = false;
-    uint32_t t = 0;
+  for (uint32_t r0 = 0; r0 < nrows; r0 += kBfsRowChunk) {
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const uint32_t r1 = min(nrows, r0 + kBfsRowChunk);
     if (valid) {
-      t = reinterpret_cast<const uint32_t*>(rows[r])[q];
-      const uint32_t bit = 1u << (t & 31u);
-      if (!(visited[t >> 5] & bit)) fresh = !(atomicOr(&visited[t >> 5], bit) & bit);
+      for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t t = reinterpret_cast<const uint32_t*>(rows[r])[q];
+        const uint32_t bit = 1u << (t & 31u);
+        if (!(visited[t >> 5] & bit) && !(atomicOr(&visited[t >> 5], bit) & bit))
+          s_new[atomicAdd(&s_cnt, 1u)] = t;
+      }
     }
-    const unsigned long long mask = __ballot(fresh);
-    if (!mask) continue;
-    uint32_t base = 0;
-    if (lane == (uint32_t)__builtin_ctzll(mask)) base = atomicAdd(next_count, (uint32_t)__popcll(mask));
-    base = __shfl(base, (int)__builtin_ctzll(mask), 64);
-    if (fresh) next[base + (uint32_t)__popcll(mask & lt)] = t;
+    __syncthreads();
+    const uint32_t cnt = s_cnt;
+    if (threadIdx.x == 0 && cnt) s_base = atomicAdd(next_count, cnt);
+    __syncthreads();
+    for (uint32_t x = threadIdx.x; x < cnt; x += kBlock) next[s_base + x] = s_new[x];
+    __syncthreads();
   }
 }
 
