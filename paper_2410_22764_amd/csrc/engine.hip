@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstdlib>
+#include <chrono>
 #include <cstring>
 
 namespace dfamin {
@@ -329,6 +330,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   std::vector<uint64_t> cnt(I, 0);
   std::vector<uint8_t> cnt_ok(I, 0);
   std::vector<uint32_t> exact, scan;
+  std::vector<uint32_t> alist(I);  // instances still refining, in order
+  for (size_t i = 0; i < I; ++i) alist[i] = (uint32_t)i;
   TRY(ensure(d_djobs_, 4 * I * 4 + 64));
   TRY(ensure_host(h_jobs_, 4 * I * 4 + 64));
   TRY(ensure_host(h_desc_, I * sizeof(InstDesc)));
@@ -341,12 +344,19 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     last.assign(h, h + words);
     return check_hip(hipMemcpyAsync(d, h, words * 4, hipMemcpyHostToDevice, s));
   };
+  // host-side time per phase of the round loop (printed with DFAMIN_TRACE)
+  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
+  double t_plan = 0, t_issue = 0, t_wait = 0, t_post = 0;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto us = [](auto a, auto b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
+  auto tp0 = now();
   while (m > 0) {
+    tp0 = now();
     if (any_auto && rounds == auto_rounds) {
       // instances still refining after auto_rounds rounds get the closure
       std::vector<uint32_t> which;
-      for (size_t i = 0; i < I; ++i)
-        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && active[i]) which.push_back((uint32_t)i);
+      for (uint32_t i : alist)
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO) which.push_back(i);
       if (!which.empty()) {
         TRY(build_closure(which, opts, s));
         TRY(upload_layout(s));
@@ -356,8 +366,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     if (rounds >= max_rounds) return DFAMIN_E_INTERNAL;
     bool dirty = false;
     // doubling instances: this round's single closure level
-    for (size_t i = 0; i < I; ++i) {
-      if (!dbl[i] || !active[i]) continue;
+    for (uint32_t i : alist) {
+      if (!dbl[i]) continue;
       const uint32_t nrows = (uint32_t)inst_rows_[i].size();
       uint32_t lvl = (uint32_t)floor_log2_u64(mj[i] + 1);
       if (lvl > nrows - 1) lvl = nrows - 1;
@@ -375,22 +385,20 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     exact.clear();
     uint32_t eb_max = 0;
     bool any_hash = false;
-    for (size_t i = 0; i < I; ++i) {
+    for (uint32_t i : alist) {
       const uint64_t kp1 = desc_[i].kp + 1ull;
       uint32_t eb = 0, ds = 0;
-      if (active[i]) {
-        if (rounds == 0) {
-          if (kp1 <= 31) { eb = 1; ds = 1; }
-        } else if (cnt_ok[i]) {
-          const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(std::max<uint64_t>(cnt[i], 1)));
-          if (kp1 * bits <= 31) {
-            eb = bits;
-            exact.push_back((uint32_t)i);
-            eb_max = std::max(eb_max, eb);
-          }
+      if (rounds == 0) {
+        if (kp1 <= 31) { eb = 1; ds = 1; }
+      } else if (cnt_ok[i]) {
+        const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(std::max<uint64_t>(cnt[i], 1)));
+        if (kp1 * bits <= 31) {
+          eb = bits;
+          exact.push_back(i);
+          eb_max = std::max(eb_max, eb);
         }
       }
-      if (active[i] && eb == 0) any_hash = true;
+      if (eb == 0) any_hash = true;
       if (desc_[i].ebits != eb || desc_[i].dsrc != ds) {
         desc_[i].ebits = eb;
         desc_[i].dsrc = ds;
@@ -423,8 +431,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     // Table: twice the number of groups this round can form, at most m.  An
     // exact-key instance forms at most 2^((kp+1) * ebits) groups.
     uint64_t groups = 0;
-    for (size_t i = 0; i < I && groups < m; ++i) {
-      if (!active[i]) continue;
+    for (uint32_t i : alist) {
+      if (groups >= m) break;
       const uint64_t width = (desc_[i].kp + 1ull) * desc_[i].ebits;
       groups += (desc_[i].ebits && width < 32) ? std::min<uint64_t>(in_[i].n, 1ull << width) : in_[i].n;
     }
@@ -437,6 +445,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     const double md = (double)m;
     const double inst_b = batch ? 4.0 : 0.0;
 
+    const auto tp1 = now();
+    t_plan += us(tp0, tp1);
     // Signature tile: forced, cached for this size class, or tuned now by
     // running every variant once on a freshly cleared table (the last run's
     // table and slot ids are as valid as any other's).
@@ -507,8 +517,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     // the round: instances that were refining before this round and whose
     // next signature could fit 31 bits, B <= min(n, B^(kp+1)) after it.
     scan.clear();
-    for (size_t i = 0; i < I; ++i) {
-      if (!active[i]) continue;
+    for (uint32_t i : alist) {
       const uint64_t B = cnt_ok[i] ? std::max<uint64_t>(cnt[i], 1) : ub[i];
       const uint64_t kp1 = desc_[i].kp + 1ull;
       const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
@@ -545,7 +554,11 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     HIP(hipGetLastError());
     // one copy: control block, refine counters, and the counts just scanned
     HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl) + 4 * I + 4 * (size_t)ns, hipMemcpyDeviceToHost, s));
+    const auto tp2 = now();
+    t_issue += us(tp1, tp2);
     HIP(stream_wait(s));
+    const auto tp3 = now();
+    t_wait += us(tp2, tp3);
     prof.collect();
     const Ctrl c = *h_rb_.as<Ctrl>();
     const uint32_t* h_refine = reinterpret_cast<const uint32_t*>(h_rb_.as<char>() + sizeof(Ctrl));
@@ -568,8 +581,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     }
     ++rounds;
     const uint32_t* rc = h_refine;
-    for (size_t i = 0; i < I; ++i) {
-      if (!active[i]) continue;
+    for (uint32_t i : alist) {
       // a round maps each block to at most B^(kp+1) signatures
       const uint64_t kp1 = desc_[i].kp + 1ull;
       const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(ub[i]));
@@ -578,10 +590,15 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       mj[i] += dbl[i] ? step[i] : 1;
       active[i] = rc[i] == rounds;
     }
+    alist.erase(std::remove_if(alist.begin(), alist.end(), [&](uint32_t i) { return !active[i]; }), alist.end());
     std::swap(cur, nxt);
     m = c.m_next;
+    t_post += us(tp3, now());
     if (!c.any_changed) break;
   }
+  if (trace)
+    std::fprintf(stderr, "[dfamin] host us over %llu rounds: plan %.0f issue %.0f wait %.0f post %.0f\n",
+                 (unsigned long long)rounds, t_plan, t_issue, t_wait, t_post);
 
   return DFAMIN_OK;
 }

@@ -255,22 +255,44 @@ def dfamin_minimize_batch(ctx, dfas, opts=None, check=True):
     return outs, results
 
 
+class BatchDevice:
+    """Arguments of dfamin_minimize_batch_device marshalled once: a batch of
+    DFAs in device memory that is minimized repeatedly (same buffers) pays
+    for building the ctypes arrays only here, not on every call."""
+
+    def __init__(self, specs, out_ptrs):
+        count = len(specs)
+        self.count = count
+        self.arr = (Dfa * max(count, 1))()
+        for i, (n, k, dp, ap, q0) in enumerate(specs):
+            self.arr[i] = Dfa(int(n), int(k), int(dp), int(ap), int(q0))
+        self.optr = (ctypes.c_void_p * max(count, 1))(*[int(p) for p in out_ptrs])
+        self.res = (Result * max(count, 1))()
+
+    def run(self, ctx, opts=None, stream=0, check=True):
+        rc = load().dfamin_minimize_batch_device(ctx.handle, self.count, self.arr, _opts(opts), self.optr,
+                                                 self.res, int(stream) or None)
+        if check and rc != DFAMIN_OK:
+            raise DfaminError(rc, "dfamin_minimize_batch_device")
+        return rc
+
+    def field(self, name):
+        """One result field for every instance, as a numpy array."""
+        view = np.ctypeslib.as_array(self.res)
+        return np.array(view[name][: self.count])
+
+    def results(self, rc=DFAMIN_OK):
+        out = [self.res[i].as_dict() for i in range(self.count)]
+        for r in out:
+            r["rc"] = rc
+        return out
+
+
 def dfamin_minimize_batch_device(ctx, specs, out_ptrs, opts=None, stream=0, check=True):
     """specs: list of (n, k, delta_ptr, accept_ptr, q0) with device pointers."""
-    count = len(specs)
-    arr = (Dfa * max(count, 1))()
-    for i, (n, k, dp, ap, q0) in enumerate(specs):
-        arr[i] = Dfa(int(n), int(k), int(dp), int(ap), int(q0))
-    optr = (ctypes.c_void_p * max(count, 1))(*[int(p) for p in out_ptrs])
-    res = (Result * max(count, 1))()
-    rc = load().dfamin_minimize_batch_device(ctx.handle, count, arr, _opts(opts), optr, res,
-                                             int(stream) or None)
-    if check and rc != DFAMIN_OK:
-        raise DfaminError(rc, "dfamin_minimize_batch_device")
-    results = [res[i].as_dict() for i in range(count)]
-    for r in results:
-        r["rc"] = rc
-    return results
+    b = BatchDevice(specs, out_ptrs)
+    rc = b.run(ctx, opts, stream, check)
+    return b.results(rc)
 
 
 def dfamin_submit(ctx, dfa, opts=None):
