@@ -56,12 +56,17 @@ WORKLOADS = {
 }
 
 
+# Sources that decide what the benchmarked kernels do (the kernels, their
+# launch parameters and the engine's choices); the serving loop and the C-ABI
+# wrappers do not take part in these workloads.
+KERNEL_SOURCES = ("kernels.hip", "internal.h", "engine.hip", "engine.h", "closure.hip", "closure.h")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2410_22764_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 

@@ -19,6 +19,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -197,6 +198,9 @@ struct Serving::Impl {
   ~Impl() { shutdown(); }
 
   Context* ctx;
+  // worker-side totals (printed at shutdown with DFAMIN_TRACE)
+  double t_join = 0, t_round = 0;
+  uint64_t iters = 0, joined = 0;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<std::shared_ptr<Request>> queue;
@@ -237,6 +241,9 @@ struct Serving::Impl {
     }
     cv_work.notify_all();
     if (worker.joinable()) worker.join();
+    if (std::getenv("DFAMIN_TRACE"))
+      std::fprintf(stderr, "[dfamin] serving: %llu iterations, %llu joined; join %.0f us, rounds %.0f us\n",
+                   (unsigned long long)iters, (unsigned long long)joined, t_join, t_round);
     {
       std::lock_guard<std::mutex> g(mu);
       for (auto& r : queue) { r->status = DFAMIN_E_CANCELLED; }
@@ -833,8 +840,15 @@ struct Serving::Impl {
         }
       }
       int rc = DFAMIN_OK;
+      const auto t0 = std::chrono::steady_clock::now();
       if (!joining.empty()) rc = join(joining);
+      const auto t1 = std::chrono::steady_clock::now();
       if (rc == DFAMIN_OK && any_resident()) rc = round();
+      const auto t2 = std::chrono::steady_clock::now();
+      t_join += std::chrono::duration<double, std::micro>(t1 - t0).count();
+      t_round += std::chrono::duration<double, std::micro>(t2 - t1).count();
+      iters += 1;
+      joined += joining.size();
       if (rc != DFAMIN_OK) {
         fail_all(rc);
         m = 0;
