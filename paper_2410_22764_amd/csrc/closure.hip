@@ -2,6 +2,9 @@
 #include "closure.h"
 
 #include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 
 #include "../../include/dfamin.h"
 
@@ -32,7 +35,11 @@ int build_closure_levels(std::vector<ClosureSpec>& specs, const ClosureScratch& 
   }
   struct Pending { uint32_t w, x, level; };
   uint32_t level = 0, batch = 1;
+  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto us = [](auto a, auto b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
   while (true) {
+    const auto t0 = now();
     // levels level+1 .. level+batch for every open letter
     std::vector<RowJob> jobs;
     std::vector<uint32_t> joboff;
@@ -90,9 +97,13 @@ int build_closure_levels(std::vector<ClosureSpec>& specs, const ClosureScratch& 
       launch_closure_level(d_jobs + lb, d_off + lb, le - lb, lvl_wgs[b], d_wg, d_flags + lb, s);
     }
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
+    const auto t1 = now();
     if (hipMemcpyAsync(h_flags, d_flags, jobs.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         stream_wait(s) != hipSuccess)
       return DFAMIN_E_DEVICE;
+    if (trace)
+      std::fprintf(stderr, "[dfamin] closure levels %u..%u: %zu jobs, %zu words, host %.0f us, device wait %.0f us\n",
+                   level + 1, level + batch, jobs.size(), words, us(t0, t1), us(t1, now()));
     // keep each letter's levels in order up to its first equal/identity one
     for (size_t j = 0; j < who.size(); ++j) {
       const Pending& p = who[j];

@@ -91,6 +91,13 @@ class Engine {
   int ensure(DevBuf& b, size_t bytes);
   int ensure_host(HostBuf& b, size_t bytes);
   int build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts, hipStream_t s);
+  // Closure levels of unary doubling instances, computed round by round.
+  struct LevelTodo {
+    uint32_t inst, level, step;
+  };
+  int lazy_levels(const std::vector<uint32_t>& which, const dfamin_opts& opts,
+                  std::vector<uint32_t>& rest, std::vector<uint8_t>& lazy);
+  int queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s);
   int signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
  public:
   // After run() on one instance: the states reachable from q0 (breadth
@@ -124,8 +131,9 @@ class Engine {
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
   DevBuf d_visit_, d_bfs_rows_, d_min_delta_, d_min_acc_;
+  DevBuf d_lvl_, d_lvl_wg_, d_lvl_flags_;  // level jobs of lazily built closure levels
   DevBuf d_rb_;  // owns d_ctrl_, d_refine_ and d_counts_ (views into it, reset every run)
-  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_, h_rb_;
+  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_, h_rb_, h_lvl_;
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {
     uint32_t n, ninst, parity;

@@ -123,12 +123,13 @@ Engine::~Engine() {
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
-                    &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
+                    &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf& b : closure_bufs_)
     if (b.p) (void)hipFree(b.p);
-  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_, &h_rb_};
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_, &h_rb_, &h_lvl_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -138,7 +139,8 @@ uint64_t Engine::device_bytes() const {
                           &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                           &d_results_, &d_wgflags_, &d_part_, &d_dense_,
-                          &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_};
+                          &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
+                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -281,6 +283,111 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
   return DFAMIN_OK;
 }
 
+// Level storage for the unary instances in `which` that refine by doubling
+// (one non-identity letter a).  A doubling round from P_j reads the single
+// level 2^l <= j+1, and j at least doubles from one round to the next, so
+// each level is computed (one pointer-jumping pass, Algorithm 5) in the round
+// that first reads it rather than all up front between host checks.  No
+// level is tested for equality with its predecessor or for the identity:
+// with t <= j+1 the letter a^t gives P_{j+t} whatever it is.  Rows 0..L point
+// at delta_a and the L level buffers; the other instances of `which` go to
+// `rest` (all of them if the storage does not fit under the closure cap).
+int Engine::lazy_levels(const std::vector<uint32_t>& which, const dfamin_opts& opts,
+                        std::vector<uint32_t>& rest, std::vector<uint8_t>& lazy) {
+  std::vector<uint32_t> uni;
+  for (uint32_t i : which) (nonid_[i].size() == 1 ? uni : rest).push_back(i);
+  if (uni.empty()) return DFAMIN_OK;
+  auto levels_of = [&](uint32_t i) {
+    uint32_t l = floor_log2_u32(in_[i].n);
+    if (opts.max_levels && opts.max_levels < l) l = opts.max_levels;
+    return l;
+  };
+  uint64_t words = 0;
+  for (uint32_t i : uni) words += (uint64_t)levels_of(i) * in_[i].n;
+  const uint64_t cap = ctx_->budget > ctx_->used ? (ctx_->budget - ctx_->used) / 2 : 0;
+  char* base = nullptr;
+  if (words) {
+    if (words * 4 > cap) {
+      rest.insert(rest.end(), uni.begin(), uni.end());
+      return DFAMIN_OK;
+    }
+    if (closure_cursor_ == closure_bufs_.size()) closure_bufs_.emplace_back();
+    DevBuf& b = closure_bufs_[closure_cursor_];
+    if (ensure(b, words * 4) != DFAMIN_OK) {
+      rest.insert(rest.end(), uni.begin(), uni.end());
+      return DFAMIN_OK;
+    }
+    ++closure_cursor_;
+    base = static_cast<char*>(b.p);
+  }
+  uint64_t off = 0;
+  for (uint32_t i : uni) {
+    const uint32_t L = levels_of(i), a = nonid_[i][0];
+    std::vector<uint64_t> r(1 + (size_t)L);
+    r[0] = reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n;
+    for (uint32_t l = 1; l <= L; ++l) {
+      r[l] = reinterpret_cast<uint64_t>(base + 4 * off);
+      off += in_[i].n;
+    }
+    inst_rows_[i] = std::move(r);
+    levels_[i] = 0;
+    has_closure_[i] = 1;
+    lazy[i] = 1;
+  }
+  return DFAMIN_OK;
+}
+
+// Queues the level passes of one round: step 0 holds each instance's first
+// missing level, step 1 the next one, and so on (one launch per step).
+int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
+  const size_t J = todo.size();
+  uint32_t S = 0;
+  for (const LevelTodo& t : todo) S = std::max(S, t.step + 1);
+  const size_t bytes = J * (sizeof(RowJob) + 4);
+  TRY(ensure_host(h_lvl_, bytes));
+  TRY(ensure(d_lvl_, bytes));
+  RowJob* hj = h_lvl_.as<RowJob>();
+  uint32_t* ho = reinterpret_cast<uint32_t*>(hj + J);
+  std::vector<uint32_t> begin(S + 1, 0), wgs(S, 0);
+  uint32_t c = 0, maxw = 0;
+  double alg = 0;
+  for (uint32_t st = 0; st < S; ++st) {
+    begin[st] = c;
+    uint32_t w = 0;
+    for (const LevelTodo& t : todo) {
+      if (t.step != st) continue;
+      const std::vector<uint64_t>& r = inst_rows_[t.inst];
+      RowJob R;
+      R.src = r[t.level - 1];
+      R.dst = r[t.level];
+      R.n = in_[t.inst].n;
+      R.flag_idx = c;
+      hj[c] = R;
+      ho[c] = w;
+      w += (R.n + kRowTile - 1) / kRowTile;
+      alg += 12.0 * R.n;
+      ++c;
+    }
+    wgs[st] = w;
+    maxw = std::max(maxw, w);
+  }
+  begin[S] = c;
+  TRY(ensure(d_lvl_wg_, (size_t)maxw * 4));
+  TRY(ensure(d_lvl_flags_, J * 4));
+  HIP(hipMemcpyAsync(d_lvl_.p, h_lvl_.p, bytes, hipMemcpyHostToDevice, s));
+  RowJob* dj = d_lvl_.as<RowJob>();
+  uint32_t* dof = reinterpret_cast<uint32_t*>(dj + J);
+  Profiler& prof = ctx_->prof;
+  prof.begin(s, "closure", alg);
+  for (uint32_t st = 0; st < S; ++st)
+    if (begin[st + 1] > begin[st])
+      launch_closure_level(dj + begin[st], dof + begin[st], begin[st + 1] - begin[st], wgs[st],
+                           d_lvl_wg_.as<uint32_t>(), d_lvl_flags_.as<uint32_t>() + begin[st], s);
+  prof.end(s);
+  HIP(hipGetLastError());
+  return DFAMIN_OK;
+}
+
 // Signature rounds (Algorithm 4, Section 3.3) over the active states until no
 // instance splits a block.
 int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s) {
@@ -325,6 +432,24 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   // per level.
   std::vector<uint8_t> active(I, 1), dbl(I, 0);
   std::vector<uint64_t> mj(I, 0), step(I, 1);
+  // Doubling instances with lazily built levels: levels computed so far.
+  // On every way out the rows are cut to the built levels, which is what
+  // later readers of the closure rows (the reachability search) may follow.
+  std::vector<uint8_t> lazy(I, 0);
+  std::vector<uint32_t> built(I, 0);
+  std::vector<LevelTodo> todo;
+  struct TrimLazy {
+    Engine* e;
+    const std::vector<uint8_t>& lazy;
+    const std::vector<uint32_t>& built;
+    ~TrimLazy() {
+      for (size_t i = 0; i < lazy.size(); ++i)
+        if (lazy[i]) {
+          e->inst_rows_[i].resize((size_t)built[i] + 1);
+          e->levels_[i] = built[i];
+        }
+    }
+  } trim_lazy{this, lazy, built};
   // Exact block counts (and instance-relative ranks in d_rank_) of the
   // instances scanned at the end of the previous round; cnt_ok marks them.
   std::vector<uint64_t> cnt(I, 0);
@@ -346,7 +471,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   };
   // host-side time per phase of the round loop (printed with DFAMIN_TRACE)
   const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
-  double t_plan = 0, t_issue = 0, t_wait = 0, t_post = 0;
+  double t_plan = 0, t_issue = 0, t_wait = 0, t_post = 0, t_closure = 0, t_desc = 0;
+  uint32_t n_dirty = 0;
   auto now = [] { return std::chrono::steady_clock::now(); };
   auto us = [](auto a, auto b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
   auto tp0 = now();
@@ -358,10 +484,16 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       for (uint32_t i : alist)
         if (in_[i].closure == DFAMIN_CLOSURE_AUTO) which.push_back(i);
       if (!which.empty()) {
-        TRY(build_closure(which, opts, s));
+        std::vector<uint32_t> rest;
+        TRY(lazy_levels(which, opts, rest, lazy));
+        if (!rest.empty()) TRY(build_closure(rest, opts, s));
+        if (trace)
+          std::fprintf(stderr, "[dfamin] closure planned for %zu instances (%zu built up front): %.0f us\n",
+                       which.size(), rest.size(), us(tp0, now()));
         TRY(upload_layout(s));
         for (uint32_t i : which) dbl[i] = nonid_[i].size() == 1;
       }
+      if (trace) t_closure += us(tp0, now());
     }
     if (rounds >= max_rounds) return DFAMIN_E_INTERNAL;
     bool dirty = false;
@@ -372,11 +504,19 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       uint32_t lvl = (uint32_t)floor_log2_u64(mj[i] + 1);
       if (lvl > nrows - 1) lvl = nrows - 1;
       step[i] = 1ull << lvl;
+      if (lazy[i] && built[i] < lvl) {
+        for (uint32_t l = built[i] + 1; l <= lvl; ++l) todo.push_back({i, l, l - built[i] - 1});
+        built[i] = lvl;
+      }
       if (desc_[i].rows_off != row_base_[i] + lvl || desc_[i].kp != 1) {
         desc_[i].rows_off = row_base_[i] + lvl;
         desc_[i].kp = 1;
         dirty = true;
       }
+    }
+    if (!todo.empty()) {
+      TRY(queue_levels(todo, s));
+      todo.clear();
     }
     // Key mode per instance (see InstDesc): exact keys while
     // (kp+1) * ceil(log2 B) fits in 31 bits, B = blocks before this round
@@ -425,8 +565,13 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       prof.end(s);
     }
     if (dirty) {
+      const auto td = now();
       std::memcpy(h_desc_.p, desc_.data(), I * sizeof(InstDesc));
       HIP(hipMemcpyAsync(d_desc_.p, h_desc_.p, I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+      if (trace) {
+        t_desc += us(td, now());
+        ++n_dirty;
+      }
     }
     // Table: twice the number of groups this round can form, at most m.  An
     // exact-key instance forms at most 2^((kp+1) * ebits) groups.
@@ -597,8 +742,10 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     if (!c.any_changed) break;
   }
   if (trace)
-    std::fprintf(stderr, "[dfamin] host us over %llu rounds: plan %.0f issue %.0f wait %.0f post %.0f\n",
-                 (unsigned long long)rounds, t_plan, t_issue, t_wait, t_post);
+    std::fprintf(stderr,
+                 "[dfamin] host us over %llu rounds: plan %.0f (closure %.0f, descriptors %.0f in %u rounds) "
+                 "issue %.0f wait %.0f post %.0f\n",
+                 (unsigned long long)rounds, t_plan, t_closure, t_desc, n_dirty, t_issue, t_wait, t_post);
 
   return DFAMIN_OK;
 }
@@ -816,7 +963,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
       J.n = in_[i].n;
       J.flag_idx = (uint32_t)jobs.size();
       joboff.push_back(wgs);
-      wgs += (J.n + kRowTile - 1) / kRowTile;
+      wgs += (J.n + kLongTile - 1) / kLongTile;
       jobs.push_back(J);
       job_inst.push_back((uint32_t)i);
     }

@@ -42,6 +42,7 @@ constexpr uint64_t kTuneMinStates = 1ull << 18;  // smaller rounds use the defau
 constexpr uint32_t kGraphRounds = 16;  // leader-election rounds per captured graph
 constexpr uint32_t kBfsLevelsBeforeClosure = 64;  // BFS levels before closure rows join
 constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
+constexpr int kLongTile = kBlock * 16;  // row elements per workgroup of validation
 
 // Per-instance descriptor (device copy).  64 bytes.
 //

@@ -179,13 +179,23 @@ __device__ __forceinline__ uint32_t tile_rank(const TileScanLds<ITEMS>& t, int e
 // Workgroup -> job by binary search over the exclusive workgroup prefix.
 __device__ __forceinline__ uint32_t find_job(const uint32_t* job_wg_off, uint32_t njobs,
                                              uint32_t* s_job) {
-  if (threadIdx.x == 0) {
-    uint32_t lo = 0, hi = njobs;  // largest j with job_wg_off[j] <= blockIdx.x
+  // Largest j with job_wg_off[j] <= blockIdx.x (offsets strictly increase,
+  // job_wg_off[0] = 0).  The first wave searches 64-ary: each step loads 64
+  // evenly spaced offsets of [lo, hi) at once and keeps the span after the
+  // last one not above blockIdx.x, so 4,096 jobs take two dependent loads.
+  if (threadIdx.x < 64) {
+    const uint32_t lane = threadIdx.x;
+    uint32_t lo = 0, hi = njobs;
     while (hi - lo > 1) {
-      uint32_t mid = (lo + hi) >> 1;
-      if (job_wg_off[mid] <= blockIdx.x) lo = mid; else hi = mid;
+      const uint32_t step = (hi - lo + 63) / 64;
+      const uint32_t idx = lo + lane * step;
+      const bool ok = idx < hi && job_wg_off[idx] <= blockIdx.x;
+      const unsigned long long mask = __ballot(ok);  // a prefix of lanes; lane 0 always
+      const uint32_t last = 63u - (uint32_t)__builtin_clzll(mask);
+      lo += last * step;
+      hi = min(hi, lo + step);
     }
-    *s_job = lo;
+    if (lane == 0) *s_job = lo;
   }
   __syncthreads();
   return *s_job;
@@ -212,10 +222,10 @@ __global__ __launch_bounds__(kBlock) void k_row_check(const RowJob* __restrict__
   const uint32_t j = find_job(job_wg_off, njobs, &s_job);
   const RowJob J = jobs[j];
   const uint32_t* __restrict__ row = reinterpret_cast<const uint32_t*>(J.src);
-  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kLongTile;
   uint32_t bits = 0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < kLongTile / kBlock; ++e) {
     uint32_t q = base + e * kBlock + threadIdx.x;
     if (q < J.n) {
       uint32_t v = row[q];
@@ -239,15 +249,16 @@ __global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restri
   const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(J.src);
   uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(J.dst);
   const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
-  uint32_t s1[4];
+  constexpr int kItems = kRowTile / kBlock;
+  uint32_t s1[kItems];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < kItems; ++e) {
     uint32_t q = base + e * kBlock + threadIdx.x;
     s1[e] = (q < J.n) ? src[q] : 0u;
   }
   uint32_t bits = 0;
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
+  for (int e = 0; e < kItems; ++e) {
     uint32_t q = base + e * kBlock + threadIdx.x;
     if (q < J.n) {
       uint32_t s2 = src[s1[e]];

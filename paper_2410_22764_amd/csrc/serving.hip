@@ -483,7 +483,7 @@ struct Serving::Impl {
         J.n = r->req->n;
         J.flag_idx = (uint32_t)jobs.size();
         joboff.push_back(wgs);
-        wgs += (J.n + kRowTile - 1) / kRowTile;
+        wgs += (J.n + kLongTile - 1) / kLongTile;
         jobs.push_back(J);
       }
     if (!grow(s_jobs, jobs.size() * sizeof(RowJob)) || !grow(s_off, joboff.size() * 4) ||

@@ -107,11 +107,14 @@ def test_deep_chain_workload_closed_form(ctx):
 def test_deep_chain_auto(ctx):
     """AUTO on the 2^20 chain: 8 plain rounds reach P_8, then doubling rounds
     with t = 8, 16, ..., 2^19 reach P_(2^20), the first partition with every
-    state alone: 8 + 17 = 25 refining rounds (5 + ceil(log2(n - 2)))."""
+    state alone: 8 + 17 = 25 refining rounds (5 + ceil(log2(n - 2))).  The
+    doubling rounds read levels 3..19 and each level is computed in the round
+    that first reads it, so 19 levels are built (no state is left to refine
+    after the last split)."""
     d = W.deep_chain()
     out, res = _run(ctx, d, "auto")
     assert res["num_blocks"] == d.n and np.array_equal(out, np.arange(d.n))
-    assert res["closure_levels"] == 20
+    assert res["closure_levels"] == 19 and res["closure_letters"] == 20
     assert res["refine_rounds"] == 25 and res["rounds_executed"] == 26
 
 
