@@ -225,14 +225,17 @@ def serving_run(ctx, seed, count, pool_size, load, threads=64):
     _, specs = W.serving_stream(seed, pool_size, 1.0)
     pool = [W.make_request(sp) for sp in specs]
     opts = {"closure": "auto"}
-    # saturation: submit the whole pool at once, closed loop
+    # saturation: submit the whole pool at once, closed loop; the first pass
+    # warms the library's caches (device pool, page-locked staging, tuned
+    # tiles) and is not timed
     print("[bench] serving: saturation", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    ts = [dfamin.dfamin_submit(ctx, d, opts) for d in pool]
-    for d, t in zip(pool, ts):
-        rc, _, _ = dfamin.dfamin_wait(ctx, t, d.n)
-        assert rc == 0
-    sat = len(pool) / (time.perf_counter() - t0)
+    for timed in (False, True):
+        t0 = time.perf_counter()
+        ts = [dfamin.dfamin_submit(ctx, d, opts) for d in pool]
+        for d, t in zip(pool, ts):
+            rc, _, _ = dfamin.dfamin_wait(ctx, t, d.n)
+            assert rc == 0
+        sat = len(pool) / (time.perf_counter() - t0)
     rate = load * sat
     arrivals, _ = W.serving_stream(seed + 1, count, rate)
     order = W.uniform_below(W.stream_key(seed, "serve", "order"), count, pool_size)

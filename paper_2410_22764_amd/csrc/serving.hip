@@ -157,16 +157,96 @@ class DevicePool {
   uint64_t budget_ = 0, used_ = 0, cached_ = 0;
 };
 
+// Page-locked host buffers for request inputs and outputs, reused by
+// power-of-two size class and bounded by a byte cap.  Copies from and to
+// page-locked memory run as asynchronous DMA at the full link rate, and
+// reuse spares every request the page faults of fresh host memory.  Shared
+// by the callers of submit/wait and the worker (hence the lock).
+class PinnedPool {
+ public:
+  explicit PinnedPool(uint64_t cap) : cap_(cap) {}
+  ~PinnedPool() {
+    for (auto& kv : free_)
+      for (void* p : kv.second) (void)hipHostFree(p);
+  }
+  // nullptr when the cap or the allocator says no (callers fall back to
+  // pageable memory)
+  void* alloc(size_t bytes, size_t* cls) {
+    const size_t c = DevicePool::size_class(bytes);
+    std::lock_guard<std::mutex> g(mu_);
+    auto& fl = free_[c];
+    if (!fl.empty()) {
+      void* p = fl.back();
+      fl.pop_back();
+      *cls = c;
+      return p;
+    }
+    // Blocks are never given back before the pool goes: unpinning (and
+    // pinning again) hundreds of megabytes costs far more than the pageable
+    // copy it would save, so past the cap requests use ordinary memory.
+    if (total_ + c > cap_) return nullptr;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, c, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    total_ += c;
+    *cls = c;
+    return p;
+  }
+  void free(void* p, size_t cls) {
+    std::lock_guard<std::mutex> g(mu_);
+    free_[cls].push_back(p);
+  }
+
+ private:
+  std::mutex mu_;
+  std::map<size_t, std::vector<void*>> free_;
+  uint64_t cap_ = 0, total_ = 0;
+};
+constexpr uint64_t kPinnedCap = 8ull << 30;
+
+// A host buffer of a request: page-locked from the pool when it fits, else
+// ordinary memory.
+struct HostStage {
+  std::shared_ptr<PinnedPool> pool;
+  void* pinned = nullptr;
+  size_t cls = 0;
+  std::vector<uint8_t> plain;
+  void* data() { return pinned ? pinned : plain.data(); }
+  bool make(const std::shared_ptr<PinnedPool>& pl, size_t bytes) {
+    release();
+    pool = pl;
+    pinned = pool ? pool->alloc(bytes, &cls) : nullptr;
+    if (pinned) return true;
+    try {
+      plain.resize(bytes);
+    } catch (...) {
+      return false;
+    }
+    return true;
+  }
+  void release() {
+    if (pinned) pool->free(pinned, cls);
+    pinned = nullptr;
+    std::vector<uint8_t>().swap(plain);
+  }
+  ~HostStage() { release(); }
+};
+
 struct Request {
   uint64_t ticket = 0;
   uint32_t n = 0, k = 0, q0 = 0;
   dfamin_opts opts{};
-  std::vector<uint32_t> delta;
-  std::vector<uint8_t> accept;
-  std::vector<uint32_t> out;
+  HostStage in;   // delta (4nk bytes), then the accept bitmap (ceil(n/8) bytes)
+  HostStage out;  // n block ids, filled by the worker at retirement
   dfamin_result result{};
   int status = 1;  // 1 pending, else a DFAMIN_* code
   std::atomic<bool> cancelled{false};
+  size_t delta_bytes() const { return 4ull * n * k; }
+  size_t accept_bytes() const { return ((size_t)n + 7) / 8; }
+  const void* delta() { return in.data(); }
+  const void* accept() { return static_cast<char*>(in.data()) + delta_bytes(); }
 };
 
 struct Resident {
@@ -198,6 +278,9 @@ struct Serving::Impl {
   ~Impl() { shutdown(); }
 
   Context* ctx;
+  // declared before the queue and the tickets: requests give their host
+  // buffers back to it, so it must outlive them (they also hold a reference)
+  std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>(kPinnedCap);
   // worker-side totals (printed at shutdown with DFAMIN_TRACE)
   double t_join = 0, t_round = 0;
   uint64_t iters = 0, joined = 0;
@@ -465,9 +548,9 @@ struct Serving::Impl {
   int join(std::vector<Resident*>& js) {
     // upload inputs
     for (Resident* r : js) {
-      if (hipMemcpyAsync(r->d_delta, r->req->delta.data(), r->sz_delta, hipMemcpyHostToDevice, stream) !=
+      if (hipMemcpyAsync(r->d_delta, r->req->delta(), r->sz_delta, hipMemcpyHostToDevice, stream) !=
               hipSuccess ||
-          hipMemcpyAsync(r->d_accept, r->req->accept.data(), r->req->accept.size(), hipMemcpyHostToDevice,
+          hipMemcpyAsync(r->d_accept, r->req->accept(), r->req->accept_bytes(), hipMemcpyHostToDevice,
                          stream) != hipSuccess)
         return DFAMIN_E_DEVICE;
     }
@@ -500,6 +583,7 @@ struct Serving::Impl {
     if (hipMemcpyAsync(h_flags.p, s_flags.p, jobs.size() * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
         stream_wait(stream) != hipSuccess)
       return DFAMIN_E_DEVICE;
+    for (Resident* r : js) r->req->in.release();  // the inputs are on the device now
     const uint32_t* f = h_flags.as<uint32_t>();
     std::vector<Resident*> ok, need_closure;
     size_t j = 0;
@@ -616,7 +700,7 @@ struct Serving::Impl {
                           static_cast<ResultDev*>(d_results), stream);
       if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
       for (Resident* r : live) {
-        r->req->out.resize(r->req->n);
+        if (!r->req->out.make(pinned, 4ull * r->req->n)) return DFAMIN_E_NOMEM;
         if (hipMemcpyAsync(r->req->out.data(), r->d_out, 4ull * r->req->n, hipMemcpyDeviceToHost, stream) !=
             hipSuccess)
           return DFAMIN_E_DEVICE;
@@ -879,12 +963,9 @@ int Serving::submit(const dfamin_dfa& dfa, const dfamin_opts& opts, uint64_t* ti
   r->k = dfa.k;
   r->q0 = dfa.q0;
   r->opts = opts;
-  try {
-    r->delta.assign(dfa.delta, dfa.delta + (size_t)dfa.n * dfa.k);
-    r->accept.assign(dfa.accept, dfa.accept + ((size_t)dfa.n + 7) / 8);
-  } catch (...) {
-    return DFAMIN_E_NOMEM;
-  }
+  if (!r->in.make(impl_->pinned, r->delta_bytes() + r->accept_bytes())) return DFAMIN_E_NOMEM;
+  std::memcpy(r->in.data(), dfa.delta, r->delta_bytes());
+  std::memcpy(static_cast<char*>(r->in.data()) + r->delta_bytes(), dfa.accept, r->accept_bytes());
   {
     std::lock_guard<std::mutex> g(impl_->mu);
     if (impl_->stop) return DFAMIN_E_CANCELLED;
@@ -914,6 +995,8 @@ int Serving::wait(uint64_t ticket, int64_t timeout_us, uint32_t* out, dfamin_res
     return DFAMIN_E_TIMEOUT;
   }
   const int st = r->status;
+  impl_->tickets.erase(it);
+  lk.unlock();  // the request is ours now: copy out without holding the lock
   if (st == DFAMIN_OK) {
     std::memcpy(out, r->out.data(), 4ull * r->n);
     if (result) *result = r->result;
@@ -921,7 +1004,7 @@ int Serving::wait(uint64_t ticket, int64_t timeout_us, uint32_t* out, dfamin_res
     std::memset(result, 0, sizeof(*result));
     result->status = st;
   }
-  impl_->tickets.erase(it);
+  r->out.release();
   return st;
 }
 
