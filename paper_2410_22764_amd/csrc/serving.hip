@@ -280,7 +280,16 @@ struct Serving::Impl {
   Context* ctx;
   // declared before the queue and the tickets: requests give their host
   // buffers back to it, so it must outlive them (they also hold a reference)
-  std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>(kPinnedCap);
+  std::shared_ptr<PinnedPool> pinned = std::make_shared<PinnedPool>(pinned_cap());
+  static uint64_t pinned_cap() {
+    // DFAMIN_SERVING_PINNED_BYTES overrides the cap (0: ordinary memory only)
+    if (const char* e = std::getenv("DFAMIN_SERVING_PINNED_BYTES")) {
+      char* end = nullptr;
+      const unsigned long long v = std::strtoull(e, &end, 10);
+      if (end != e) return v;
+    }
+    return kPinnedCap;
+  }
   // worker-side totals (printed at shutdown with DFAMIN_TRACE)
   double t_join = 0, t_round = 0;
   uint64_t iters = 0, joined = 0;

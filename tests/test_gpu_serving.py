@@ -120,3 +120,22 @@ def test_cancel_and_errors(ctx):
     rc, out, _ = dfamin.dfamin_wait(ctx, t, d.n)
     want, _ = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
     assert rc == dfamin.DFAMIN_OK and np.array_equal(out, want)
+
+
+def test_pageable_staging_when_pinned_cap_is_zero(monkeypatch):
+    """With the page-locked staging pool capped at 0 bytes every request is
+    staged in ordinary host memory; results are unchanged."""
+    from paper_2410_22764_amd import dfamin
+    monkeypatch.setenv("DFAMIN_SERVING_PINNED_BYTES", "0")
+    c = dfamin.dfamin_create(0)
+    try:
+        reqs = _mix(7, 12)
+        print("[case] serving mix of 12, pageable staging", flush=True)
+        tickets = [dfamin.dfamin_submit(c, d, {"closure": cl}) for d, cl in reqs]
+        for (d, cl), t in zip(reqs, tickets):
+            rc, out, res = dfamin.dfamin_wait(c, t, d.n, timeout_us=20_000_000)
+            assert rc == dfamin.DFAMIN_OK, (d.name, rc)
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert res["num_blocks"] == nb and np.array_equal(out, want), d.name
+    finally:
+        c.close()
