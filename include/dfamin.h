@@ -64,7 +64,8 @@ typedef struct dfamin_ctx dfamin_ctx;  /* opaque */
  * pointers are host pointers; for the *_device calls they are device
  * pointers (HIP device memory of the context's device). */
 typedef struct {
-  uint32_t n;             /* number of states, >= 1 */
+  uint32_t n;             /* number of states, 1 <= n < 2^31 - 256 (state ids are 31-bit; the
+                             states of one batched call also sum below that) */
   uint32_t k;             /* number of letters, >= 1 */
   const uint32_t *delta;  /* k*n entries, letter-major, each < n */
   const uint8_t *accept;  /* ceil(n/8) bytes, LSB first */

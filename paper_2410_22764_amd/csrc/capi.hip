@@ -24,7 +24,7 @@ using dfamin::InstOutcome;
 
 int check_dfa_shape(const dfamin_dfa* d) {
   if (!d || !d->delta || !d->accept) return DFAMIN_E_INVAL;
-  if (d->n == 0 || d->k == 0 || d->q0 >= d->n) return DFAMIN_E_INVAL;
+  if (d->n == 0 || d->k == 0 || d->q0 >= d->n || d->n >= dfamin::kMaxStates) return DFAMIN_E_INVAL;
   if ((uint64_t)d->n * d->k > (1ull << 40)) return DFAMIN_E_INVAL;
   return DFAMIN_OK;
 }

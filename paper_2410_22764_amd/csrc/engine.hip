@@ -946,7 +946,7 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   uint64_t N = 0;
   uint32_t nmax = 0;
   for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
-  if (N >= 0x7FFFFF00ull) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
+  if (N >= kMaxStates) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
   N_ = N;
   closure_cursor_ = 0;
   Profiler& prof = ctx_->prof;

@@ -41,6 +41,7 @@ constexpr int kSigDefaultVariant = 1;
 constexpr uint64_t kTuneMinStates = 1ull << 18;  // smaller rounds use the default
 constexpr uint32_t kGraphRounds = 16;  // leader-election rounds per captured graph
 constexpr uint32_t kBfsLevelsBeforeClosure = 64;  // BFS levels before closure rows join
+constexpr uint64_t kMaxStates = 0x7FFFFF00ull;  // states per call: ids are 31-bit in hash slots
 constexpr int kRowTile = kBlock * 4;  // row elements per workgroup in row jobs
 constexpr int kLongTile = kBlock * 16;  // row elements per workgroup of validation
 

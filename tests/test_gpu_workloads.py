@@ -99,3 +99,49 @@ def test_table2_fib30(ctx):
     out, res = dfamin.dfamin_minimize(ctx, d, "auto")
     assert res["num_blocks"] == d.n
     assert np.array_equal(out, np.arange(d.n, dtype=np.uint32))
+
+
+def test_state_limit_rejected_before_staging(ctx):
+    """n at the 31-bit state-id limit is refused up front: the host-input
+    entry point returns E_INVAL without reading the (here tiny) buffers."""
+    from paper_2410_22764_amd import dfamin
+    print("[case] n = 2^31 - 256 rejected", flush=True)
+    d = W.DFA(n=(1 << 31) - 256, k=1, delta=np.zeros(4, np.uint32), accept=np.zeros(4, np.uint8), q0=0,
+              name="over the limit")
+    s, keep = dfamin._host_dfa(d)
+    out = np.empty(4, np.uint32)
+    res = dfamin.Result()
+    rc = dfamin.load().dfamin_minimize(ctx.handle, dfamin.ctypes.byref(s), dfamin._opts(None),
+                                       out.ctypes.data, dfamin.ctypes.byref(res))
+    assert rc == dfamin.DFAMIN_E_INVAL
+
+
+def test_huge_chain_64bit_offsets(ctx):
+    """A chain of n = 2^27 states over 40 letters, built on the device: the
+    last letter is the chain (i -> i+1, n-1 -> n-1), the 39 others are the
+    identity, only state n-1 accepts.  delta has 40 * 2^27 = 5.4e9 entries,
+    so every row offset past letter 31 needs more than 32 bits.  Closed forms:
+    every state is its own class, and AUTO takes 5 + ceil(log2(n - 2)) = 32
+    refining rounds (8 plain rounds, then doubling)."""
+    import torch
+    from paper_2410_22764_amd import dfamin
+    n, k = 1 << 27, 40
+    print(f"[case] chain n=2^27 k={k} on the device", flush=True)
+    dev = torch.device("cuda:0")
+    ar = torch.arange(n, dtype=torch.int32, device=dev)
+    delta = torch.empty((k, n), dtype=torch.int32, device=dev)
+    delta[:] = ar
+    delta[k - 1, :-1] = ar[1:]
+    delta[k - 1, -1] = n - 1
+    acc = torch.zeros((n + 7) // 8, dtype=torch.uint8, device=dev)
+    acc[(n - 1) >> 3] = 1 << ((n - 1) & 7)
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+    res = dfamin.dfamin_minimize_device(ctx, n, k, delta.data_ptr(), acc.data_ptr(), 0, out.data_ptr(),
+                                        {"closure": "auto"}, stream=torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert res["num_blocks"] == n and res["initial_block"] == 0
+    assert res["refine_rounds"] == 32 and res["rounds_executed"] == 33
+    assert bool(torch.equal(out, ar))
+    del delta, acc, out, ar
+    torch.cuda.empty_cache()
