@@ -312,8 +312,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; the multi-GPU sharding design "
-                                   "is documented but not implemented", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU only; sharding across GPUs is "
+                                   "described in the design notes but not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
