@@ -478,11 +478,26 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   auto tp0 = now();
   while (m > 0) {
     tp0 = now();
+    if (any_auto && rounds == 0) {
+      // Unary instances refine by doubling from the first round: a doubling
+      // round costs what a plain one does (one gathered letter) plus one
+      // level pass, and after r rounds it holds P_(2^r - 1) instead of P_r.
+      // Those whose level storage does not fit stay plain for now.
+      std::vector<uint32_t> uni, rest;
+      for (uint32_t i : alist)
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && nonid_[i].size() == 1) uni.push_back(i);
+      if (!uni.empty()) {
+        TRY(lazy_levels(uni, opts, rest, lazy));
+        for (uint32_t i : uni) dbl[i] = lazy[i];
+        TRY(upload_layout(s));
+      }
+      if (trace) t_closure += us(tp0, now());
+    }
     if (any_auto && rounds == auto_rounds) {
-      // instances still refining after auto_rounds rounds get the closure
+      // other instances still refining after auto_rounds rounds get the closure
       std::vector<uint32_t> which;
       for (uint32_t i : alist)
-        if (in_[i].closure == DFAMIN_CLOSURE_AUTO) which.push_back(i);
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && !has_closure_[i]) which.push_back(i);
       if (!which.empty()) {
         std::vector<uint32_t> rest;
         TRY(lazy_levels(which, opts, rest, lazy));

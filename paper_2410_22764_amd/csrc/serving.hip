@@ -269,6 +269,10 @@ struct Resident {
   // round); mj: the current partition is Moore's P_mj; step: this round's t
   bool dbl = false;
   uint64_t mj = 0, step = 1;
+  // doubling levels computed in the round that first reads them (rows hold
+  // pointers to all L level buffers; `built` of them are filled)
+  bool lazy = false;
+  uint32_t built = 0;
 };
 
 }  // namespace
@@ -474,6 +478,79 @@ struct Serving::Impl {
   }
 
   // (re)upload descriptors and row pointers of every resident request
+  // Level passes of the coming round (step 0: each resident's first missing
+  // level, step 1 the next, ...), one launch per step, queued before it.
+  struct LevelTodo {
+    Resident* r;
+    uint32_t level, step;
+  };
+  std::vector<LevelTodo> todo;
+  int queue_levels() {
+    uint32_t S = 0;
+    for (const LevelTodo& t : todo) S = std::max(S, t.step + 1);
+    std::vector<RowJob> jobs;
+    std::vector<uint32_t> joboff, begin(S + 1, 0), wgs(S, 0);
+    uint32_t maxw = 0;
+    for (uint32_t st = 0; st < S; ++st) {
+      begin[st] = (uint32_t)jobs.size();
+      uint32_t w = 0;
+      for (const LevelTodo& t : todo) {
+        if (t.step != st) continue;
+        RowJob J;
+        J.src = t.r->rows[t.level - 1];
+        J.dst = t.r->rows[t.level];
+        J.n = t.r->req->n;
+        J.flag_idx = (uint32_t)jobs.size();
+        joboff.push_back(w);
+        w += (J.n + kRowTile - 1) / kRowTile;
+        jobs.push_back(J);
+      }
+      wgs[st] = w;
+      maxw = std::max(maxw, w);
+    }
+    begin[S] = (uint32_t)jobs.size();
+    todo.clear();
+    if (!grow(s_jobs, jobs.size() * sizeof(RowJob)) || !grow(s_off, joboff.size() * 4) ||
+        !grow(s_flags, jobs.size() * 4) || !grow(s_wg, (size_t)maxw * 4))
+      return DFAMIN_E_NOMEM;
+    if (hipMemcpyAsync(s_jobs.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(s_off.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    for (uint32_t st = 0; st < S; ++st)
+      if (begin[st + 1] > begin[st])
+        launch_closure_level(s_jobs.as<RowJob>() + begin[st], s_off.as<uint32_t>() + begin[st],
+                             begin[st + 1] - begin[st], wgs[st], s_wg.as<uint32_t>(),
+                             s_flags.as<uint32_t>() + begin[st], stream);
+    return hipGetLastError() == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
+  }
+
+  // Level storage for a unary AUTO resident, which then refines by doubling
+  // from its first round (the same schedule as the batch path).  Returns
+  // false, leaving the resident plain, when the pool has no room.
+  bool plan_lazy_levels(Resident* r) {
+    uint32_t L = floor_log2_u32(r->req->n);
+    if (r->req->opts.max_levels && r->req->opts.max_levels < L) L = r->req->opts.max_levels;
+    const size_t bytes = 4ull * L * r->req->n;
+    char* base = nullptr;
+    if (bytes) {
+      if (pool.live() + bytes > pool.budget()) return false;
+      base = static_cast<char*>(pool.alloc(bytes));
+      if (!base) return false;
+      r->closure_bufs.emplace_back(base, bytes);
+    }
+    std::vector<uint64_t> rows(1 + (size_t)L);
+    rows[0] = reinterpret_cast<uint64_t>(r->d_delta) + 4ull * r->nonid[0] * r->req->n;
+    for (uint32_t l = 1; l <= L; ++l) rows[l] = reinterpret_cast<uint64_t>(base + 4ull * (l - 1) * r->req->n);
+    r->rows = std::move(rows);
+    r->lazy = true;
+    r->built = 0;
+    r->levels = 0;
+    r->closure = true;
+    r->dbl = true;
+    return true;
+  }
+
   int upload_layout() {
     rows_host.clear();
     for (uint32_t s = 0; s < kSlots; ++s) {
@@ -488,8 +565,16 @@ struct Serving::Impl {
         r->step = 1ull << lvl;
         desc[s].rows_off += lvl;
         desc[s].kp = 1;
+        if (r->lazy && r->built < lvl) {
+          for (uint32_t l = r->built + 1; l <= lvl; ++l) todo.push_back({r, l, l - r->built - 1});
+          r->built = lvl;
+        }
       }
       rows_host.insert(rows_host.end(), r->rows.begin(), r->rows.end());
+    }
+    if (!todo.empty()) {
+      const int rc = queue_levels();
+      if (rc != DFAMIN_OK) return rc;
     }
     if (rows_host.size() * 8 > rows_cap) {
       if (d_rows) (void)hipFree(d_rows);
@@ -623,6 +708,7 @@ struct Serving::Impl {
       D.sig = reinterpret_cast<uint64_t>(r->d_sig);
       ok.push_back(r);
       if (r->req->opts.closure == DFAMIN_CLOSURE_ON) need_closure.push_back(r);
+      if (r->req->opts.closure == DFAMIN_CLOSURE_AUTO && r->nonid.size() == 1) (void)plan_lazy_levels(r);
     }
     js = ok;
     if (js.empty()) return DFAMIN_OK;
@@ -728,8 +814,8 @@ struct Serving::Impl {
         o.initial_block = res[w].initial_block;
         o.refine_rounds = res[w].refine_rounds;
         o.rounds_executed = res[w].refine_rounds + 1;
-        o.closure_levels = r->closure ? r->levels : 0;
-        o.closure_letters = r->closure ? (uint32_t)r->rows.size() : 0;
+        o.closure_levels = !r->closure ? 0 : (r->lazy ? r->built : r->levels);
+        o.closure_letters = !r->closure ? 0 : (r->lazy ? r->built + 1 : (uint32_t)r->rows.size());
         o.status = DFAMIN_OK;
       }
     }

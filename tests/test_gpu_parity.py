@@ -105,17 +105,18 @@ def test_deep_chain_workload_closed_form(ctx):
 
 
 def test_deep_chain_auto(ctx):
-    """AUTO on the 2^20 chain: 8 plain rounds reach P_8, then doubling rounds
-    with t = 8, 16, ..., 2^19 reach P_(2^20), the first partition with every
-    state alone: 8 + 17 = 25 refining rounds (5 + ceil(log2(n - 2))).  The
-    doubling rounds read levels 3..19 and each level is computed in the round
-    that first reads it, so 19 levels are built (no state is left to refine
-    after the last split)."""
+    """AUTO on the 2^20 chain (one non-identity letter): doubling from the
+    first round, t = 1, 2, 4, ..., 2^19, holds P_(2^r - 1) after r rounds and
+    reaches P_(2^20 - 1), the first partition with every state alone (it
+    needs j >= n - 2), after ceil(log2(n - 1)) = 20 refining rounds.  The
+    rounds read levels 0..19, each computed in the round that first reads
+    it, so 19 levels are built (no state is left to refine after the last
+    split)."""
     d = W.deep_chain()
     out, res = _run(ctx, d, "auto")
     assert res["num_blocks"] == d.n and np.array_equal(out, np.arange(d.n))
     assert res["closure_levels"] == 19 and res["closure_letters"] == 20
-    assert res["refine_rounds"] == 25 and res["rounds_executed"] == 26
+    assert res["refine_rounds"] == 20 and res["rounds_executed"] == 21
 
 
 def _kept_levels(d, a):
@@ -134,11 +135,12 @@ def _kept_levels(d, a):
     return kept
 
 
-def _auto_unary_rounds(d, auto_rounds=8):
+def _auto_unary_rounds(d, auto_rounds=0):
     """Refining rounds of AUTO on a unary instance, from Moore's partitions
-    P_j alone: plain rounds (j -> j + 1) until auto_rounds, then j -> j + t
-    with t the largest kept level 2^l <= j + 1; stop at the first step that
-    leaves the block count unchanged."""
+    P_j alone: plain rounds (j -> j + 1) until auto_rounds (none: a unary
+    instance doubles from its first round), then j -> j + t with t the
+    largest kept level 2^l <= j + 1; stop at the first step that leaves the
+    block count unchanged."""
     rows = d.rows()
     letters = [a for a in range(d.k) if not np.array_equal(rows[a], np.arange(d.n))]
     assert len(letters) == 1

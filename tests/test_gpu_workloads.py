@@ -121,8 +121,8 @@ def test_huge_chain_64bit_offsets(ctx):
     last letter is the chain (i -> i+1, n-1 -> n-1), the 39 others are the
     identity, only state n-1 accepts.  delta has 40 * 2^27 = 5.4e9 entries,
     so every row offset past letter 31 needs more than 32 bits.  Closed forms:
-    every state is its own class, and AUTO takes 5 + ceil(log2(n - 2)) = 32
-    refining rounds (8 plain rounds, then doubling)."""
+    every state is its own class, and AUTO (doubling from the first round)
+    takes ceil(log2(n - 1)) = 27 refining rounds."""
     import torch
     from paper_2410_22764_amd import dfamin
     n, k = 1 << 27, 40
@@ -141,7 +141,7 @@ def test_huge_chain_64bit_offsets(ctx):
                                         {"closure": "auto"}, stream=torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     assert res["num_blocks"] == n and res["initial_block"] == 0
-    assert res["refine_rounds"] == 32 and res["rounds_executed"] == 33
+    assert res["refine_rounds"] == 27 and res["rounds_executed"] == 28
     assert bool(torch.equal(out, ar))
     del delta, acc, out, ar
     torch.cuda.empty_cache()
