@@ -147,6 +147,7 @@ class Engine {
   };
   GraphKey graph_key_{};
   hipGraphExec_t graph_exec_ = nullptr;
+  hipEvent_t ev_rb_ = nullptr;  // a signature round's readback, waited for by itself
 };
 
 // Signature-tile autotuner state of a context: a forced variant, or the

@@ -43,6 +43,7 @@ inline uint64_t mix64(uint64_t z) {
 }
 
 constexpr uint32_t kDefaultAutoRounds = 8;
+constexpr uint64_t kClearAheadSlots = 1ull << 22;  // 32 MiB: a few microseconds to clear
 constexpr int kMaxSaltRetries = 8;
 
 }  // namespace
@@ -119,6 +120,7 @@ int Profiler::copy_stats(dfamin_kernel_stat* out, int cap) const {
 // ------------------------------------------------------------------ Engine
 Engine::~Engine() {
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+  if (ev_rb_) (void)hipEventDestroy(ev_rb_);
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
@@ -432,24 +434,27 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   // per level.
   std::vector<uint8_t> active(I, 1), dbl(I, 0);
   std::vector<uint64_t> mj(I, 0), step(I, 1);
-  // Doubling instances with lazily built levels: levels computed so far.
-  // On every way out the rows are cut to the built levels, which is what
-  // later readers of the closure rows (the reachability search) may follow.
+  // Doubling instances with lazily built levels: levels computed so far
+  // (possibly one ahead of the rounds) and the highest level a round read.
+  // On every way out the rows are cut to the levels read, all of them built,
+  // which is what later readers of the closure rows (the reachability
+  // search) may follow and what the results report.
   std::vector<uint8_t> lazy(I, 0);
-  std::vector<uint32_t> built(I, 0);
+  std::vector<uint32_t> built(I, 0), used(I, 0);
   std::vector<LevelTodo> todo;
+  uint64_t spec_clear = 0;  // table slots cleared ahead for the coming round
   struct TrimLazy {
     Engine* e;
     const std::vector<uint8_t>& lazy;
-    const std::vector<uint32_t>& built;
+    const std::vector<uint32_t>& used;
     ~TrimLazy() {
       for (size_t i = 0; i < lazy.size(); ++i)
         if (lazy[i]) {
-          e->inst_rows_[i].resize((size_t)built[i] + 1);
-          e->levels_[i] = built[i];
+          e->inst_rows_[i].resize((size_t)used[i] + 1);
+          e->levels_[i] = used[i];
         }
     }
-  } trim_lazy{this, lazy, built};
+  } trim_lazy{this, lazy, used};
   // Exact block counts (and instance-relative ranks in d_rank_) of the
   // instances scanned at the end of the previous round; cnt_ok marks them.
   std::vector<uint64_t> cnt(I, 0);
@@ -523,6 +528,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         for (uint32_t l = built[i] + 1; l <= lvl; ++l) todo.push_back({i, l, l - built[i] - 1});
         built[i] = lvl;
       }
+      used[i] = std::max(used[i], lvl);
       if (desc_[i].rows_off != row_base_[i] + lvl || desc_[i].kp != 1) {
         desc_[i].rows_off = row_base_[i] + lvl;
         desc_[i].kp = 1;
@@ -650,10 +656,14 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
                        (unsigned long long)m, variant, best_ms);
       }
     }
+    const bool cleared = spec_clear >= tsize;  // by the previous round's tail
+    spec_clear = 0;
     if (!tuned_now) {
-      prof.begin(s, "clear_table", 8.0 * (double)tsize);
-      launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
-      prof.end(s);
+      if (!cleared) {
+        prof.begin(s, "clear_table", 8.0 * (double)tsize);
+        launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+        prof.end(s);
+      }
       prof.begin(s, "signature", md * sig_bytes());
       launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                        d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
@@ -714,9 +724,41 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     HIP(hipGetLastError());
     // one copy: control block, refine counters, and the counts just scanned
     HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl) + 4 * I + 4 * (size_t)ns, hipMemcpyDeviceToHost, s));
+    // Work of the next round that needs none of this round's results is
+    // queued behind the copy and runs while the host waits and plans: the
+    // next level of each doubling instance (j grows by this round's step; if
+    // the round is redone, the level is just ready early) and a cleared table
+    // of this round's size, which the next round uses when its own table is
+    // no larger (table sizes mostly shrink with m).  Only small tables are
+    // cleared ahead: after the last round the clear is wasted, and a large
+    // one would then delay the final numbering.  The host waits for the copy
+    // alone; with profiling on it waits for everything, so that every timed
+    // launch has finished when the times are collected.
+    const bool overlap = !prof.enabled();
+    if (overlap) {
+      if (!ev_rb_) HIP(hipEventCreateWithFlags(&ev_rb_, hipEventDisableTiming));
+      HIP(hipEventRecord(ev_rb_, s));
+      for (uint32_t i : alist) {
+        if (!dbl[i] || !lazy[i]) continue;
+        const uint32_t nrows = (uint32_t)inst_rows_[i].size();
+        uint32_t lvl = (uint32_t)floor_log2_u64(mj[i] + step[i] + 1);
+        if (lvl > nrows - 1) lvl = nrows - 1;
+        for (uint32_t l = built[i] + 1; l <= lvl; ++l) todo.push_back({i, l, l - built[i] - 1});
+        if (built[i] < lvl) built[i] = lvl;
+      }
+      if (!todo.empty()) {
+        TRY(queue_levels(todo, s));
+        todo.clear();
+      }
+      if (tsize <= kClearAheadSlots) {
+        launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+        HIP(hipGetLastError());
+        spec_clear = tsize;
+      }
+    }
     const auto tp2 = now();
     t_issue += us(tp1, tp2);
-    HIP(stream_wait(s));
+    HIP(overlap ? event_wait(ev_rb_) : stream_wait(s));
     const auto tp3 = now();
     t_wait += us(tp2, tp3);
     prof.collect();

@@ -115,6 +115,17 @@ inline hipError_t stream_wait(hipStream_t s) {
   }
 }
 
+// The same wait for one event (work queued behind it keeps running).
+inline hipError_t event_wait(hipEvent_t ev) {
+  const auto t0 = std::chrono::steady_clock::now();
+  while (true) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(2000))
+      return hipEventSynchronize(ev);
+  }
+}
+
 // One row of n entries handled by a row job (validation, closure level).
 struct RowJob {
   uint64_t src;        // device address of a uint32[n] row
