@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <array>
 #include <map>
 #include <vector>
 
@@ -148,6 +149,13 @@ class Engine {
   GraphKey graph_key_{};
   hipGraphExec_t graph_exec_ = nullptr;
   hipEvent_t ev_rb_ = nullptr;  // a signature round's readback, waited for by itself
+  // captured queued signature rounds, reused while every pointer and size in
+  // the key matches
+  static constexpr int kQueueKeyWords = 24;
+  std::array<uint64_t, kQueueKeyWords> queue_key_{};
+  hipGraphExec_t queue_exec_ = nullptr;
+  int queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, uint64_t salt, uint32_t* cur,
+                    uint32_t* nxt, uint64_t max_left, bool use_graph, hipStream_t s, uint64_t& executed);
 };
 
 // Signature-tile autotuner state of a context: a forced variant, or the

@@ -44,7 +44,7 @@ inline uint64_t mix64(uint64_t z) {
 
 constexpr uint32_t kDefaultAutoRounds = 8;
 constexpr uint64_t kClearAheadSlots = 1ull << 22;  // 32 MiB: a few microseconds to clear
-constexpr int kMaxSaltRetries = 8;
+constexpr uint32_t kQueueRounds = 8;               // queued signature rounds per graph (even)
 
 }  // namespace
 
@@ -120,6 +120,7 @@ int Profiler::copy_stats(dfamin_kernel_stat* out, int cap) const {
 // ------------------------------------------------------------------ Engine
 Engine::~Engine() {
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
+  if (queue_exec_) (void)hipGraphExecDestroy(queue_exec_);
   if (ev_rb_) (void)hipEventDestroy(ev_rb_);
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
@@ -390,6 +391,92 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   return DFAMIN_OK;
 }
 
+// Queued signature rounds.  Once every instance still refining groups by
+// hash (which lasts: block counts only grow) and needs no closure change and
+// no count scan, a round needs no decision of the host.  The kernels then
+// take the live active count and the salt from the control block, the grids
+// and the table are sized for the current m (which never grows), a one-thread
+// step ends each round (a new salt after a hash collision, else the next
+// count, and stop once nothing split), and every kernel of a later round
+// returns at once after stop.  Rounds go to the stream in captured graphs of
+// kQueueRounds (or directly), and the host reads the control block after 1,
+// 2, 4 ... of them.  `executed`: the refining rounds run (the one that found
+// nothing to split included).
+int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, uint64_t salt, uint32_t* cur,
+                          uint32_t* nxt, uint64_t max_left, bool use_graph, hipStream_t s,
+                          uint64_t& executed) {
+  const size_t I = in_.size();
+  const bool batch = I > 1;
+  const uint64_t tsize = 1ull << tbits;
+  const uint32_t ntiles = scan_tiles(m, items);
+  launch_queue_start(d_ctrl_.as<Ctrl>(), (uint32_t)m, salt, s);
+  HIP(hipGetLastError());
+  auto queue = [&](uint32_t* a, uint32_t* b) {
+    launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 1);
+    launch_signature(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                     d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, 4, d_table_.as<Slot>(), tbits,
+                     d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(), variant, s, 1);
+    launch_resolve(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                   d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(), d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(),
+                   d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                   d_status_.as<unsigned long long>(), ntiles, s, 1);
+    launch_compact(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
+                   d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(), b,
+                   d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), items, s, 1);
+    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
+                     d_ctrl_.as<Ctrl>(), s, nullptr, 0, 1);
+    launch_round_step(d_ctrl_.as<Ctrl>(), s);
+  };
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    const std::array<uint64_t, kQueueKeyWords> key{
+        m, tbits, (uint64_t)variant, (uint64_t)items, I,
+        reinterpret_cast<uint64_t>(cur), reinterpret_cast<uint64_t>(nxt), reinterpret_cast<uint64_t>(d_inst_of_.p),
+        reinterpret_cast<uint64_t>(d_desc_.p), reinterpret_cast<uint64_t>(d_rows_.p),
+        reinterpret_cast<uint64_t>(d_block_.p), reinterpret_cast<uint64_t>(d_table_.p),
+        reinterpret_cast<uint64_t>(d_slot_of_.p), reinterpret_cast<uint64_t>(d_nb_.p),
+        reinterpret_cast<uint64_t>(d_keep_.p), reinterpret_cast<uint64_t>(d_changed_.p),
+        reinterpret_cast<uint64_t>(d_refine_.p), reinterpret_cast<uint64_t>(d_ctrl_.p),
+        reinterpret_cast<uint64_t>(d_status_.p), reinterpret_cast<uint64_t>(d_dense_.p),
+        reinterpret_cast<uint64_t>(s), 1, 0, 0};
+    if (queue_exec_ && queue_key_ == key) {
+      exec = queue_exec_;
+    } else {
+      if (queue_exec_) (void)hipGraphExecDestroy(queue_exec_);
+      queue_exec_ = nullptr;
+      hipGraph_t g = nullptr;
+      HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      for (uint32_t r = 0; r < kQueueRounds; ++r) queue(r & 1 ? nxt : cur, r & 1 ? cur : nxt);
+      const hipError_t ce = hipStreamEndCapture(s, &g);
+      if (ce != hipSuccess || !g) return check_hip(ce != hipSuccess ? ce : hipErrorUnknown);
+      const hipError_t ie = hipGraphInstantiate(&queue_exec_, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      HIP(ie);
+      queue_key_ = key;
+      exec = queue_exec_;
+    }
+  }
+  uint32_t per_check = 1;
+  while (true) {
+    for (uint32_t b = 0; b < per_check; ++b) {
+      if (exec) {
+        HIP(hipGraphLaunch(exec, s));
+      } else {
+        for (uint32_t r = 0; r < kQueueRounds; ++r) queue(r & 1 ? nxt : cur, r & 1 ? cur : nxt);
+      }
+    }
+    HIP(hipGetLastError());
+    HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    HIP(stream_wait(s));
+    const Ctrl c = *h_rb_.as<Ctrl>();
+    if (c.fault) return DFAMIN_E_INTERNAL;
+    executed = c.iterations;
+    if (c.stop) return DFAMIN_OK;
+    if (executed > max_left) return DFAMIN_E_INTERNAL;
+    per_check = std::min<uint32_t>(per_check * 2, 8);
+  }
+}
+
 // Signature rounds (Algorithm 4, Section 3.3) over the active states until no
 // instance splits a block.
 int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s) {
@@ -443,6 +530,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   std::vector<uint32_t> built(I, 0), used(I, 0);
   std::vector<LevelTodo> todo;
   uint64_t spec_clear = 0;  // table slots cleared ahead for the coming round
+  bool prev_all_hash = false;  // the last round grouped every instance by hash
   struct TrimLazy {
     Engine* e;
     const std::vector<uint8_t>& lazy;
@@ -459,6 +547,15 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   // instances scanned at the end of the previous round; cnt_ok marks them.
   std::vector<uint64_t> cnt(I, 0);
   std::vector<uint8_t> cnt_ok(I, 0);
+  // an instance whose next signature could fit 31 bits is counted exactly
+  // at the end of a round (B <= min(n, B^(kp+1)) after it)
+  auto would_scan = [&](uint32_t i) {
+    const uint64_t B = cnt_ok[i] ? std::max<uint64_t>(cnt[i], 1) : ub[i];
+    const uint64_t kp1 = desc_[i].kp + 1ull;
+    const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
+    const uint64_t nb = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
+    return kp1 * std::max<uint32_t>(1, ceil_log2_u64(nb)) <= 31;
+  };
   std::vector<uint32_t> exact, scan;
   std::vector<uint32_t> alist(I);  // instances still refining, in order
   for (size_t i = 0; i < I; ++i) alist[i] = (uint32_t)i;
@@ -621,10 +718,35 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
                           (ceil_log2_u64(m) << 8);
     int variant = kSigDefaultVariant;
     bool tuned_now = false;
+    const auto tuned = tu.best.find(tkey);
+    // Queued rounds (queued_rounds): every instance still refining grouped by
+    // hash in this round and the last, none refines by doubling or still
+    // waits for its AUTO closure, and none needs a count scan.
+    const bool all_hash = rounds > 0 && exact.empty();
+    bool queue_ok = all_hash && prev_all_hash && !prof.enabled();
+    for (uint32_t i : alist) {
+      if (!queue_ok) break;
+      if (dbl[i] || would_scan(i) ||
+          (in_[i].closure == DFAMIN_CLOSURE_AUTO && !has_closure_[i] && rounds < auto_rounds))
+        queue_ok = false;
+    }
+    prev_all_hash = all_hash;
+    if (queue_ok) {
+      if (tu.forced >= 0) variant = tu.forced;
+      else if (tuned != tu.best.end()) variant = tuned->second;
+      const bool use_graph = !(opts.flags & DFAMIN_FLAG_NO_GRAPH) && s != nullptr;
+      uint64_t executed = 0;
+      TRY(queued_rounds(m, tbits, variant, citems, salt, cur, nxt, max_rounds - rounds, use_graph, s, executed));
+      rounds += executed;
+      if (rounds > max_rounds) return DFAMIN_E_INTERNAL;
+      if (trace) std::fprintf(stderr, "[dfamin] %llu queued rounds from m=%llu\n", (unsigned long long)executed,
+                              (unsigned long long)m);
+      break;
+    }
     if (tu.forced >= 0) {
       variant = tu.forced;
     } else if (m >= kTuneMinStates) {
-      auto it = tu.best.find(tkey);
+      auto it = tuned;
       if (it != tu.best.end()) {
         variant = it->second;
       } else {
@@ -687,13 +809,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     // the round: instances that were refining before this round and whose
     // next signature could fit 31 bits, B <= min(n, B^(kp+1)) after it.
     scan.clear();
-    for (uint32_t i : alist) {
-      const uint64_t B = cnt_ok[i] ? std::max<uint64_t>(cnt[i], 1) : ub[i];
-      const uint64_t kp1 = desc_[i].kp + 1ull;
-      const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(B));
-      const uint64_t nb = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
-      if (kp1 * std::max<uint32_t>(1, ceil_log2_u64(nb)) <= 31) scan.push_back((uint32_t)i);
-    }
+    for (uint32_t i : alist)
+      if (would_scan(i)) scan.push_back((uint32_t)i);
     const uint32_t ns = (uint32_t)scan.size();
     uint32_t* hs = hj + 2 * I;
     uint32_t* ds = dj + 2 * I;
@@ -777,11 +894,12 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
                    c.collision, exact.size());
     if (c.collision) {
       // the partition is unchanged, so the counts just taken still hold
-      if (++retries > kMaxSaltRetries) return DFAMIN_E_INTERNAL;
+      if (++retries > (int)kMaxSaltRetries) return DFAMIN_E_INTERNAL;
       salt = mix64(salt + 0x9E3779B97F4A7C15ull);
       continue;
     }
     ++rounds;
+    retries = 0;  // the bound is on redoing one round
     const uint32_t* rc = h_refine;
     for (uint32_t i : alist) {
       // a round maps each block to at most B^(kp+1) signatures
@@ -1130,6 +1248,14 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
+  if (const char* e = std::getenv("DFAMIN_HASH_BITS")) {
+    // testing: weak signature hashes (see Ctrl::hash_mask)
+    const int bits = std::atoi(e);
+    if (bits >= 1 && bits < 64) {
+      const uint64_t mask = (1ull << bits) - 1ull;
+      launch_store_u64(&d_ctrl_.as<Ctrl>()->hash_mask, mask, s);
+    }
+  }
 
   // ---- 4. initial partition {F, Q\F}
   prof.begin(s, "init_minmax", (double)N / 8.0);

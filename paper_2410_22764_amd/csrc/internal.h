@@ -89,9 +89,13 @@ struct Ctrl {
   uint32_t collision;     // two different signatures shared a hash this round
   uint32_t m_next;        // active states for the next round
   uint32_t fault;         // a bounded device wait or probe ran out (never expected)
-  uint32_t stop;          // leader-election rounds: no block split, later rounds do nothing
-  uint32_t iterations;    // leader-election rounds run (the one that found stability included)
-  uint32_t pad0[26];
+  uint32_t stop;          // queued rounds: nothing left to split, later rounds do nothing
+  uint32_t iterations;    // queued rounds run (leader rounds: the one that found stability included)
+  uint32_t m_cur;         // queued signature rounds: active states of the coming round
+  uint32_t retries;       // queued signature rounds: times the coming round was redone (hash collision)
+  uint64_t salt;          // queued signature rounds: hash salt of the coming round
+  uint64_t hash_mask;     // testing: nonzero keeps only these bits of a signature hash
+  uint32_t pad0[20];
   uint32_t tile_counter;  // dynamic tile ids for the look-back scans
   uint32_t pad1[31];
 };
@@ -164,13 +168,18 @@ void launch_init_minmax(const InstDesc* desc, const uint32_t* job_wg_off, uint32
 void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,
                        uint32_t total_wgs, const uint32_t* minF, const uint32_t* minN,
                        uint32_t* inst_of, uint32_t* block, uint32_t* act, hipStream_t s);
-void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s);
+// gmode (clear_table, signature, resolve, compact, round_end): a queued
+// round whose kernels return at once when ctrl->stop is set and otherwise
+// take the active count (m) and the salt from ctrl->m_cur and ctrl->salt; m
+// is then an upper bound that only sizes the grid.
+void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode = 0);
 // dense / dense_width: dense block numbers (exact-key rounds that read them),
 // stored dense_width (1, 2 or 4) bytes per state.
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
-                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s);
+                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s,
+                      int gmode = 0);
 // dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
 // instance's blocks in order of least member, dense_width bytes wide (every
 // number must fit).
@@ -184,16 +193,26 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
                     const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
-                    uint32_t ntiles, hipStream_t s);
+                    uint32_t ntiles, hipStream_t s, int gmode = 0);
 // dead (nullable): instances whose states leave the active list (cancelled).
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
-                    unsigned long long* scan_status, int items, hipStream_t s);
+                    unsigned long long* scan_status, int items, hipStream_t s, int gmode = 0);
 // last (nullable) receives this round's per-instance changed flags.
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
                       Ctrl* ctrl, hipStream_t s, unsigned long long* clear_status = nullptr,
-                      uint32_t clear_tiles = 0);
+                      uint32_t clear_tiles = 0, int gmode = 0);
+// Queued signature rounds: start (stop, iterations and retries cleared,
+// m_cur and salt set) and the one-thread step that ends each round: after a
+// hash collision a new salt (the round is redone; too many set fault and
+// stop), else iterations + 1, m_cur = m_next, and stop once a round split
+// nothing or left no active state.
+void launch_queue_start(Ctrl* ctrl, uint32_t m, uint64_t salt, hipStream_t s);
+// *p = v, in stream order
+void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s);
+void launch_round_step(Ctrl* ctrl, hipStream_t s);
+constexpr uint32_t kMaxSaltRetries = 8;
 // One round of leader-based refinement (Algorithm 2, Section 3.2) over all
 // N states: elect (states that differ from their leader in a successor
 // block; the least of them becomes new_leader[leader]), move (they join the

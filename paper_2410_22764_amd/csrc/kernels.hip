@@ -386,7 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_init_block(const InstDesc* __restric
 // ---------------------------------------------------------------- round
 // Algorithmic bytes: 8 per slot.
 __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table, uint64_t tsize,
-                                                        Ctrl* __restrict__ ctrl) {
+                                                        Ctrl* __restrict__ ctrl, uint32_t gmode) {
+  if (gmode && ctrl->stop) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->any_changed = 0u;
     ctrl->collision = 0u;
@@ -450,7 +451,12 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
     const uint32_t* __restrict__ block, const void* __restrict__ dense,
     Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
-    Ctrl* __restrict__ ctrl) {
+    Ctrl* __restrict__ ctrl, uint32_t gmode) {
+  if (gmode) {  // a queued round: live count and salt from the control block
+    if (ctrl->stop) return;
+    m = ctrl->m_cur;
+    salt = ctrl->salt;
+  }
   // SI states per thread; an LDS table of twice the tile's states
   constexpr uint32_t kTile = kBlock * SI, kSlots = 2 * kTile;
   __shared__ unsigned long long lkey[kSlots];
@@ -537,6 +543,9 @@ __global__ __launch_bounds__(kBlock) void k_signature(
           }
       }
       hh = hash_final(hh);
+      // testing: a hash with only a few bits of entropy (spread again), so
+      // that different signatures share hashes and the rounds are redone
+      if (const uint64_t hm = ctrl->hash_mask) hh = hash_final(hh & hm);
       h[e] = hh;
       frag[e] = (uint32_t)(hh >> 32) | 1u;
       lk = hh | (1ull << 63);  // hash keys and exact keys (< 2^32) never meet
@@ -576,7 +585,11 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
     const Slot* __restrict__ table, const uint32_t* __restrict__ slot_of,
     const uint32_t* __restrict__ block, uint32_t* __restrict__ nb, uint8_t* __restrict__ keep,
     uint32_t* __restrict__ changed_inst, Ctrl* __restrict__ ctrl,
-    unsigned long long* __restrict__ scan_status, uint32_t ntiles) {
+    unsigned long long* __restrict__ scan_status, uint32_t ntiles, uint32_t gmode) {
+  if (gmode) {
+    if (ctrl->stop) return;
+    m = ctrl->m_cur;
+  }
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (j < ntiles) store_status(&scan_status[j], 0ull);
   if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
@@ -626,10 +639,15 @@ __global__ __launch_bounds__(kBlock) void k_compact(
     const uint32_t* __restrict__ nb, const uint8_t* __restrict__ keep,
     const uint32_t* __restrict__ changed_inst, const uint32_t* __restrict__ dead,
     uint32_t* __restrict__ block, uint32_t* __restrict__ act_next, Ctrl* __restrict__ ctrl,
-    unsigned long long* __restrict__ scan_status) {
+    unsigned long long* __restrict__ scan_status, uint32_t gmode) {
+  if (gmode) {  // every workgroup reads the same flag: all of them leave, or none
+    if (ctrl->stop) return;
+    m = ctrl->m_cur;
+  }
   // On a hash collision the round is redone with another salt: nothing is
-  // written, but every tile still takes part in the look-back so that no
-  // workgroup can wait for one that left early.
+  // written (in a queued round the active list is carried over unchanged),
+  // but every tile still takes part in the look-back so that no workgroup
+  // can wait for one that left early.
   __shared__ uint32_t s_tile, s_prefix, s_coll;
   __shared__ TileScanLds<ITEMS> s_scan;
   if (threadIdx.x == 0) {
@@ -644,6 +662,8 @@ __global__ __launch_bounds__(kBlock) void k_compact(
 #pragma unroll 8
   for (int e = 0; e < ITEMS; ++e) {
     const uint32_t j = base + e * kBlock + threadIdx.x;
+    // a queued round that collided is redone from the next buffer: same list
+    if (gmode && coll && j < m) act_next[j] = act[j];
     if (j < m && !coll) {
       const uint32_t g = act[j];
       block[g] = nb[j];
@@ -674,7 +694,8 @@ __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
                                                       uint32_t* __restrict__ last,
                                                       Ctrl* __restrict__ ctrl,
                                                       unsigned long long* __restrict__ clear_status,
-                                                      uint32_t clear_tiles) {
+                                                      uint32_t clear_tiles, uint32_t gmode) {
+  if (gmode && ctrl->stop) return;
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (clear_status) {
     if (i < clear_tiles) store_status(&clear_status[i], 0ull);
@@ -689,6 +710,36 @@ __global__ __launch_bounds__(kBlock) void k_round_end(uint32_t ninst,
     if (!coll) refine_cnt[i] += 1u;
     changed_inst[i] = 0u;
   }
+}
+
+// Queued signature rounds: see launch_queue_start / launch_round_step.
+__global__ void k_queue_start(Ctrl* __restrict__ ctrl, uint32_t m, uint64_t salt) {
+  if (threadIdx.x != 0) return;
+  ctrl->stop = 0u;
+  ctrl->iterations = 0u;
+  ctrl->retries = 0u;
+  ctrl->m_cur = m;
+  ctrl->salt = salt;
+}
+
+__global__ void k_store_u64(uint64_t* __restrict__ p, uint64_t v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+__global__ void k_round_step(Ctrl* __restrict__ ctrl) {
+  if (threadIdx.x != 0 || ctrl->stop) return;
+  if (ctrl->collision) {  // redo the round with another salt
+    ctrl->salt = hash_final(ctrl->salt + 0x9E3779B97F4A7C15ull);
+    if (++ctrl->retries > kMaxSaltRetries) {
+      ctrl->fault = 1u;
+      ctrl->stop = 1u;
+    }
+    return;
+  }
+  ctrl->iterations += 1u;
+  ctrl->retries = 0u;  // the bound is on redoing one round
+  ctrl->m_cur = ctrl->m_next;
+  if (!ctrl->any_changed || ctrl->m_next == 0u) ctrl->stop = 1u;
 }
 
 // ------------------------------------------------ leader-based refinement
@@ -1204,11 +1255,23 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
                      minN, inst_of, block, act);
 }
 
-void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s) {
+void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode) {
   uint32_t grid = grid_for(tsize, 2 * kBlock);
   if (grid > 65536u) grid = 65536u;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl);
+  hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl, (uint32_t)gmode);
+}
+
+void launch_queue_start(Ctrl* ctrl, uint32_t m, uint64_t salt, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_start, dim3(1), dim3(64), 0, s, ctrl, m, salt);
+}
+
+void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_store_u64, dim3(1), dim3(64), 0, s, p, v);
+}
+
+void launch_round_step(Ctrl* ctrl, hipStream_t s) {
+  hipLaunchKernelGGL(k_round_step, dim3(1), dim3(64), 0, s, ctrl);
 }
 
 namespace {
@@ -1216,33 +1279,33 @@ template <bool BATCH, int SI>
 void launch_signature_si(int dw, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                          const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                          const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
-                         Ctrl* ctrl, hipStream_t s) {
+                         Ctrl* ctrl, hipStream_t s, uint32_t gm) {
   const dim3 grid(grid_for(m, kBlock * SI));
   if (dw == 1)
     hipLaunchKernelGGL((k_signature<BATCH, 1, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm);
   else if (dw == 2)
     hipLaunchKernelGGL((k_signature<BATCH, 2, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm);
   else
     hipLaunchKernelGGL((k_signature<BATCH, 4, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm);
 }
 
 template <bool BATCH>
 void launch_signature_w(int dw, int variant, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                         const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                         const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
-                        Ctrl* ctrl, hipStream_t s) {
+                        Ctrl* ctrl, hipStream_t s, uint32_t gm) {
   if (variant == 0)
     launch_signature_si<BATCH, 1>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s);
+                                  ctrl, s, gm);
   else if (variant == 2)
     launch_signature_si<BATCH, 4>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s);
+                                  ctrl, s, gm);
   else
     launch_signature_si<BATCH, 2>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s);
+                                  ctrl, s, gm);
 }
 
 template <bool BATCH>
@@ -1261,14 +1324,15 @@ void launch_dense_w(int dw, uint32_t N, const uint32_t* inst_of, const InstDesc*
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
-                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s) {
+                      uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s,
+                      int gmode) {
   if (!m) return;
   if (batch)
     launch_signature_w<true>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
-                             slot_of, salt, ctrl, s);
+                             slot_of, salt, ctrl, s, (uint32_t)gmode);
   else
     launch_signature_w<false>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
-                              slot_of, salt, ctrl, s);
+                              slot_of, salt, ctrl, s, (uint32_t)gmode);
 }
 
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
@@ -1292,46 +1356,48 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
                     const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
-                    uint32_t ntiles, hipStream_t s) {
+                    uint32_t ntiles, hipStream_t s, int gmode) {
   if (!m) return;
-  const uint32_t grid = grid_for(m, kBlock);
+  const uint32_t grid = grid_for(std::max(m, ntiles), kBlock);
   if (batch)
     hipLaunchKernelGGL(k_resolve<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
-                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles);
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode);
   else
     hipLaunchKernelGGL(k_resolve<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
-                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles);
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode);
 }
 
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
-                    unsigned long long* scan_status, int items, hipStream_t s) {
+                    unsigned long long* scan_status, int items, hipStream_t s, int gmode) {
   if (!m) return;
   const dim3 grid(scan_tiles(m, items));
+  const uint32_t gm = (uint32_t)gmode;
   if (items == kScanItemsLarge) {
     if (batch)
       hipLaunchKernelGGL((k_compact<true, kScanItemsLarge>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
     else
       hipLaunchKernelGGL((k_compact<false, kScanItemsLarge>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
   } else {
     if (batch)
       hipLaunchKernelGGL((k_compact<true, kScanItemsSmall>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
     else
       hipLaunchKernelGGL((k_compact<false, kScanItemsSmall>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
   }
 }
 
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
-                      Ctrl* ctrl, hipStream_t s, unsigned long long* clear_status, uint32_t clear_tiles) {
+                      Ctrl* ctrl, hipStream_t s, unsigned long long* clear_status, uint32_t clear_tiles,
+                      int gmode) {
   const uint32_t threads = std::max(ninst, clear_status ? clear_tiles : 0u);
   if (!threads) return;
   hipLaunchKernelGGL(k_round_end, dim3(grid_for(threads, kBlock)), dim3(kBlock), 0, s, ninst,
-                     changed_inst, refine_cnt, last, ctrl, clear_status, clear_tiles);
+                     changed_inst, refine_cnt, last, ctrl, clear_status, clear_tiles, (uint32_t)gmode);
 }
 
 void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,

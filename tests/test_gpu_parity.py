@@ -297,3 +297,78 @@ def test_signature_tile_variants_identical(ctx, variant):
             assert r["num_blocks"] == nb and np.array_equal(o, want), d.name
     finally:
         dfamin.dfamin_set_tuning(ctx, -1)
+
+
+def _hash_mode_cases():
+    """Inputs whose later rounds group every instance by hash (queued rounds)."""
+    return [W.random_dfa(3000, 3, 21), W.random_dfa(2500, 4, 22), W.bitsplitter_dfa(9),
+            W.permuted_chain_dfa(1500, 2, 23), W.fib_dfa(13)]
+
+
+def test_queued_rounds_graph_direct_and_planned_agree(ctx):
+    """Once every instance groups by hash, rounds are queued on the device.
+    Replayed from a captured graph (several calls, other work in between),
+    launched one by one (no-graph flag), and planned by the host round by
+    round (profiling on), they give the oracle's partition and the same round
+    counts."""
+    from paper_2410_22764_amd import dfamin
+    cases = [(d, "on" if d.name.lower().startswith(("permuted_chain", "fib")) else "off")
+             for d in _hash_mode_cases()]
+    for d, closure in cases:
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        print(f"[case] queued rounds {d.name} closure={closure}", flush=True)
+        dfamin.dfamin_set_profiling(ctx, True)
+        planned, rp = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+        dfamin.dfamin_set_profiling(ctx, False)
+        assert rp["num_blocks"] == nb and np.array_equal(planned, want), d.name
+        direct, rd = dfamin.dfamin_minimize(ctx, d, dict(closure=closure, no_graph=True))
+        assert np.array_equal(direct, want) and rd == rp, d.name
+        for rep in range(3):
+            out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+            assert np.array_equal(out, want) and r == rp, (d.name, rep)
+            other = W.random_dfa(777 + rep, 2, rep)  # other work between the replays
+            o2, _ = dfamin.dfamin_minimize(ctx, other, "off")
+            assert np.array_equal(o2, oracle.hopcroft(other.n, other.k, other.delta, other.accept)[0])
+
+
+def test_weak_hash_collisions_are_redone(ctx, monkeypatch):
+    """With signature hashes cut to 16 bits of entropy (a testing knob),
+    different signatures of a round share a hash now and then: the full
+    comparison in resolve catches every such case and the round is redone
+    with another salt.  Rounds planned by the host (profiling on) show the
+    redone rounds as extra signature launches; queued rounds redo them on the
+    device.  Partitions and round counts stay exact either way.  Cut to 12
+    bits, every salt collides: the call fails with E_INTERNAL after the
+    bounded retries, in both modes, and the context stays usable."""
+    from paper_2410_22764_amd import dfamin
+    cases = [(W.bitsplitter_dfa(9), "off"), (W.permuted_chain_dfa(1500, 2, 23), "on")]
+
+    def profiled(d, closure):
+        dfamin.dfamin_set_profiling(ctx, True)
+        out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure), check=False)
+        stats = {s["name"]: s["launches"] for s in dfamin.dfamin_get_kernel_stats(ctx)}
+        dfamin.dfamin_set_profiling(ctx, False)
+        return out, r, stats.get("signature", 0)
+
+    strong = {d.name: profiled(d, closure) for d, closure in cases}
+    monkeypatch.setenv("DFAMIN_HASH_BITS", "16")
+    for d, closure in cases:
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        print(f"[case] weak hash {d.name} closure={closure}", flush=True)
+        _, rs, ls = strong[d.name]
+        out, r, lw = profiled(d, closure)
+        assert r["rc"] == 0 and np.array_equal(out, want) and r == rs, d.name
+        assert lw > ls, d.name  # rounds were redone
+        out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+        assert np.array_equal(out, want) and r == rs, d.name
+    monkeypatch.setenv("DFAMIN_HASH_BITS", "12")
+    for d, closure in cases:
+        print(f"[case] hopeless hash {d.name} closure={closure}", flush=True)
+        _, r, _ = profiled(d, closure)
+        assert r["rc"] == dfamin.DFAMIN_E_INTERNAL, d.name
+        _, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure), check=False)
+        assert r["rc"] == dfamin.DFAMIN_E_INTERNAL, d.name
+    monkeypatch.delenv("DFAMIN_HASH_BITS")
+    d, closure = cases[1]
+    out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+    assert np.array_equal(out, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]) and r == strong[d.name][1]
