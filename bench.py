@@ -284,6 +284,8 @@ def main():
                     help="refinement rounds: signature (Algorithm 4) or leader election (Algorithm 2)")
     ap.add_argument("--closure", default=None, choices=["off", "on", "auto"],
                     help="override the workload's closure policy")
+    ap.add_argument("--queue", action="store_true",
+                    help="queue hash-mode and doubling rounds on the device (DFAMIN_FLAG_QUEUE)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event kernel timing")
     ap.add_argument("--profile-steps", type=int, default=5, help="extra steps timed per kernel")
@@ -340,7 +342,7 @@ def main():
     stream = torch.cuda.current_stream()
     ctx = dfamin.dfamin_create(0)
     closure = args.closure or spec["closure"]
-    opts = dict(closure=closure, method=args.method)
+    opts = dict(closure=closure, method=args.method, queue=args.queue)
     if spec["kind"] == "batch":
         from paper_2410_22764_amd import workloads as W
         batch = W.batch_mixed(seed=args.seed)
@@ -348,7 +350,7 @@ def main():
         trans = sum(x.n * x.k for x in batch)
         cfg = {"workload": f"{args.workload}: {spec['desc']}", "instances": len(batch),
                "states": sum(x.n for x in batch), "transitions": trans, "seed": args.seed,
-               "closure": closure, "method": args.method, "parallelism": "single GPU"}
+               "closure": closure, "method": args.method, "queue": args.queue, "parallelism": "single GPU"}
 
         prepared = dfamin.BatchDevice(specs, outs)  # ctypes arguments built once
 
@@ -362,7 +364,7 @@ def main():
         out = torch.empty(d.n, dtype=torch.int32, device=dev)
         trans = d.n * d.k
         cfg = {"workload": f"{args.workload}: {spec['desc']}", "n": d.n, "k": d.k, "seed": args.seed,
-               "closure": closure, "method": args.method, "parallelism": "single GPU"}
+               "closure": closure, "method": args.method, "queue": args.queue, "parallelism": "single GPU"}
         if "paper" in spec:
             cfg["paper_context"] = spec["paper"]
 

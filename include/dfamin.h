@@ -85,8 +85,15 @@ typedef struct {
                                        closure ON this is the paper's transPR (Algorithm 5) */
 
 /* Flags. */
-#define DFAMIN_FLAG_NO_GRAPH 1u     /* leader rounds: launch kernels directly instead of replaying a
-                                       captured HIP graph of rounds (same results) */
+#define DFAMIN_FLAG_NO_GRAPH 1u     /* leader rounds and queued signature rounds: launch kernels directly
+                                       instead of replaying a captured HIP graph of rounds (same results) */
+#define DFAMIN_FLAG_QUEUE 2u        /* signature rounds: once every instance still refining groups by hash
+                                       (or refines by doubling, whose levels the device then plans), queue
+                                       the remaining rounds on the device, replayed from a captured HIP
+                                       graph on a non-null stream, and check for the end after 8, 24, 56 ...
+                                       rounds.  Same partition and round counts; not the default, because
+                                       on the benchmark workloads rounds planned by the host (with the next
+                                       round's independent work overlapped) measure as fast or faster */
 
 typedef struct {
   uint32_t closure;      /* DFAMIN_CLOSURE_*; a zeroed struct means OFF */

@@ -31,7 +31,7 @@ int check_dfa_shape(const dfamin_dfa* d) {
 
 int check_opts(const dfamin_opts* o) {
   if (o && (o->closure > DFAMIN_CLOSURE_AUTO || o->method > DFAMIN_METHOD_LEADER ||
-            (o->flags & ~DFAMIN_FLAG_NO_GRAPH)))
+            (o->flags & ~(DFAMIN_FLAG_NO_GRAPH | DFAMIN_FLAG_QUEUE))))
     return DFAMIN_E_INVAL;
   return DFAMIN_OK;
 }

@@ -155,7 +155,10 @@ class Engine {
   std::array<uint64_t, kQueueKeyWords> queue_key_{};
   hipGraphExec_t queue_exec_ = nullptr;
   int queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, uint64_t salt, uint32_t* cur,
-                    uint32_t* nxt, uint64_t max_left, bool use_graph, hipStream_t s, uint64_t& executed);
+                    uint32_t* nxt, uint64_t max_left, bool use_graph, const QueueDbl* dq, hipStream_t s,
+                    uint64_t& executed);
+  DevBuf d_qdbl_;   // per-instance doubling state of queued rounds
+  HostBuf h_qdbl_;
 };
 
 // Signature-tile autotuner state of a context: a forced variant, or the

@@ -127,12 +127,13 @@ Engine::~Engine() {
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_};
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_};
   for (DevBuf* b : bufs)
     if (b->p) (void)hipFree(b->p);
   for (DevBuf& b : closure_bufs_)
     if (b.p) (void)hipFree(b.p);
-  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_, &h_rb_, &h_lvl_};
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_, &h_rb_, &h_lvl_,
+                   &h_qdbl_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -143,7 +144,7 @@ uint64_t Engine::device_bytes() const {
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                           &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                           &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_};
+                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -403,7 +404,7 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
 // 2, 4 ... of them.  `executed`: the refining rounds run (the one that found
 // nothing to split included).
 int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, uint64_t salt, uint32_t* cur,
-                          uint32_t* nxt, uint64_t max_left, bool use_graph, hipStream_t s,
+                          uint32_t* nxt, uint64_t max_left, bool use_graph, const QueueDbl* dq, hipStream_t s,
                           uint64_t& executed) {
   const size_t I = in_.size();
   const bool batch = I > 1;
@@ -412,6 +413,10 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
   launch_queue_start(d_ctrl_.as<Ctrl>(), (uint32_t)m, salt, s);
   HIP(hipGetLastError());
   auto queue = [&](uint32_t* a, uint32_t* b) {
+    if (dq) {
+      launch_queue_plan(*dq, d_desc_.as<InstDesc>(), d_ctrl_.as<Ctrl>(), s);
+      launch_queue_levels(*dq, d_rows_.as<uint64_t>(), d_ctrl_.as<Ctrl>(), s);
+    }
     launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 1);
     launch_signature(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                      d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, 4, d_table_.as<Slot>(), tbits,
@@ -425,6 +430,7 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
                    d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), items, s, 1);
     launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
                      d_ctrl_.as<Ctrl>(), s, nullptr, 0, 1);
+    if (dq) launch_queue_advance(*dq, d_ctrl_.as<Ctrl>(), s);
     launch_round_step(d_ctrl_.as<Ctrl>(), s);
   };
   hipGraphExec_t exec = nullptr;
@@ -438,7 +444,8 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
         reinterpret_cast<uint64_t>(d_keep_.p), reinterpret_cast<uint64_t>(d_changed_.p),
         reinterpret_cast<uint64_t>(d_refine_.p), reinterpret_cast<uint64_t>(d_ctrl_.p),
         reinterpret_cast<uint64_t>(d_status_.p), reinterpret_cast<uint64_t>(d_dense_.p),
-        reinterpret_cast<uint64_t>(s), 1, 0, 0};
+        reinterpret_cast<uint64_t>(s), 1, dq ? reinterpret_cast<uint64_t>(dq->mj) : 0,
+        dq ? ((uint64_t)dq->count << 32 | dq->wgs) : 0};
     if (queue_exec_ && queue_key_ == key) {
       exec = queue_exec_;
     } else {
@@ -531,6 +538,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   std::vector<LevelTodo> todo;
   uint64_t spec_clear = 0;  // table slots cleared ahead for the coming round
   bool prev_all_hash = false;  // the last round grouped every instance by hash
+
   struct TrimLazy {
     Engine* e;
     const std::vector<uint8_t>& lazy;
@@ -723,7 +731,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     // hash in this round and the last, none refines by doubling or still
     // waits for its AUTO closure, and none needs a count scan.
     const bool all_hash = rounds > 0 && exact.empty();
-    bool queue_ok = all_hash && prev_all_hash && !prof.enabled();
+    const bool queue_allowed = !prof.enabled() && (opts.flags & DFAMIN_FLAG_QUEUE);
+    bool queue_ok = all_hash && prev_all_hash && queue_allowed;
     for (uint32_t i : alist) {
       if (!queue_ok) break;
       if (dbl[i] || would_scan(i) ||
@@ -731,12 +740,82 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         queue_ok = false;
     }
     prev_all_hash = all_hash;
-    if (queue_ok) {
+    // ... or every instance still refining doubles, with levels built as
+    // read: the device then plans the levels too, and every round groups by
+    // hash (always exact; for one gathered letter about as fast as exact
+    // keys with their count scans)
+    bool queue_dbl = !queue_ok && queue_allowed && rounds > 0 && !alist.empty();
+    for (uint32_t i : alist) {
+      if (!queue_dbl) break;
+      if (!dbl[i] || !lazy[i]) queue_dbl = false;
+    }
+    QueueDbl dq{};
+    if (queue_dbl) {
+      const uint32_t T = (uint32_t)alist.size();
+      const size_t bytes = 8ull * T + 36ull * T;
+      TRY(ensure(d_qdbl_, bytes));
+      TRY(ensure_host(h_qdbl_, bytes));
+      uint64_t* hmj = h_qdbl_.as<uint64_t>();
+      uint32_t* h32 = reinterpret_cast<uint32_t*>(hmj + T);
+      uint32_t* f[9];
+      for (int a = 0; a < 9; ++a) f[a] = h32 + (size_t)a * T;  // list built lmax rbase need lv used n wgoff
+      uint32_t wgs = 0;
+      for (uint32_t t = 0; t < T; ++t) {
+        const uint32_t i = alist[t];
+        hmj[t] = mj[i];
+        f[0][t] = i;
+        f[1][t] = built[i];
+        f[2][t] = (uint32_t)inst_rows_[i].size() - 1;
+        f[3][t] = row_base_[i];
+        f[4][t] = 0;
+        f[5][t] = 0;
+        f[6][t] = used[i];
+        f[7][t] = in_[i].n;
+        f[8][t] = wgs;
+        wgs += (in_[i].n + kRowTile - 1) / kRowTile;
+        desc_[i].ebits = 0;  // hash keys from here on
+        desc_[i].dsrc = 0;
+      }
+      HIP(hipMemcpyAsync(d_qdbl_.p, h_qdbl_.p, bytes, hipMemcpyHostToDevice, s));
+      std::memcpy(h_desc_.p, desc_.data(), I * sizeof(InstDesc));
+      HIP(hipMemcpyAsync(d_desc_.p, h_desc_.p, I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+      uint64_t* dmj = d_qdbl_.as<uint64_t>();
+      uint32_t* d32 = reinterpret_cast<uint32_t*>(dmj + T);
+      dq.mj = dmj;
+      dq.list = d32;
+      dq.built = d32 + T;
+      dq.lmax = d32 + 2 * T;
+      dq.rbase = d32 + 3 * T;
+      dq.need = d32 + 4 * T;
+      dq.lv = d32 + 5 * T;
+      dq.used = d32 + 6 * T;
+      dq.n = d32 + 7 * T;
+      dq.wgoff = d32 + 8 * T;
+      dq.count = T;
+      dq.wgs = wgs;
+    }
+    if (queue_ok || queue_dbl) {
       if (tu.forced >= 0) variant = tu.forced;
       else if (tuned != tu.best.end()) variant = tuned->second;
       const bool use_graph = !(opts.flags & DFAMIN_FLAG_NO_GRAPH) && s != nullptr;
+      // hash keys for every instance: at most m groups
+      const uint32_t qtbits = queue_dbl ? std::max<uint32_t>(9, ceil_log2_u64(2 * m)) : tbits;
+      TRY(ensure(d_table_, (1ull << qtbits) * sizeof(Slot)));
       uint64_t executed = 0;
-      TRY(queued_rounds(m, tbits, variant, citems, salt, cur, nxt, max_rounds - rounds, use_graph, s, executed));
+      TRY(queued_rounds(m, qtbits, variant, citems, salt, cur, nxt, max_rounds - rounds, use_graph,
+                        queue_dbl ? &dq : nullptr, s, executed));
+      if (queue_dbl) {
+        // levels built and read on the device
+        const uint32_t T = dq.count;
+        HIP(hipMemcpyAsync(h_qdbl_.p, d_qdbl_.p, 8ull * T + 36ull * T, hipMemcpyDeviceToHost, s));
+        HIP(stream_wait(s));
+        const uint32_t* h32 = reinterpret_cast<const uint32_t*>(h_qdbl_.as<uint64_t>() + T);
+        for (uint32_t t = 0; t < T; ++t) {
+          const uint32_t i = h32[t];
+          built[i] = std::max(built[i], h32[T + t]);
+          used[i] = std::max(used[i], h32[6 * T + t]);
+        }
+      }
       rounds += executed;
       if (rounds > max_rounds) return DFAMIN_E_INTERNAL;
       if (trace) std::fprintf(stderr, "[dfamin] %llu queued rounds from m=%llu\n", (unsigned long long)executed,

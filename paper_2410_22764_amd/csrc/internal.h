@@ -211,6 +211,22 @@ void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_c
 void launch_queue_start(Ctrl* ctrl, uint32_t m, uint64_t salt, hipStream_t s);
 // *p = v, in stream order
 void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s);
+// Queued rounds of instances refining by doubling (one closure level per
+// round, 2^l <= j+1): per listed instance t (instance list[t]) the device
+// keeps j (mj), the levels built and the highest level read.  Before a
+// round, plan points the descriptor at this round's level (and notes a
+// level to build: at most one, since j at least doubles) and levels builds
+// it (dst = src o src, Algorithm 5) over the instance's states; after a
+// round that was not redone, advance adds 2^l to j.  All return at once when
+// ctrl->stop is set.
+struct QueueDbl {
+  uint64_t* mj;
+  uint32_t *list, *built, *lmax, *rbase, *need, *lv, *used, *n, *wgoff;
+  uint32_t count, wgs;
+};
+void launch_queue_plan(const QueueDbl& q, InstDesc* desc, const Ctrl* ctrl, hipStream_t s);
+void launch_queue_levels(const QueueDbl& q, const uint64_t* rows, const Ctrl* ctrl, hipStream_t s);
+void launch_queue_advance(const QueueDbl& q, const Ctrl* ctrl, hipStream_t s);
 void launch_round_step(Ctrl* ctrl, hipStream_t s);
 constexpr uint32_t kMaxSaltRetries = 8;
 // One round of leader-based refinement (Algorithm 2, Section 3.2) over all

@@ -726,6 +726,45 @@ __global__ void k_store_u64(uint64_t* __restrict__ p, uint64_t v) {
   if (threadIdx.x == 0) *p = v;
 }
 
+__global__ __launch_bounds__(kBlock) void k_queue_plan(QueueDbl q, InstDesc* __restrict__ desc,
+                                                       const Ctrl* __restrict__ ctrl) {
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= q.count || ctrl->stop) return;
+  const uint32_t i = q.list[t];
+  uint32_t lvl = 0;
+  for (uint64_t x = q.mj[t] + 1; x >> 1; x >>= 1) ++lvl;  // floor(log2(j+1))
+  if (lvl > q.lmax[t]) lvl = q.lmax[t];
+  desc[i].rows_off = q.rbase[t] + lvl;
+  q.need[t] = lvl > q.built[t] ? lvl : 0u;
+  if (lvl > q.built[t]) q.built[t] = lvl;
+  q.lv[t] = lvl;
+  if (lvl > q.used[t]) q.used[t] = lvl;
+}
+
+__global__ __launch_bounds__(kBlock) void k_queue_levels(QueueDbl q, const uint64_t* __restrict__ rows,
+                                                         const Ctrl* __restrict__ ctrl) {
+  __shared__ uint32_t s_job;
+  if (ctrl->stop) return;
+  const uint32_t t = find_job(q.wgoff, q.count, &s_job);
+  const uint32_t lvl = q.need[t];
+  if (!lvl) return;
+  const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(rows[q.rbase[t] + lvl - 1]);
+  uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(rows[q.rbase[t] + lvl]);
+  const uint32_t n = q.n[t];
+  const uint32_t base = (blockIdx.x - q.wgoff[t]) * kRowTile;
+#pragma unroll
+  for (int e = 0; e < kRowTile / kBlock; ++e) {
+    const uint32_t x = base + e * kBlock + threadIdx.x;
+    if (x < n) dst[x] = src[src[x]];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_queue_advance(QueueDbl q, const Ctrl* __restrict__ ctrl) {
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= q.count || ctrl->stop || ctrl->collision) return;
+  q.mj[t] += 1ull << q.lv[t];
+}
+
 __global__ void k_round_step(Ctrl* __restrict__ ctrl) {
   if (threadIdx.x != 0 || ctrl->stop) return;
   if (ctrl->collision) {  // redo the round with another salt
@@ -1264,6 +1303,21 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, 
 
 void launch_queue_start(Ctrl* ctrl, uint32_t m, uint64_t salt, hipStream_t s) {
   hipLaunchKernelGGL(k_queue_start, dim3(1), dim3(64), 0, s, ctrl, m, salt);
+}
+
+void launch_queue_plan(const QueueDbl& q, InstDesc* desc, const Ctrl* ctrl, hipStream_t s) {
+  if (!q.count) return;
+  hipLaunchKernelGGL(k_queue_plan, dim3(grid_for(q.count, kBlock)), dim3(kBlock), 0, s, q, desc, ctrl);
+}
+
+void launch_queue_levels(const QueueDbl& q, const uint64_t* rows, const Ctrl* ctrl, hipStream_t s) {
+  if (!q.count || !q.wgs) return;
+  hipLaunchKernelGGL(k_queue_levels, dim3(q.wgs), dim3(kBlock), 0, s, q, rows, ctrl);
+}
+
+void launch_queue_advance(const QueueDbl& q, const Ctrl* ctrl, hipStream_t s) {
+  if (!q.count) return;
+  hipLaunchKernelGGL(k_queue_advance, dim3(grid_for(q.count, kBlock)), dim3(kBlock), 0, s, q, ctrl);
 }
 
 void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s) {

@@ -141,12 +141,15 @@ dfamin_status_str = status_str
 
 METHOD = {"signature": 0, "leader": 1}
 FLAG_NO_GRAPH = 1
+FLAG_QUEUE = 2
 
 
-def make_opts(closure="off", max_levels=0, auto_rounds=0, max_rounds=0, method="signature", no_graph=False):
+def make_opts(closure="off", max_levels=0, auto_rounds=0, max_rounds=0, method="signature", no_graph=False,
+              queue=False):
     c = CLOSURE[closure] if isinstance(closure, str) else int(closure)
     m = METHOD[method] if isinstance(method, str) else int(method)
-    return Opts(c, max_levels, auto_rounds, max_rounds, m, FLAG_NO_GRAPH if no_graph else 0)
+    flags = (FLAG_NO_GRAPH if no_graph else 0) | (FLAG_QUEUE if queue else 0)
+    return Opts(c, max_levels, auto_rounds, max_rounds, m, flags)
 
 
 def _opts(opts):

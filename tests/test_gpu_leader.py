@@ -113,7 +113,7 @@ def test_leader_options_rejected(ctx):
     _, res = dfamin.dfamin_minimize(ctx, d, dfamin.make_opts(method=2), check=False)
     assert res["rc"] == dfamin.DFAMIN_E_INVAL
     o = dfamin.make_opts()
-    o.flags = 2
+    o.flags = 4  # no such flag
     _, res = dfamin.dfamin_minimize(ctx, d, o, check=False)
     assert res["rc"] == dfamin.DFAMIN_E_INVAL
     with pytest.raises(dfamin.DfaminError):

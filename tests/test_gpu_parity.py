@@ -4,6 +4,8 @@ Every comparison is exact (integer output, canonical numbering).  Sizes span
 several workgroup tiles (256 states per signature workgroup, 1024 per scan
 tile) and ragged tails.
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -306,11 +308,11 @@ def _hash_mode_cases():
 
 
 def test_queued_rounds_graph_direct_and_planned_agree(ctx):
-    """Once every instance groups by hash, rounds are queued on the device.
-    Replayed from a captured graph (several calls, other work in between),
-    launched one by one (no-graph flag), and planned by the host round by
-    round (profiling on), they give the oracle's partition and the same round
-    counts."""
+    """With the queue flag, once every instance groups by hash the rounds are
+    queued on the device.  Replayed from a captured graph (several calls,
+    other work in between), launched one by one (no-graph flag), and planned
+    by the host round by round (profiling on), they give the oracle's
+    partition and the same round counts."""
     from paper_2410_22764_amd import dfamin
     cases = [(d, "on" if d.name.lower().startswith(("permuted_chain", "fib")) else "off")
              for d in _hash_mode_cases()]
@@ -321,10 +323,10 @@ def test_queued_rounds_graph_direct_and_planned_agree(ctx):
         planned, rp = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
         dfamin.dfamin_set_profiling(ctx, False)
         assert rp["num_blocks"] == nb and np.array_equal(planned, want), d.name
-        direct, rd = dfamin.dfamin_minimize(ctx, d, dict(closure=closure, no_graph=True))
+        direct, rd = dfamin.dfamin_minimize(ctx, d, dict(closure=closure, queue=True, no_graph=True))
         assert np.array_equal(direct, want) and rd == rp, d.name
         for rep in range(3):
-            out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+            out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure, queue=True))
             assert np.array_equal(out, want) and r == rp, (d.name, rep)
             other = W.random_dfa(777 + rep, 2, rep)  # other work between the replays
             o2, _ = dfamin.dfamin_minimize(ctx, other, "off")
@@ -359,16 +361,52 @@ def test_weak_hash_collisions_are_redone(ctx, monkeypatch):
         out, r, lw = profiled(d, closure)
         assert r["rc"] == 0 and np.array_equal(out, want) and r == rs, d.name
         assert lw > ls, d.name  # rounds were redone
-        out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
+        out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure, queue=True))
         assert np.array_equal(out, want) and r == rs, d.name
     monkeypatch.setenv("DFAMIN_HASH_BITS", "12")
     for d, closure in cases:
         print(f"[case] hopeless hash {d.name} closure={closure}", flush=True)
         _, r, _ = profiled(d, closure)
         assert r["rc"] == dfamin.DFAMIN_E_INTERNAL, d.name
-        _, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure), check=False)
+        _, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure, queue=True), check=False)
         assert r["rc"] == dfamin.DFAMIN_E_INTERNAL, d.name
     monkeypatch.delenv("DFAMIN_HASH_BITS")
     d, closure = cases[1]
     out, r = dfamin.dfamin_minimize(ctx, d, dict(closure=closure))
     assert np.array_equal(out, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]) and r == strong[d.name][1]
+
+
+def test_queued_doubling_rounds_agree(ctx):
+    """One-letter instances under AUTO with the queue flag: once every
+    instance still refining doubles, the device plans the levels and the
+    rounds are queued (hash keys).  Alone and in a batch of chains of different lengths, queued
+    rounds (graph and direct) match host-planned rounds (profiling on) and
+    the oracle, with the round counts derived from Moore's partitions."""
+    from paper_2410_22764_amd import dfamin
+    singles = [W.chain_dfa(2000, 2), W.fib_dfa(14), W.permuted_chain_dfa(1500, 3, 5), W.random_dfa(1500, 1, 4)]
+    for d in singles:
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        print(f"[case] queued doubling {d.name}", flush=True)
+        dfamin.dfamin_set_profiling(ctx, True)
+        planned, rp = dfamin.dfamin_minimize(ctx, d, "auto")
+        dfamin.dfamin_set_profiling(ctx, False)
+        assert np.array_equal(planned, want) and rp["refine_rounds"] == _auto_unary_rounds(d), d.name
+        for opts in [dict(closure="auto", queue=True), dict(closure="auto", queue=True, no_graph=True),
+                     dict(closure="auto", queue=True)]:
+            out, r = dfamin.dfamin_minimize(ctx, d, opts)
+            assert np.array_equal(out, want) and r == rp, (d.name, opts)
+    sizes = (17, 300, 1000, 4097, 20000)
+    batch = [W.permuted_chain_dfa(n, 2, 40 + n) for n in sizes] + [W.fib_dfa(12)]
+    # a chain of n states needs ceil(log2(n - 1)) doubling rounds (P_(2^r - 1)
+    # holds every state alone once 2^r - 1 >= n - 2)
+    want_rounds = [math.ceil(math.log2(n - 1)) for n in sizes] + [_auto_unary_rounds(batch[-1])]
+    print("[case] queued doubling batch", flush=True)
+    dfamin.dfamin_set_profiling(ctx, True)
+    po, pr = dfamin.dfamin_minimize_batch(ctx, batch, "auto")
+    dfamin.dfamin_set_profiling(ctx, False)
+    for opts in [dict(closure="auto", queue=True), dict(closure="auto", queue=True, no_graph=True)]:
+        outs, res = dfamin.dfamin_minimize_batch(ctx, batch, opts)
+        for d, o, r, p, rp, wr in zip(batch, outs, res, po, pr, want_rounds):
+            want, _ = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert np.array_equal(o, want) and np.array_equal(p, want), d.name
+            assert r == rp and r["refine_rounds"] == wr, d.name
