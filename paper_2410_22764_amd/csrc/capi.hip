@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <algorithm>
+#include <thread>
+#include <atomic>
 #include <new>
 #include <vector>
 
@@ -101,6 +104,57 @@ int ensure_host(dfamin::HostBuf& b, size_t bytes) {
 inline size_t accept_bytes(uint32_t n) { return ((size_t)n + 7) / 8; }
 inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
+// One contiguous host copy of a staged transfer.
+struct Piece {
+  char* dst;
+  const char* src;
+  size_t bytes;
+  size_t dev_off;  // where the piece goes in device memory (uploads)
+};
+constexpr size_t kPieceBytes = 4u << 20;
+
+// Runs pieces on up to 8 host threads (fewer for small transfers); each
+// piece, once copied, is handed to after(piece) on the same thread.  Threads
+// started here make `device` current first (-1: none).  Returns false if any
+// after() failed.
+template <typename After>
+bool run_pieces(const std::vector<Piece>& pieces, size_t total_bytes, int device, After after) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const unsigned nt = (unsigned)std::min<size_t>({8u, hw, (total_bytes + kPieceBytes - 1) / kPieceBytes});
+  std::atomic<size_t> next{0};
+  std::atomic<bool> ok{true};
+  auto work = [&] {
+    for (size_t j = next++; j < pieces.size(); j = next++) {
+      std::memcpy(pieces[j].dst, pieces[j].src, pieces[j].bytes);
+      if (!after(pieces[j])) ok = false;
+    }
+  };
+  if (nt <= 1) {
+    work();
+  } else {
+    std::vector<std::thread> ts;
+    for (unsigned t = 1; t < nt; ++t)
+      ts.emplace_back([&] {
+        if (device >= 0 && hipSetDevice(device) != hipSuccess) {
+          ok = false;
+          return;
+        }
+        work();
+      });
+    work();
+    for (auto& t : ts) t.join();
+  }
+  return ok;
+}
+
+// Splits [src, src + bytes) into pieces of at most kPieceBytes.
+void add_pieces(std::vector<Piece>& out, char* dst, const char* src, size_t bytes, size_t dev_off) {
+  for (size_t o = 0; o < bytes; o += kPieceBytes) {
+    const size_t b = std::min(kPieceBytes, bytes - o);
+    out.push_back({dst + o, src + o, b, dev_off + o});
+  }
+}
+
 // Host-input batch: pack every instance into pinned staging, one H2D copy,
 // run, one D2H copy, scatter into the caller's buffers.
 int run_host_batch(Context& c, uint32_t count, const dfamin_dfa* dfas, const dfamin_opts& o,
@@ -120,12 +174,22 @@ int run_host_batch(Context& c, uint32_t count, const dfamin_dfa* dfas, const dfa
   if ((rc = ensure_host(c.h_out, out_bytes)) != DFAMIN_OK) return rc;
   if ((rc = ensure(c, c.in_delta, in_bytes)) != DFAMIN_OK) return rc;
   if ((rc = ensure(c, c.in_out, out_bytes)) != DFAMIN_OK) return rc;
+  // Staging: pieces of the caller's buffers are copied into page-locked
+  // memory by several threads, and each piece is uploaded as soon as it is
+  // there, so the host copies overlap the transfers (all are queued before
+  // any kernel of the call).
   char* hin = c.h_in.as<char>();
+  char* din = c.in_delta.as<char>();
+  std::vector<Piece> pieces;
   for (uint32_t i = 0; i < count; ++i) {
-    std::memcpy(hin + d_off[i], dfas[i].delta, 4ull * dfas[i].n * dfas[i].k);
-    std::memcpy(hin + a_off[i], dfas[i].accept, accept_bytes(dfas[i].n));
+    add_pieces(pieces, hin + d_off[i], reinterpret_cast<const char*>(dfas[i].delta), 4ull * dfas[i].n * dfas[i].k,
+               d_off[i]);
+    add_pieces(pieces, hin + a_off[i], reinterpret_cast<const char*>(dfas[i].accept), accept_bytes(dfas[i].n),
+               a_off[i]);
   }
-  if (hipMemcpyAsync(c.in_delta.p, hin, in_bytes, hipMemcpyHostToDevice, c.stream) != hipSuccess)
+  if (!run_pieces(pieces, in_bytes, c.device, [&](const Piece& p) {
+        return hipMemcpyAsync(din + p.dev_off, p.dst, p.bytes, hipMemcpyHostToDevice, c.stream) == hipSuccess;
+      }))
     return DFAMIN_E_DEVICE;
   std::vector<InstInput> in(count);
   char* dbase = c.in_delta.as<char>();
@@ -150,10 +214,12 @@ int run_host_batch(Context& c, uint32_t count, const dfamin_dfa* dfas, const dfa
     return DFAMIN_E_DEVICE;
   if (hipStreamSynchronize(c.stream) != hipSuccess) return DFAMIN_E_DEVICE;
   const char* hout = c.h_out.as<char>();
+  std::vector<Piece> back;
   for (uint32_t i = 0; i < count; ++i) {
-    std::memcpy(outs[i], hout + o_off[i], 4ull * dfas[i].n);
+    add_pieces(back, reinterpret_cast<char*>(outs[i]), hout + o_off[i], 4ull * dfas[i].n, 0);
     to_result(res[i], results ? &results[i] : nullptr);
   }
+  (void)run_pieces(back, out_bytes, -1, [](const Piece&) { return true; });
   return DFAMIN_OK;
 }
 
