@@ -309,9 +309,19 @@ int dfamin_minimal_dfa(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin
   const uint8_t* d_acc = nullptr;
   rc = ctx->c.engine.minimal_dfa(o, ctx->c.stream, r.num_blocks, r.initial_block, mi, &d_delta, &d_acc);
   if (rc != DFAMIN_OK) return rc;
-  if (hipMemcpy(min_delta, d_delta, 4ull * host_dfa->k * mi.n, hipMemcpyDeviceToHost) != hipSuccess ||
-      hipMemcpy(min_accept, d_acc, ((size_t)mi.n + 7) / 8, hipMemcpyDeviceToHost) != hipSuccess)
+  // back through page-locked staging on the context's stream, then to the
+  // caller's buffers by several threads
+  const size_t dbytes = 4ull * host_dfa->k * mi.n, abytes = ((size_t)mi.n + 7) / 8;
+  if ((rc = ensure_host(ctx->c.h_out, align16(dbytes) + abytes)) != DFAMIN_OK) return rc;
+  char* hb = ctx->c.h_out.as<char>();
+  if (hipMemcpyAsync(hb, d_delta, dbytes, hipMemcpyDeviceToHost, ctx->c.stream) != hipSuccess ||
+      hipMemcpyAsync(hb + align16(dbytes), d_acc, abytes, hipMemcpyDeviceToHost, ctx->c.stream) != hipSuccess ||
+      hipStreamSynchronize(ctx->c.stream) != hipSuccess)
     return DFAMIN_E_DEVICE;
+  std::vector<Piece> back;
+  add_pieces(back, reinterpret_cast<char*>(min_delta), hb, dbytes, 0);
+  add_pieces(back, reinterpret_cast<char*>(min_accept), hb + align16(dbytes), abytes, 0);
+  (void)run_pieces(back, dbytes + abytes, -1, [](const Piece&) { return true; });
   if (info) {
     *info = dfamin_minimal{};
     info->n = mi.n;
