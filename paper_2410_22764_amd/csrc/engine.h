@@ -149,6 +149,8 @@ class Engine {
   GraphKey graph_key_{};
   hipGraphExec_t graph_exec_ = nullptr;
   hipEvent_t ev_rb_ = nullptr;  // a signature round's readback, waited for by itself
+  hipEvent_t ev_lvl_ = nullptr;  // the last upload of level jobs out of h_lvl_
+  bool lvl_pending_ = false;      // ev_lvl_ recorded and not yet waited for
   // captured queued signature rounds, reused while every pointer and size in
   // the key matches
   static constexpr int kQueueKeyWords = 24;

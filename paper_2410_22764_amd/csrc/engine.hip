@@ -122,6 +122,7 @@ Engine::~Engine() {
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
   if (queue_exec_) (void)hipGraphExecDestroy(queue_exec_);
   if (ev_rb_) (void)hipEventDestroy(ev_rb_);
+  if (ev_lvl_) (void)hipEventDestroy(ev_lvl_);
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
@@ -348,6 +349,13 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   uint32_t S = 0;
   for (const LevelTodo& t : todo) S = std::max(S, t.step + 1);
   const size_t bytes = J * (sizeof(RowJob) + 4);
+  // h_lvl_ is page-locked, so its last upload reads it whenever the stream
+  // gets there: wait for that copy before the jobs are rewritten (two calls
+  // can fall in one round, with the round's kernels queued in between)
+  if (lvl_pending_) {
+    HIP(event_wait(ev_lvl_));
+    lvl_pending_ = false;
+  }
   TRY(ensure_host(h_lvl_, bytes));
   TRY(ensure(d_lvl_, bytes));
   RowJob* hj = h_lvl_.as<RowJob>();
@@ -379,6 +387,9 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   TRY(ensure(d_lvl_wg_, (size_t)maxw * 4));
   TRY(ensure(d_lvl_flags_, J * 4));
   HIP(hipMemcpyAsync(d_lvl_.p, h_lvl_.p, bytes, hipMemcpyHostToDevice, s));
+  if (!ev_lvl_) HIP(hipEventCreateWithFlags(&ev_lvl_, hipEventDisableTiming));
+  HIP(hipEventRecord(ev_lvl_, s));
+  lvl_pending_ = true;
   RowJob* dj = d_lvl_.as<RowJob>();
   uint32_t* dof = reinterpret_cast<uint32_t*>(dj + J);
   Profiler& prof = ctx_->prof;
@@ -593,9 +604,12 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       // round costs what a plain one does (one gathered letter) plus one
       // level pass, and after r rounds it holds P_(2^r - 1) instead of P_r.
       // Those whose level storage does not fit stay plain for now.
+      // (a round redone after a hash collision keeps the storage and the
+      // levels already built for it)
       std::vector<uint32_t> uni, rest;
       for (uint32_t i : alist)
-        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && nonid_[i].size() == 1) uni.push_back(i);
+        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && nonid_[i].size() == 1 && !has_closure_[i])
+          uni.push_back(i);
       if (!uni.empty()) {
         TRY(lazy_levels(uni, opts, rest, lazy));
         for (uint32_t i : uni) dbl[i] = lazy[i];

@@ -169,6 +169,7 @@ class Ctx:
 
     def __init__(self, handle):
         self.handle = handle
+        self.tickets = {}  # serving ticket -> n of the submitted DFA
 
     def close(self):
         if self.handle:
@@ -200,10 +201,19 @@ def dfamin_destroy(ctx):
     ctx.close()
 
 
-def _host_dfa(d):
-    delta = np.ascontiguousarray(d.delta, dtype=np.uint32)
-    accept = np.ascontiguousarray(d.accept, dtype=np.uint8)
-    s = Dfa(int(d.n), int(d.k), delta.ctypes.data, accept.ctypes.data, int(d.q0))
+def _host_dfa(d, check=True):
+    """Marshal a host DFA.  The library copies k*n transitions and ceil(n/8)
+    accept bytes out of these buffers, so shorter arrays are refused here
+    (ValueError) before any native call; check=False marshals as given."""
+    n, k = int(d.n), int(d.k)
+    delta = np.ascontiguousarray(d.delta, dtype=np.uint32).reshape(-1)
+    accept = np.ascontiguousarray(d.accept, dtype=np.uint8).reshape(-1)
+    if check:
+        if delta.size != n * k:
+            raise ValueError(f"delta holds {delta.size} entries, k*n = {n * k}")
+        if accept.size < (n + 7) // 8:
+            raise ValueError(f"accept holds {accept.size} bytes, ceil(n/8) = {(n + 7) // 8}")
+    s = Dfa(n, k, delta.ctypes.data, accept.ctypes.data, int(d.q0))
     return s, (delta, accept)
 
 
@@ -304,15 +314,23 @@ def dfamin_submit(ctx, dfa, opts=None):
     rc = load().dfamin_submit(ctx.handle, ctypes.byref(s), _opts(opts), ctypes.byref(t))
     if rc != DFAMIN_OK:
         raise DfaminError(rc, "dfamin_submit")
+    ctx.tickets[t.value] = int(dfa.n)
     return t.value
 
 
 def dfamin_wait(ctx, ticket, n, timeout_us=-1):
-    """Returns (rc, out or None, result dict)."""
-    out = np.empty(int(n), np.uint32)
+    """Returns (rc, out or None, result dict).  The library writes the
+    submitted DFA's n classes into `out`, so n must be at least that n for
+    tickets of this context (ValueError otherwise)."""
+    known = ctx.tickets.get(int(ticket))
+    if known is not None and int(n) < known:
+        raise ValueError(f"ticket {ticket} holds {known} states, out has room for {n}")
+    out = np.empty(max(int(n), known or 0, 1), np.uint32)
     res = Result()
     rc = load().dfamin_wait(ctx.handle, int(ticket), int(timeout_us), out.ctypes.data, ctypes.byref(res))
-    return rc, (out if rc == DFAMIN_OK else None), res.as_dict()
+    if rc != DFAMIN_E_TIMEOUT:
+        ctx.tickets.pop(int(ticket), None)
+    return rc, (out[: int(n)] if rc == DFAMIN_OK else None), res.as_dict()
 
 
 def dfamin_cancel(ctx, ticket):

@@ -52,3 +52,44 @@ def test_create_without_gpu_reports_device_error():
     h = ctypes.c_void_p()
     rc = dfamin.load().dfamin_create(0, 0, ctypes.byref(h))
     assert rc == dfamin.DFAMIN_E_DEVICE and not h.value
+
+
+def test_binding_refuses_short_host_arrays():
+    """The library copies k*n transitions and ceil(n/8) accept bytes out of
+    the caller's host buffers; the binding refuses shorter arrays before any
+    native call (here: no context, no GPU)."""
+    import numpy as np
+    from paper_2410_22764_amd import workloads as W
+
+    class NoCtx:
+        handle = None
+        tickets = {}
+
+    n = 7913
+    rows = np.stack([(np.arange(n) + 1) % n, np.arange(n)]).astype(np.uint32)
+    acc = np.arange(n) % 3 == 0
+    good = W.from_rows(rows, acc)
+    assert good.accept.size == (n + 7) // 8
+    twice = W.from_rows(rows, W.pack_accept(acc))  # bitmap packed twice: 124 bytes
+    assert twice.accept.size < (n + 7) // 8
+    for call in (lambda d: dfamin.dfamin_minimize(NoCtx(), d),
+                 lambda d: dfamin.dfamin_minimize_batch(NoCtx(), [good, d]),
+                 lambda d: dfamin.dfamin_submit(NoCtx(), d),
+                 lambda d: dfamin.dfamin_minimal_dfa(NoCtx(), d)):
+        with pytest.raises(ValueError, match="accept"):
+            call(twice)
+        short = W.DFA(n, 2, good.delta[:-1], good.accept)
+        with pytest.raises(ValueError, match="delta"):
+            call(short)
+    # raw marshalling stays available to exercise the C-side checks
+    s, _ = dfamin._host_dfa(twice, check=False)
+    assert s.n == n
+
+
+def test_wait_refuses_an_output_shorter_than_the_ticket():
+    class FakeCtx:
+        handle = None
+        tickets = {7: 100}
+
+    with pytest.raises(ValueError, match="room"):
+        dfamin.dfamin_wait(FakeCtx(), 7, 99)

@@ -376,6 +376,80 @@ def test_weak_hash_collisions_are_redone(ctx, monkeypatch):
     assert np.array_equal(out, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]) and r == strong[d.name][1]
 
 
+def test_first_round_redo_keeps_doubling_levels(ctx, monkeypatch):
+    """A hash collision in the first round redoes it for the whole batch.
+    The one-letter AUTO instances, which refine by doubling from that round,
+    keep their level storage and the level already built for the next round
+    (queued while the host waits).  A 40-letter instance groups by hash from
+    the first round (41 key components do not fit 31 bits); with hashes cut
+    to 16 bits of entropy (a testing knob), its 250 states collide in about a
+    third of all attempts.  Every batch that finishes matches the oracle; one
+    whose retries all collide fails with E_INTERNAL and is skipped."""
+    from paper_2410_22764_amd import dfamin
+    monkeypatch.setenv("DFAMIN_HASH_BITS", "16")
+    finished = 0
+    for seed in range(6):
+        ds = [W.random_dfa(250, 40, 100 + seed), W.random_dfa(3000, 1, 200 + seed),
+              W.permuted_chain_dfa(2000, 1, 300 + seed)]
+        print(f"[case] first-round redo seed={seed}", flush=True)
+        outs, res = dfamin.dfamin_minimize_batch(ctx, ds, dict(closure="auto"), check=False)
+        if res[0]["rc"] == dfamin.DFAMIN_E_INTERNAL:
+            continue
+        finished += 1
+        for d, o, r in zip(ds, outs, res):
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert r["rc"] == 0 and r["num_blocks"] == nb and np.array_equal(o, want), (seed, d.name)
+    monkeypatch.delenv("DFAMIN_HASH_BITS")
+    assert finished >= 3
+
+
+def _mixed_case(rng, i):
+    kind = rng.choice(["random", "chain", "pchain", "fib", "coarse", "cycle"])
+    n = int(2 ** rng.uniform(0, 12)) + 1
+    k = int(rng.integers(1, 6))
+    seed = int(rng.integers(1, 1 << 30))
+    if kind == "random":
+        return W.random_dfa(n, k, seed)
+    if kind == "chain":
+        return W.chain_dfa(max(n, 2), k)
+    if kind == "pchain":
+        return W.permuted_chain_dfa(max(n, 2), k, seed)
+    if kind == "fib":
+        return W.fib_dfa(int(rng.integers(3, 15)))
+    if kind == "cycle":
+        rows = np.array([(np.arange(n) + 1) % n] + [np.arange(n)] * (k - 1), dtype=np.uint32)
+        return W.from_rows(rows, rng.random(n) < 0.3, name=f"cycle{n}x{k}")
+    d = W.random_dfa(n, k, seed)
+    acc = np.zeros(n, bool)
+    acc[:: int(rng.integers(2, 50))] = True
+    d.accept = W.pack_accept(acc)
+    return d
+
+
+def test_mixed_call_sequence_one_context(ctx):
+    """Sixty calls on one context with shapes, methods and options drawn at
+    random (seeded): single DFAs and batches, closure off/on/auto, queued
+    rounds on and off, signature and leader rounds.  Buffers, captured
+    graphs and tuned tiles carried from call to call must not change any
+    result: each one is checked against the oracle."""
+    from paper_2410_22764_amd import dfamin
+    rng = np.random.default_rng(2024)
+    for it in range(60):
+        ds = [_mixed_case(rng, j) for j in range(int(rng.integers(2, 9)) if rng.random() < 0.25 else 1)]
+        opts = dict(closure=str(rng.choice(["off", "on", "auto"])), queue=bool(rng.random() < 0.5),
+                    method=str(rng.choice(["signature", "leader"], p=[0.8, 0.2])))
+        if opts["method"] == "leader":
+            opts.pop("queue")
+            if opts["closure"] == "off" and max(d.n for d in ds) > 1000:
+                opts["closure"] = "auto"  # plain leader rounds on a long chain take n rounds
+        print(f"[case] mixed it={it} {[d.name for d in ds]} {opts}", flush=True)
+        outs, res = dfamin.dfamin_minimize_batch(ctx, ds, opts)
+        for d, o, r in zip(ds, outs, res):
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert r["num_blocks"] == nb and np.array_equal(o, want), (it, d.name, opts)
+            assert r["initial_block"] == want[d.q0]
+
+
 def test_queued_doubling_rounds_agree(ctx):
     """One-letter instances under AUTO with the queue flag: once every
     instance still refining doubles, the device plans the levels and the

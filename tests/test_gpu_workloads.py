@@ -108,7 +108,7 @@ def test_state_limit_rejected_before_staging(ctx):
     print("[case] n = 2^31 - 256 rejected", flush=True)
     d = W.DFA(n=(1 << 31) - 256, k=1, delta=np.zeros(4, np.uint32), accept=np.zeros(4, np.uint8), q0=0,
               name="over the limit")
-    s, keep = dfamin._host_dfa(d)
+    s, keep = dfamin._host_dfa(d, check=False)
     out = np.empty(4, np.uint32)
     res = dfamin.Result()
     rc = dfamin.load().dfamin_minimize(ctx.handle, dfamin.ctypes.byref(s), dfamin._opts(None),
