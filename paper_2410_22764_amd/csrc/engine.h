@@ -84,11 +84,15 @@ class Engine {
  public:
   explicit Engine(Context* ctx) : ctx_(ctx) {}
   ~Engine();
+  // On an error return, the stream has been drained: no work of the call is
+  // left queued on the context's buffers (a later call may use another stream).
   int run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
           std::vector<InstOutcome>& res);
   uint64_t device_bytes() const;
 
  private:
+  int run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+               std::vector<InstOutcome>& res);
   int ensure(DevBuf& b, size_t bytes);
   int ensure_host(HostBuf& b, size_t bytes);
   int build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts, hipStream_t s);

@@ -1206,6 +1206,16 @@ int Engine::minimal_dfa(const dfamin_opts& opts, hipStream_t s, uint32_t nb, uin
 
 int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
                 std::vector<InstOutcome>& res) {
+  const int rc = run_path(in, opts, s, res);
+  // A call that stops early may leave work queued behind its last wait (the
+  // next round's level passes and table clear): let it finish before the
+  // buffers are handed to another call.
+  if (rc != DFAMIN_OK && !ctx_->device_lost) (void)hipStreamSynchronize(s);
+  return rc;
+}
+
+int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+                     std::vector<InstOutcome>& res) {
   in_ = in;
   const size_t I = in_.size();
   res.assign(I, InstOutcome{});
