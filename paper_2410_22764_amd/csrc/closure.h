@@ -28,10 +28,16 @@ struct ClosureSpec {
 // building (out of memory or over the caller's cap): the levels built so far
 // are kept, which is sound because any subset of closure letters preserves
 // the equivalence.
+// Optional: upload(dev, host, bytes) queues a host-to-device copy of the
+// caller's choosing and flags_to_host(dev, bytes) a copy into the
+// host_flags buffer, each returning false on failure; when unset, plain
+// hipMemcpyAsync copies are queued.
 struct ClosureScratch {
   std::function<void*(int, size_t)> ensure;
   std::function<void*(size_t)> host_flags;
   std::function<void*(size_t)> level_storage;
+  std::function<bool(void*, const void*, size_t)> upload;
+  std::function<bool(const void*, size_t)> flags_to_host;
 };
 
 // Builds closure levels (dst[q] = src[src[q]]) for every letter of every

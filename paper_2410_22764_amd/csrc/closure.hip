@@ -87,9 +87,11 @@ int build_closure_levels(std::vector<ClosureSpec>& specs, const ClosureScratch& 
     uint32_t* d_wg = static_cast<uint32_t*>(scratch.ensure(3, (size_t)max_wgs * 4));
     uint32_t* h_flags = static_cast<uint32_t*>(scratch.host_flags(jobs.size() * 4));
     if (!d_jobs || !d_off || !d_flags || !d_wg || !h_flags) return DFAMIN_E_NOMEM;
-    if (hipMemcpyAsync(d_jobs, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        hipMemcpyAsync(d_off, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+    auto up = [&](void* d, const void* h, size_t bytes) {
+      return scratch.upload ? scratch.upload(d, h, bytes)
+                            : hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    };
+    if (!up(d_jobs, jobs.data(), jobs.size() * sizeof(RowJob)) || !up(d_off, joboff.data(), joboff.size() * 4))
       return DFAMIN_E_DEVICE;
     for (uint32_t b = 0; b < batch; ++b) {
       const uint32_t lb = lvl_begin[b], le = lvl_begin[b + 1];
@@ -98,9 +100,10 @@ int build_closure_levels(std::vector<ClosureSpec>& specs, const ClosureScratch& 
     }
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     const auto t1 = now();
-    if (hipMemcpyAsync(h_flags, d_flags, jobs.size() * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        stream_wait(s) != hipSuccess)
-      return DFAMIN_E_DEVICE;
+    const bool copied = scratch.flags_to_host
+                            ? scratch.flags_to_host(d_flags, jobs.size() * 4)
+                            : hipMemcpyAsync(h_flags, d_flags, jobs.size() * 4, hipMemcpyDeviceToHost, s) == hipSuccess;
+    if (!copied || stream_wait(s) != hipSuccess) return DFAMIN_E_DEVICE;
     if (trace)
       std::fprintf(stderr, "[dfamin] closure levels %u..%u: %zu jobs, %zu words, host %.0f us, device wait %.0f us\n",
                    level + 1, level + batch, jobs.size(), words, us(t0, t1), us(t1, now()));

@@ -22,9 +22,13 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Host staging buffer in pinned memory (grow-only).
+// Host staging buffer in pinned memory (grow-only).  dp is the same memory
+// as the device addresses it (set for the engine's buffers, which are
+// page-locked with hipHostMallocCoherent so that kernels may read and write
+// them directly).
 struct HostBuf {
   void* p = nullptr;
+  void* dp = nullptr;
   size_t cap = 0;
   template <class T>
   T* as() const { return static_cast<T*>(p); }
@@ -103,6 +107,21 @@ class Engine {
   int lazy_levels(const std::vector<uint32_t>& which, const dfamin_opts& opts,
                   std::vector<uint32_t>& rest, std::vector<uint8_t>& lazy);
   int queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s);
+  // Host-to-device uploads of a call go through two page-locked arenas: the
+  // bytes are staged at the arena's next free offset and a copy kernel moves
+  // them in stream order.  An arena's space is reused only after a host wait
+  // that every copy out of it precedes: stage_flip() after a signature
+  // round's readback event (the arena used before the previous flip is free
+  // then), stage_idle() after the stream has drained; an arena that runs out
+  // drains the stream and grows.
+  int upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+  void stage_flip() {
+    stage_cur_ ^= 1;
+    stage_[stage_cur_].off = 0;
+  }
+  void stage_idle() { stage_[0].off = stage_[1].off = 0; }
+  // device -> engine host buffer (page-locked, mapped) by a copy kernel
+  int readback(HostBuf& h, const void* src, size_t bytes, hipStream_t s);
   int signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
  public:
   // After run() on one instance: the states reachable from q0 (breadth
@@ -138,7 +157,14 @@ class Engine {
   DevBuf d_visit_, d_bfs_rows_, d_min_delta_, d_min_acc_;
   DevBuf d_lvl_, d_lvl_wg_, d_lvl_flags_;  // level jobs of lazily built closure levels
   DevBuf d_rb_;  // owns d_ctrl_, d_refine_ and d_counts_ (views into it, reset every run)
-  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_desc_, h_rb_, h_lvl_;
+  HostBuf h_ctrl_, h_flags_, h_results_, h_counts_, h_jobs_, h_rb_;
+  struct Stage {
+    HostBuf buf;
+    size_t off = 0;
+  };
+  Stage stage_[2];
+  uint32_t stage_cur_ = 0;
+  std::vector<char> lvl_host_;  // level jobs being assembled
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {
     uint32_t n, ninst, parity;
@@ -153,8 +179,6 @@ class Engine {
   GraphKey graph_key_{};
   hipGraphExec_t graph_exec_ = nullptr;
   hipEvent_t ev_rb_ = nullptr;  // a signature round's readback, waited for by itself
-  hipEvent_t ev_lvl_ = nullptr;  // the last upload of level jobs out of h_lvl_
-  bool lvl_pending_ = false;      // ev_lvl_ recorded and not yet waited for
   // captured queued signature rounds, reused while every pointer and size in
   // the key matches
   static constexpr int kQueueKeyWords = 24;

@@ -117,12 +117,18 @@ int Profiler::copy_stats(dfamin_kernel_stat* out, int cap) const {
   return n;
 }
 
+#define TRY(x)                    \
+  do {                            \
+    int _rc = (x);                \
+    if (_rc != DFAMIN_OK) return _rc; \
+  } while (0)
+#define HIP(x) TRY(check_hip(x))
+
 // ------------------------------------------------------------------ Engine
 Engine::~Engine() {
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
   if (queue_exec_) (void)hipGraphExecDestroy(queue_exec_);
   if (ev_rb_) (void)hipEventDestroy(ev_rb_);
-  if (ev_lvl_) (void)hipEventDestroy(ev_lvl_);
   DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
                     &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
@@ -133,8 +139,8 @@ Engine::~Engine() {
     if (b->p) (void)hipFree(b->p);
   for (DevBuf& b : closure_bufs_)
     if (b.p) (void)hipFree(b.p);
-  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_desc_, &h_rb_, &h_lvl_,
-                   &h_qdbl_};
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_rb_, &h_qdbl_,
+                   &stage_[0].buf, &stage_[1].buf};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -189,23 +195,49 @@ int Engine::ensure_host(HostBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 64;
   if (b.cap >= bytes) return DFAMIN_OK;
   if (b.p) (void)hipHostFree(b.p);
-  b.p = nullptr;
+  b.p = b.dp = nullptr;
   b.cap = 0;
-  size_t want = bytes + bytes / 8 + 64;
-  if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+  size_t want = (bytes + bytes / 8 + 64 + 15) & ~size_t(15);
+  // coherent: the copy kernels read and write it directly, uncached on the
+  // device side, so no device cache can hold a stale copy between calls
+  if (hipHostMalloc(&b.p, want, hipHostMallocCoherent) != hipSuccess) {
     b.p = nullptr;
+    (void)hipGetLastError();
     return DFAMIN_E_NOMEM;
+  }
+  if (hipHostGetDevicePointer(&b.dp, b.p, 0) != hipSuccess || !b.dp) {
+    (void)hipHostFree(b.p);
+    b.p = b.dp = nullptr;
+    return check_hip(hipErrorInvalidValue);
   }
   b.cap = want;
   return DFAMIN_OK;
 }
 
-#define TRY(x)                    \
-  do {                            \
-    int _rc = (x);                \
-    if (_rc != DFAMIN_OK) return _rc; \
-  } while (0)
-#define HIP(x) TRY(check_hip(x))
+int Engine::upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return DFAMIN_OK;
+  Stage& st = stage_[stage_cur_];
+  size_t at = (st.off + 15) & ~size_t(15);
+  if (at + bytes > st.buf.cap) {
+    // every copy staged so far has run once the stream has drained; the
+    // arena then grows to twice what this phase has asked for
+    HIP(stream_wait(s));
+    stage_idle();
+    TRY(ensure_host(st.buf, std::max<size_t>(2 * (at + bytes), size_t(64) << 10)));
+    at = 0;
+  }
+  std::memcpy(st.buf.as<char>() + at, src, bytes);
+  st.off = at + bytes;
+  launch_copy_bytes(dst, static_cast<const char*>(st.buf.dp) + at, bytes, s);
+  return check_hip(hipGetLastError());
+}
+
+int Engine::readback(HostBuf& h, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return DFAMIN_OK;
+  if (h.cap < bytes || !h.dp) return DFAMIN_E_INTERNAL;
+  launch_copy_bytes(h.dp, src, bytes, s);
+  return check_hip(hipGetLastError());
+}
 
 // Rebuild descriptors, row pointers and signature-record offsets from the
 // per-instance row lists and upload them.
@@ -226,9 +258,8 @@ int Engine::upload_layout(hipStream_t s) {
   for (size_t i = 0; i < I; ++i) desc_[i].sig = reinterpret_cast<uint64_t>(d_sig_.p) + 4 * desc_[i].sig;
   TRY(ensure(d_desc_, I * sizeof(InstDesc)));
   TRY(ensure(d_rows_, std::max<size_t>(rows_.size(), 1) * 8));
-  HIP(hipMemcpyAsync(d_desc_.p, desc_.data(), I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
-  if (!rows_.empty())
-    HIP(hipMemcpyAsync(d_rows_.p, rows_.data(), rows_.size() * 8, hipMemcpyHostToDevice, s));
+  TRY(upload(d_desc_.p, desc_.data(), I * sizeof(InstDesc), s));
+  if (!rows_.empty()) TRY(upload(d_rows_.p, rows_.data(), rows_.size() * 8, s));
   return DFAMIN_OK;
 }
 
@@ -257,6 +288,10 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
   };
   scratch.host_flags = [&](size_t bytes) -> void* {
     return ensure_host(h_flags_, bytes) == DFAMIN_OK ? h_flags_.p : nullptr;
+  };
+  scratch.upload = [&](void* d, const void* h, size_t bytes) { return upload(d, h, bytes, s) == DFAMIN_OK; };
+  scratch.flags_to_host = [&](const void* d, size_t bytes) {
+    return readback(h_flags_, d, bytes, s) == DFAMIN_OK;
   };
   scratch.level_storage = [&](size_t bytes) -> void* {
     if (taken + bytes > cap) return nullptr;
@@ -349,16 +384,11 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   uint32_t S = 0;
   for (const LevelTodo& t : todo) S = std::max(S, t.step + 1);
   const size_t bytes = J * (sizeof(RowJob) + 4);
-  // h_lvl_ is page-locked, so its last upload reads it whenever the stream
-  // gets there: wait for that copy before the jobs are rewritten (two calls
-  // can fall in one round, with the round's kernels queued in between)
-  if (lvl_pending_) {
-    HIP(event_wait(ev_lvl_));
-    lvl_pending_ = false;
-  }
-  TRY(ensure_host(h_lvl_, bytes));
+  // assembled here, then staged by upload(): two calls in one round (with
+  // the round's kernels queued in between) never share host memory
+  lvl_host_.resize(bytes);
   TRY(ensure(d_lvl_, bytes));
-  RowJob* hj = h_lvl_.as<RowJob>();
+  RowJob* hj = reinterpret_cast<RowJob*>(lvl_host_.data());
   uint32_t* ho = reinterpret_cast<uint32_t*>(hj + J);
   std::vector<uint32_t> begin(S + 1, 0), wgs(S, 0);
   uint32_t c = 0, maxw = 0;
@@ -386,10 +416,7 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   begin[S] = c;
   TRY(ensure(d_lvl_wg_, (size_t)maxw * 4));
   TRY(ensure(d_lvl_flags_, J * 4));
-  HIP(hipMemcpyAsync(d_lvl_.p, h_lvl_.p, bytes, hipMemcpyHostToDevice, s));
-  if (!ev_lvl_) HIP(hipEventCreateWithFlags(&ev_lvl_, hipEventDisableTiming));
-  HIP(hipEventRecord(ev_lvl_, s));
-  lvl_pending_ = true;
+  TRY(upload(d_lvl_.p, lvl_host_.data(), bytes, s));
   RowJob* dj = d_lvl_.as<RowJob>();
   uint32_t* dof = reinterpret_cast<uint32_t*>(dj + J);
   Profiler& prof = ctx_->prof;
@@ -484,8 +511,9 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
       }
     }
     HIP(hipGetLastError());
-    HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+    TRY(readback(h_rb_, d_rb_.p, sizeof(Ctrl), s));
     HIP(stream_wait(s));
+    stage_idle();
     const Ctrl c = *h_rb_.as<Ctrl>();
     if (c.fault) return DFAMIN_E_INTERNAL;
     executed = c.iterations;
@@ -580,7 +608,6 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   for (size_t i = 0; i < I; ++i) alist[i] = (uint32_t)i;
   TRY(ensure(d_djobs_, 4 * I * 4 + 64));
   TRY(ensure_host(h_jobs_, 4 * I * 4 + 64));
-  TRY(ensure_host(h_desc_, I * sizeof(InstDesc)));
   uint32_t* hj = h_jobs_.as<uint32_t>();
   uint32_t* dj = d_djobs_.as<uint32_t>();
   // job lists already on the device (uploaded again only when they change)
@@ -588,7 +615,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   auto upload_if_changed = [&](std::vector<uint32_t>& last, const uint32_t* h, uint32_t* d, size_t words) {
     if (last.size() == words && std::equal(last.begin(), last.end(), h)) return DFAMIN_OK;
     last.assign(h, h + words);
-    return check_hip(hipMemcpyAsync(d, h, words * 4, hipMemcpyHostToDevice, s));
+    return upload(d, h, words * 4, s);
   };
   // host-side time per phase of the round loop (printed with DFAMIN_TRACE)
   const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
@@ -706,8 +733,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     }
     if (dirty) {
       const auto td = now();
-      std::memcpy(h_desc_.p, desc_.data(), I * sizeof(InstDesc));
-      HIP(hipMemcpyAsync(d_desc_.p, h_desc_.p, I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+      TRY(upload(d_desc_.p, desc_.data(), I * sizeof(InstDesc), s));
       if (trace) {
         t_desc += us(td, now());
         ++n_dirty;
@@ -790,9 +816,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         desc_[i].ebits = 0;  // hash keys from here on
         desc_[i].dsrc = 0;
       }
-      HIP(hipMemcpyAsync(d_qdbl_.p, h_qdbl_.p, bytes, hipMemcpyHostToDevice, s));
-      std::memcpy(h_desc_.p, desc_.data(), I * sizeof(InstDesc));
-      HIP(hipMemcpyAsync(d_desc_.p, h_desc_.p, I * sizeof(InstDesc), hipMemcpyHostToDevice, s));
+      TRY(upload(d_qdbl_.p, h_qdbl_.p, bytes, s));
+      TRY(upload(d_desc_.p, desc_.data(), I * sizeof(InstDesc), s));
       uint64_t* dmj = d_qdbl_.as<uint64_t>();
       uint32_t* d32 = reinterpret_cast<uint32_t*>(dmj + T);
       dq.mj = dmj;
@@ -821,7 +846,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       if (queue_dbl) {
         // levels built and read on the device
         const uint32_t T = dq.count;
-        HIP(hipMemcpyAsync(h_qdbl_.p, d_qdbl_.p, 8ull * T + 36ull * T, hipMemcpyDeviceToHost, s));
+        TRY(readback(h_qdbl_, d_qdbl_.p, 8ull * T + 36ull * T, s));
         HIP(stream_wait(s));
         const uint32_t* h32 = reinterpret_cast<const uint32_t*>(h_qdbl_.as<uint64_t>() + T);
         for (uint32_t t = 0; t < T; ++t) {
@@ -933,7 +958,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     }
     HIP(hipGetLastError());
     // one copy: control block, refine counters, and the counts just scanned
-    HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl) + 4 * I + 4 * (size_t)ns, hipMemcpyDeviceToHost, s));
+    TRY(readback(h_rb_, d_rb_.p, sizeof(Ctrl) + 4 * I + 4 * (size_t)ns, s));
     // Work of the next round that needs none of this round's results is
     // queued behind the copy and runs while the host waits and plans: the
     // next level of each doubling instance (j grows by this round's step; if
@@ -969,6 +994,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     const auto tp2 = now();
     t_issue += us(tp1, tp2);
     HIP(overlap ? event_wait(ev_rb_) : stream_wait(s));
+    stage_flip();  // every upload of the previous round has run
     const auto tp3 = now();
     t_wait += us(tp2, tp3);
     prof.collect();
@@ -1050,8 +1076,9 @@ int Engine::leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStrea
   };
   auto read_ctrl = [&](Ctrl& c) -> int {
     HIP(hipGetLastError());
-    HIP(hipMemcpyAsync(h_rb_.p, d_rb_.p, sizeof(Ctrl) + 4 * I, hipMemcpyDeviceToHost, s));
+    TRY(readback(h_rb_, d_rb_.p, sizeof(Ctrl) + 4 * I, s));
     HIP(stream_wait(s));
+    stage_idle();
     prof.collect();
     c = *h_rb_.as<Ctrl>();
     if (c.fault) return DFAMIN_E_INTERNAL;
@@ -1227,7 +1254,15 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   if (N >= kMaxStates) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
   N_ = N;
   closure_cursor_ = 0;
+  // the previous call ended with its stream drained (run() drains on errors)
+  stage_idle();
+  stage_cur_ = 0;
   Profiler& prof = ctx_->prof;
+  // host time per phase of the call (printed with DFAMIN_TRACE)
+  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto us = [](auto a, auto b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
+  const auto t_start = now();
 
   // ---- 1. validation + identity letters: one row job per (instance, letter)
   std::vector<RowJob> jobs;
@@ -1250,8 +1285,8 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   TRY(ensure(d_flags_, jobs.size() * 4));
   TRY(ensure(d_wgflags_, (size_t)wgs * 4));
   TRY(ensure_host(h_flags_, jobs.size() * 4));
-  HIP(hipMemcpyAsync(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, s));
-  HIP(hipMemcpyAsync(d_joboff_.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, s));
+  TRY(upload(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), s));
+  TRY(upload(d_joboff_.p, joboff.data(), joboff.size() * 4, s));
   HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
   {
     double bytes = 0;
@@ -1262,8 +1297,9 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     prof.end(s);
     HIP(hipGetLastError());
   }
-  HIP(hipMemcpyAsync(h_flags_.p, d_flags_.p, jobs.size() * 4, hipMemcpyDeviceToHost, s));
+  TRY(readback(h_flags_, d_flags_.p, jobs.size() * 4, s));
   HIP(stream_wait(s));
+  stage_idle();
   prof.collect();
   bool any_bad = false;
   nonid_.assign(I, {});
@@ -1281,6 +1317,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     }
   }
   if (any_bad) return DFAMIN_E_BAD_DFA;
+  const auto t_valid = now();
 
   // ---- 2. descriptors and signature letters
   desc_.assign(I, InstDesc{});
@@ -1346,7 +1383,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     inst_off[i] = init_wgs;
     init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
   }
-  HIP(hipMemcpyAsync(d_inst_off_.p, inst_off.data(), I * 4, hipMemcpyHostToDevice, s));
+  TRY(upload(d_inst_off_.p, inst_off.data(), I * 4, s));
   TRY(ensure(d_part_, (size_t)init_wgs * 8));
   HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
@@ -1374,6 +1411,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   HIP(hipGetLastError());
 
   // ---- 5. rounds
+  const auto t_setup = now();
   {
     const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
     TRY(opts.method == DFAMIN_METHOD_LEADER ? leader_rounds(opts, max_rounds, s)
@@ -1381,6 +1419,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   }
 
   // ---- 6. canonical numbering and emission
+  const auto t_rounds = now();
   const int fitems = scan_items_for(N);
   const uint32_t ntilesN = scan_tiles(N, fitems);
   launch_prep_scan(d_status_.as<unsigned long long>(), ntilesN, d_ctrl_.as<Ctrl>(), s);
@@ -1395,11 +1434,16 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   launch_results((uint32_t)I, d_desc_.as<InstDesc>(), d_rank_.as<uint32_t>(),
                  d_refine_.as<uint32_t>(), d_results_.as<ResultDev>(), s);
   HIP(hipGetLastError());
-  HIP(hipMemcpyAsync(h_results_.p, d_results_.p, I * sizeof(ResultDev), hipMemcpyDeviceToHost, s));
-  HIP(hipMemcpyAsync(h_ctrl_.p, d_ctrl_.p, sizeof(Ctrl), hipMemcpyDeviceToHost, s));
+  TRY(readback(h_results_, d_results_.p, I * sizeof(ResultDev), s));
+  TRY(readback(h_ctrl_, d_ctrl_.p, sizeof(Ctrl), s));
   HIP(stream_wait(s));
   prof.collect();
   if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
+  if (trace)
+    std::fprintf(stderr,
+                 "[dfamin] call of %zu instances, host us: validation %.0f, setup %.0f, rounds %.0f, "
+                 "numbering %.0f\n",
+                 I, us(t_start, t_valid), us(t_valid, t_setup), us(t_setup, t_rounds), us(t_rounds, now()));
   const ResultDev* r = h_results_.as<ResultDev>();
   for (size_t i = 0; i < I; ++i) {
     res[i].num_blocks = r[i].num_blocks;

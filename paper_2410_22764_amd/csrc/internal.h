@@ -211,6 +211,13 @@ void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_c
 void launch_queue_start(Ctrl* ctrl, uint32_t m, uint64_t salt, hipStream_t s);
 // *p = v, in stream order
 void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s);
+// Copies `bytes` from src to dst as a kernel on the stream (16-byte units
+// where both addresses and the size allow, else 4-byte or 1-byte units).  Either side may be page-locked host memory
+// mapped into the device's address space; stores reach memory before the
+// kernel ends, so a host wait on a later event sees them.  Between two
+// kernels such a copy costs a few microseconds, where a copy-engine transfer
+// of 32 KB or more adds about 15 us of hand-off in each direction.
+void launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 // Queued rounds of instances refining by doubling (one closure level per
 // round, 2^l <= j+1): per listed instance t (instance list[t]) the device
 // keeps j (mj), the levels built and the highest level read.  Before a

@@ -726,6 +726,15 @@ __global__ void k_store_u64(uint64_t* __restrict__ p, uint64_t v) {
   if (threadIdx.x == 0) *p = v;
 }
 
+// Stream-ordered copy of `units` elements (see launch_copy_bytes).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_units(T* __restrict__ dst, const T* __restrict__ src,
+                                                       uint64_t units) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < units; i += stride) dst[i] = src[i];
+  __threadfence_system();
+}
+
 __global__ __launch_bounds__(kBlock) void k_queue_plan(QueueDbl q, InstDesc* __restrict__ desc,
                                                        const Ctrl* __restrict__ ctrl) {
   const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
@@ -1326,6 +1335,23 @@ void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s) {
 
 void launch_round_step(Ctrl* ctrl, hipStream_t s) {
   hipLaunchKernelGGL(k_round_step, dim3(1), dim3(64), 0, s, ctrl);
+}
+
+void launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src) | (uintptr_t)bytes;
+  const uint32_t unit = (a & 15u) == 0 ? 16u : ((a & 3u) == 0 ? 4u : 1u);
+  const uint64_t units = bytes / unit;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>((units + kBlock - 1) / kBlock, 128);
+  if (unit == 16)
+    hipLaunchKernelGGL(k_copy_units<uint4>, dim3(grid), dim3(kBlock), 0, s, static_cast<uint4*>(dst),
+                       static_cast<const uint4*>(src), units);
+  else if (unit == 4)
+    hipLaunchKernelGGL(k_copy_units<uint32_t>, dim3(grid), dim3(kBlock), 0, s, static_cast<uint32_t*>(dst),
+                       static_cast<const uint32_t*>(src), units);
+  else
+    hipLaunchKernelGGL(k_copy_units<uint8_t>, dim3(grid), dim3(kBlock), 0, s, static_cast<uint8_t*>(dst),
+                       static_cast<const uint8_t*>(src), units);
 }
 
 namespace {
