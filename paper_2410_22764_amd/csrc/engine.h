@@ -165,6 +165,9 @@ class Engine {
   Stage stage_[2];
   uint32_t stage_cur_ = 0;
   std::vector<char> lvl_host_;  // level jobs being assembled
+  std::vector<RowJob> vjobs_;    // validation jobs of a call
+  std::vector<uint32_t> vjoboff_;
+  std::vector<uint8_t> lazy_;    // per instance: levels built as the doubling rounds read them
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {
     uint32_t n, ninst, parity;

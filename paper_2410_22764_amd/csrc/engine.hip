@@ -572,7 +572,9 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   // On every way out the rows are cut to the levels read, all of them built,
   // which is what later readers of the closure rows (the reachability
   // search) may follow and what the results report.
-  std::vector<uint8_t> lazy(I, 0);
+  std::vector<uint8_t> lazy = lazy_;  // planned by run() before the layout went up
+  lazy.resize(I, 0);
+  for (size_t i = 0; i < I; ++i) dbl[i] = lazy[i];
   std::vector<uint32_t> built(I, 0), used(I, 0);
   std::vector<LevelTodo> todo;
   uint64_t spec_clear = 0;  // table slots cleared ahead for the coming round
@@ -626,24 +628,6 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   auto tp0 = now();
   while (m > 0) {
     tp0 = now();
-    if (any_auto && rounds == 0) {
-      // Unary instances refine by doubling from the first round: a doubling
-      // round costs what a plain one does (one gathered letter) plus one
-      // level pass, and after r rounds it holds P_(2^r - 1) instead of P_r.
-      // Those whose level storage does not fit stay plain for now.
-      // (a round redone after a hash collision keeps the storage and the
-      // levels already built for it)
-      std::vector<uint32_t> uni, rest;
-      for (uint32_t i : alist)
-        if (in_[i].closure == DFAMIN_CLOSURE_AUTO && nonid_[i].size() == 1 && !has_closure_[i])
-          uni.push_back(i);
-      if (!uni.empty()) {
-        TRY(lazy_levels(uni, opts, rest, lazy));
-        for (uint32_t i : uni) dbl[i] = lazy[i];
-        TRY(upload_layout(s));
-      }
-      if (trace) t_closure += us(tp0, now());
-    }
     if (any_auto && rounds == auto_rounds) {
       // other instances still refining after auto_rounds rounds get the closure
       std::vector<uint32_t> which;
@@ -758,6 +742,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
 
     const auto tp1 = now();
     t_plan += us(tp0, tp1);
+    if (trace && rounds == 0)
+      std::fprintf(stderr, "[dfamin] round 1 planned in %.0f us (descriptors %.0f us)\n", us(tp0, tp1), t_desc);
     // Signature tile: forced, cached for this size class, or tuned now by
     // running every variant once on a freshly cleared table (the last run's
     // table and slot ids are as valid as any other's).
@@ -1265,21 +1251,27 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   const auto t_start = now();
 
   // ---- 1. validation + identity letters: one row job per (instance, letter)
-  std::vector<RowJob> jobs;
-  std::vector<uint32_t> joboff, job_inst;
+  // (the job vectors are members, so a call of the same shape allocates nothing)
+  size_t njobs = 0;
+  for (auto& x : in_) njobs += x.k;
+  std::vector<RowJob>& jobs = vjobs_;
+  std::vector<uint32_t>& joboff = vjoboff_;
+  jobs.resize(njobs);
+  joboff.resize(njobs);
   uint32_t wgs = 0;
-  for (size_t i = 0; i < I; ++i)
-    for (uint32_t a = 0; a < in_[i].k; ++a) {
-      RowJob J;
-      J.src = reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n;
-      J.dst = 0;
-      J.n = in_[i].n;
-      J.flag_idx = (uint32_t)jobs.size();
-      joboff.push_back(wgs);
-      wgs += (J.n + kLongTile - 1) / kLongTile;
-      jobs.push_back(J);
-      job_inst.push_back((uint32_t)i);
-    }
+  {
+    size_t j = 0;
+    for (size_t i = 0; i < I; ++i)
+      for (uint32_t a = 0; a < in_[i].k; ++a, ++j) {
+        RowJob& J = jobs[j];
+        J.src = reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n;
+        J.dst = 0;
+        J.n = in_[i].n;
+        J.flag_idx = (uint32_t)j;
+        joboff[j] = wgs;
+        wgs += (J.n + kLongTile - 1) / kLongTile;
+      }
+  }
   TRY(ensure(d_jobs_, jobs.size() * sizeof(RowJob)));
   TRY(ensure(d_joboff_, joboff.size() * 4));
   TRY(ensure(d_flags_, jobs.size() * 4));
@@ -1297,23 +1289,29 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     prof.end(s);
     HIP(hipGetLastError());
   }
+  const auto t_issue = now();
   TRY(readback(h_flags_, d_flags_.p, jobs.size() * 4, s));
   HIP(stream_wait(s));
   stage_idle();
+  const auto t_vwait = now();
   prof.collect();
   bool any_bad = false;
-  nonid_.assign(I, {});
+  nonid_.resize(I);
   {
-    const uint32_t* f = h_flags_.as<uint32_t>();
-    for (size_t j = 0; j < jobs.size(); ++j)
-      if (f[j] & kFlagBad) { res[job_inst[j]].status = DFAMIN_E_BAD_DFA; any_bad = true; }
     // jobs are ordered (instance, letter): job j of instance i is letter j - first(i)
+    const uint32_t* f = h_flags_.as<uint32_t>();
     size_t j = 0;
     for (size_t i = 0; i < I; ++i) {
-      std::vector<uint32_t> letters;
-      for (uint32_t a = 0; a < in_[i].k; ++a, ++j)
-        if (f[j] & kFlagNonId) letters.push_back(a);
-      nonid_[i] = letters;
+      std::vector<uint32_t>& letters = nonid_[i];
+      letters.clear();
+      for (uint32_t a = 0; a < in_[i].k; ++a, ++j) {
+        const uint32_t fl = f[j];
+        if (fl & kFlagBad) {
+          res[i].status = DFAMIN_E_BAD_DFA;
+          any_bad = true;
+        }
+        if (fl & kFlagNonId) letters.push_back(a);
+      }
     }
   }
   if (any_bad) return DFAMIN_E_BAD_DFA;
@@ -1321,7 +1319,8 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
 
   // ---- 2. descriptors and signature letters
   desc_.assign(I, InstDesc{});
-  inst_rows_.assign(I, {});
+  inst_rows_.resize(I);
+  for (auto& r : inst_rows_) r.clear();
   levels_.assign(I, 0);
   has_closure_.assign(I, 0);
   {
@@ -1339,12 +1338,14 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
         inst_rows_[i].push_back(reinterpret_cast<uint64_t>(in_[i].delta) + 4ull * a * in_[i].n);
     }
   }
+  const auto t_desc = now();
   {
     std::vector<uint32_t> on;
     for (size_t i = 0; i < I; ++i)
       if (in_[i].closure == DFAMIN_CLOSURE_ON) on.push_back((uint32_t)i);
     if (!on.empty()) TRY(build_closure(on, opts, s));
   }
+  const auto t_closure = now();
 
   // ---- 3. buffers sized for N
   TRY(ensure(d_block_, N * 4));
@@ -1375,7 +1376,20 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   TRY(ensure_host(h_ctrl_, sizeof(Ctrl)));
   TRY(ensure_host(h_results_, I * sizeof(ResultDev)));
   TRY(ensure_host(h_counts_, I * 4));
+  // One-letter AUTO instances refine by doubling from the first signature
+  // round (their levels are built as the rounds read them); planning their
+  // level storage here lets the layout go up once.  Those whose storage does
+  // not fit stay plain until the AUTO closure is decided.
+  lazy_.assign(I, 0);
+  if (opts.method == DFAMIN_METHOD_SIGNATURE) {
+    std::vector<uint32_t> uni, rest;
+    for (size_t i = 0; i < I; ++i)
+      if (in_[i].closure == DFAMIN_CLOSURE_AUTO && nonid_[i].size() == 1) uni.push_back((uint32_t)i);
+    if (!uni.empty()) TRY(lazy_levels(uni, opts, rest, lazy_));
+  }
+  const auto t_bufs = now();
   TRY(upload_layout(s));
+  const auto t_layout = now();
   // workgroup offsets of the per-instance init jobs
   std::vector<uint32_t> inst_off(I);
   uint32_t init_wgs = 0;
@@ -1441,9 +1455,12 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
   if (trace)
     std::fprintf(stderr,
-                 "[dfamin] call of %zu instances, host us: validation %.0f, setup %.0f, rounds %.0f, "
-                 "numbering %.0f\n",
-                 I, us(t_start, t_valid), us(t_valid, t_setup), us(t_setup, t_rounds), us(t_rounds, now()));
+                 "[dfamin] call of %zu instances, host us: validation %.0f (issue %.0f, wait %.0f, flags %.0f), "
+                 "setup %.0f (descriptors %.0f, closure %.0f, buffers %.0f, layout %.0f, init %.0f), "
+                 "rounds %.0f, numbering %.0f\n",
+                 I, us(t_start, t_valid), us(t_start, t_issue), us(t_issue, t_vwait), us(t_vwait, t_valid),
+                 us(t_valid, t_setup), us(t_valid, t_desc), us(t_desc, t_closure), us(t_closure, t_bufs),
+                 us(t_bufs, t_layout), us(t_layout, t_setup), us(t_setup, t_rounds), us(t_rounds, now()));
   const ResultDev* r = h_results_.as<ResultDev>();
   for (size_t i = 0; i < I; ++i) {
     res[i].num_blocks = r[i].num_blocks;
