@@ -168,6 +168,8 @@ class Engine {
   std::vector<RowJob> vjobs_;    // validation jobs of a call
   std::vector<uint32_t> vjoboff_;
   std::vector<uint8_t> lazy_;    // per instance: levels built as the doubling rounds read them
+  uint32_t cas_bits_ = 2;        // signature gmode bits 1-2 (table insertion order) of the round
+  int cas_forced_ = -1;          // testing override of cas_bits_
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {
     uint32_t n, ninst, parity;

@@ -458,7 +458,7 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
     launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 1);
     launch_signature(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                      d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, 4, d_table_.as<Slot>(), tbits,
-                     d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(), variant, s, 1);
+                     d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(), variant, s, 1 | (int)cas_bits_);
     launch_resolve(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                    d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(), d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(),
                    d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
@@ -482,7 +482,7 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
         reinterpret_cast<uint64_t>(d_keep_.p), reinterpret_cast<uint64_t>(d_changed_.p),
         reinterpret_cast<uint64_t>(d_refine_.p), reinterpret_cast<uint64_t>(d_ctrl_.p),
         reinterpret_cast<uint64_t>(d_status_.p), reinterpret_cast<uint64_t>(d_dense_.p),
-        reinterpret_cast<uint64_t>(s), 1, dq ? reinterpret_cast<uint64_t>(dq->mj) : 0,
+        reinterpret_cast<uint64_t>(s), 1u | cas_bits_, dq ? reinterpret_cast<uint64_t>(dq->mj) : 0,
         dq ? ((uint64_t)dq->count << 32 | dq->wgs) : 0};
     if (queue_exec_ && queue_key_ == key) {
       exec = queue_exec_;
@@ -733,6 +733,28 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     }
     groups = std::min<uint64_t>(groups, m);
     const uint32_t tbits = std::max<uint32_t>(9, ceil_log2_u64(2 * groups));
+    // Table insertion order (table_insert).  A hash-mode group is mostly
+    // new to the table: a CAS on the home slot claims it without a read
+    // first (C1's third round: 2.05 -> 1.85 ms).  Exact keys do the same
+    // unless few global groups take inserts from many workgroups: each
+    // workgroup tile (at most 1,024 states) inserts at most one local group
+    // per global group, and above 64 inserts per global group on average the
+    // read first lets most joins skip the atomic on a hot slot (C1's first
+    // round, 32 groups: 0.38 ms, against 0.62 ms with the CAS; batch_mixed's
+    // first round, about 2M groups over 4,096 instances: 1.01 ms with the
+    // CAS, against 1.23 ms).
+    {
+      uint64_t ex_groups = 0, ex_inserts = 0;
+      for (uint32_t i : alist) {
+        if (!desc_[i].ebits) continue;
+        const uint64_t width = (desc_[i].kp + 1ull) * desc_[i].ebits;
+        const uint64_t gi = width < 32 ? std::min<uint64_t>(in_[i].n, 1ull << width) : in_[i].n;
+        ex_groups += gi;
+        ex_inserts += ((in_[i].n + 1023ull) / 1024ull) * std::min<uint64_t>(1024, gi);
+      }
+      cas_bits_ = 2u | (ex_inserts <= 64 * ex_groups ? 4u : 0u);
+      if (cas_forced_ >= 0) cas_bits_ = (uint32_t)cas_forced_;
+    }
     const uint64_t tsize = 1ull << tbits;
     TRY(ensure(d_table_, tsize * sizeof(Slot)));
     const int citems = scan_items_for(m);
@@ -864,7 +886,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
           launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                            d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
                            d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
-                           v, s);
+                           v, s, (int)cas_bits_);
           HIP(hipEventRecord(tu.ev[2 * v + 1], s));
         }
         HIP(hipGetLastError());
@@ -894,7 +916,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                        d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
                        d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
-                       variant, s);
+                       variant, s, (int)cas_bits_);
       prof.end(s);
     }
     prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
@@ -1402,6 +1424,10 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
+  // testing: force the table insertion order of every signature round
+  // (DFAMIN_CAS_FIRST=b: bit 0 hash-mode states, bit 1 exact-key states)
+  cas_forced_ = -1;
+  if (const char* e = std::getenv("DFAMIN_CAS_FIRST")) cas_forced_ = (std::atoi(e) & 3) << 1;
   if (const char* e = std::getenv("DFAMIN_HASH_BITS")) {
     // testing: weak signature hashes (see Ctrl::hash_mask)
     const int bits = std::atoi(e);

@@ -174,7 +174,9 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
 // is then an upper bound that only sizes the grid.
 void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode = 0);
 // dense / dense_width: dense block numbers (exact-key rounds that read them),
-// stored dense_width (1, 2 or 4) bytes per state.
+// stored dense_width (1, 2 or 4) bytes per state.  gmode bit 0 as above;
+// bits 1 and 2: hash-mode / exact-key states insert their group with a CAS
+// on the home slot before reading it (table_insert).
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,

@@ -400,7 +400,10 @@ __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table
 }
 
 // Insert a local group (least member g, a global state id, `shared` if it
-// already has two members) into the global table; returns the slot.  A slot
+// already has two members) into the global table; returns the slot.  The
+// home slot is read first (a join that changes nothing then costs no
+// atomic), or, with cas_first, claimed by a CAS straight away (a new group
+// then costs one atomic and no read).  A slot
 // belongs to one instance: its least member lies in [lo, hi), the inserting
 // instance's state range, or the slot holds another instance's key and the
 // probe moves on.  So exact keys (the same small numbers in every instance)
@@ -410,12 +413,18 @@ __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table
 // instance, shared bit only set).
 __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint64_t mask, uint64_t h,
                                                  uint32_t frag, uint32_t g, bool shared, uint32_t lo,
-                                                 uint32_t hi, Ctrl* __restrict__ ctrl) {
+                                                 uint32_t hi, bool cas_first, Ctrl* __restrict__ ctrl) {
   uint64_t p = h & mask;
   const unsigned long long mine =
       ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)g;
   for (uint64_t probes = 0; probes <= mask; ++probes) {
-    unsigned long long cur = table[p];
+    unsigned long long cur;
+    if (cas_first) {
+      cur = atomicCAS(&table[p], 0ull, mine);
+      if (cur == 0ull) return (uint32_t)p;
+    } else {
+      cur = table[p];
+    }
     while (true) {
       if (cur == 0ull) {
         const unsigned long long prev = atomicCAS(&table[p], 0ull, mine);
@@ -452,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     const uint32_t* __restrict__ block, const void* __restrict__ dense,
     Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
     Ctrl* __restrict__ ctrl, uint32_t gmode) {
-  if (gmode) {  // a queued round: live count and salt from the control block
+  if (gmode & 1u) {  // a queued round: live count and salt from the control block
     if (ctrl->stop) return;
     m = ctrl->m_cur;
     salt = ctrl->salt;
@@ -469,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
   __syncthreads();
   uint64_t h[SI];
   uint32_t frag[SI], lp[SI], jj[SI], gg[SI], glo[SI], ghi[SI];
-  bool valid[SI];
+  bool valid[SI], cfirst[SI];
 #pragma unroll
   for (int e = 0; e < SI; ++e) {
     const uint32_t j = blockIdx.x * kTile + e * kBlock + threadIdx.x;
@@ -481,6 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     h[e] = 0;
     frag[e] = 0;
     lp[e] = 0;
+    cfirst[e] = false;
     if (!valid[e]) continue;
     const uint32_t g = act[j];
     gg[e] = g;
@@ -491,6 +501,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     ghi[e] = D.state_off + D.n;
     const uint32_t kp = D.kp;
     const uint64_t* __restrict__ R = rows + D.rows_off;
+    cfirst[e] = (gmode & (D.ebits ? 4u : 2u)) != 0u;
     unsigned long long lk;  // local grouping key (exact key + 1, or the hash)
     if (D.ebits) {
       // exact key: own dense number, then one per letter, ebits each
@@ -565,7 +576,8 @@ __global__ __launch_bounds__(kBlock) void k_signature(
 #pragma unroll
   for (int e = 0; e < SI; ++e) {
     if (valid[e] && lmin[lp[e]] == gg[e])
-      lslot[lp[e]] = table_insert(table, mask, h[e], frag[e], gg[e], lcnt[lp[e]] > 1u, glo[e], ghi[e], ctrl);
+      lslot[lp[e]] =
+          table_insert(table, mask, h[e], frag[e], gg[e], lcnt[lp[e]] > 1u, glo[e], ghi[e], cfirst[e], ctrl);
   }
   __syncthreads();
 #pragma unroll

@@ -859,7 +859,8 @@ struct Serving::Impl {
         launch_signature(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<InstDesc*>(d_desc),
                          static_cast<uint64_t*>(d_rows), static_cast<uint32_t*>(d_block), nullptr, 4,
                          static_cast<Slot*>(d_table), tbits, static_cast<uint32_t*>(d_slot_of), salt,
-                         static_cast<Ctrl*>(d_ctrl), kSigDefaultVariant, stream);
+                         static_cast<Ctrl*>(d_ctrl), kSigDefaultVariant, stream,
+                         2 /* hash-mode groups claim their slot by CAS first */);
         launch_resolve(true, act, m, static_cast<uint32_t*>(d_inst_of), static_cast<InstDesc*>(d_desc),
                        static_cast<Slot*>(d_table), static_cast<uint32_t*>(d_slot_of),
                        static_cast<uint32_t*>(d_block), static_cast<uint32_t*>(d_nb),
