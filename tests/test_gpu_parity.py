@@ -403,6 +403,28 @@ def test_first_round_redo_keeps_doubling_levels(ctx, monkeypatch):
     assert finished >= 3
 
 
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_table_insertion_orders_agree(ctx, monkeypatch, order):
+    """A signature group joins the global table either by reading its home
+    slot first or by a CAS straight away, chosen per round and key mode.
+    Forcing each combination (a testing knob: bit 0 hash-mode keys, bit 1
+    exact keys) changes no partition and no round count, alone or batched."""
+    from paper_2410_22764_amd import dfamin
+    monkeypatch.setenv("DFAMIN_CAS_FIRST", str(order))
+    cases = [W.random_dfa(20000, 3, 7), W.permuted_chain_dfa(3000, 1, 3), W.random_dfa(5000, 1, 2),
+             W.fib_dfa(12)]
+    for d in cases:
+        want, nb, rounds = oracle.moore(d.n, d.k, d.delta, d.accept)
+        print(f"[case] insertion order {order} {d.name}", flush=True)
+        out, r = dfamin.dfamin_minimize(ctx, d, "off")
+        assert r["num_blocks"] == nb and np.array_equal(out, want) and r["refine_rounds"] == rounds, d.name
+        out, r = dfamin.dfamin_minimize(ctx, d, "auto")
+        assert r["num_blocks"] == nb and np.array_equal(out, want), d.name
+    outs, res = dfamin.dfamin_minimize_batch(ctx, cases, "auto")
+    for d, o, r in zip(cases, outs, res):
+        assert np.array_equal(o, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]), d.name
+
+
 def _mixed_case(rng, i):
     kind = rng.choice(["random", "chain", "pchain", "fib", "coarse", "cycle"])
     n = int(2 ** rng.uniform(0, 12)) + 1
