@@ -176,20 +176,32 @@ __device__ __forceinline__ uint32_t tile_rank(const TileScanLds<ITEMS>& t, int e
   return t.off[w] + (uint32_t)__popcll(t.mask[w] & lt);
 }
 
+// Workgroups are dispatched to the chip's 8 XCDs in turn (workgroup b to
+// XCD b mod 8), and each XCD has its own L2.  This bijection of [0, G) gives
+// each XCD one contiguous range of logical workgroup ids, so the rows that
+// neighbouring tiles gather from (one instance's block ids, one closure row)
+// are pulled into one L2 instead of eight.  Any order is correct; only
+// locality depends on it.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t G) {
+  const uint32_t x = b % kXcds, l = b / kXcds, q = G / kXcds, r = G % kXcds;
+  return x < r ? x * (q + 1) + l : r * (q + 1) + (x - r) * q + l;
+}
+
 // Workgroup -> job by binary search over the exclusive workgroup prefix.
 __device__ __forceinline__ uint32_t find_job(const uint32_t* job_wg_off, uint32_t njobs,
-                                             uint32_t* s_job) {
-  // Largest j with job_wg_off[j] <= blockIdx.x (offsets strictly increase,
+                                             uint32_t* s_job, uint32_t wg) {
+  // Largest j with job_wg_off[j] <= wg (offsets strictly increase,
   // job_wg_off[0] = 0).  The first wave searches 64-ary: each step loads 64
   // evenly spaced offsets of [lo, hi) at once and keeps the span after the
-  // last one not above blockIdx.x, so 4,096 jobs take two dependent loads.
+  // last one not above wg, so 4,096 jobs take two dependent loads.
   if (threadIdx.x < 64) {
     const uint32_t lane = threadIdx.x;
     uint32_t lo = 0, hi = njobs;
     while (hi - lo > 1) {
       const uint32_t step = (hi - lo + 63) / 64;
       const uint32_t idx = lo + lane * step;
-      const bool ok = idx < hi && job_wg_off[idx] <= blockIdx.x;
+      const bool ok = idx < hi && job_wg_off[idx] <= wg;
       const unsigned long long mask = __ballot(ok);  // a prefix of lanes; lane 0 always
       const uint32_t last = 63u - (uint32_t)__builtin_clzll(mask);
       lo += last * step;
@@ -199,6 +211,10 @@ __device__ __forceinline__ uint32_t find_job(const uint32_t* job_wg_off, uint32_
   }
   __syncthreads();
   return *s_job;
+}
+__device__ __forceinline__ uint32_t find_job(const uint32_t* job_wg_off, uint32_t njobs,
+                                             uint32_t* s_job) {
+  return find_job(job_wg_off, njobs, s_job, blockIdx.x);
 }
 
 // OR of one flag word per thread into a single word per workgroup.
@@ -244,11 +260,12 @@ __global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restri
                                                           uint32_t njobs,
                                                           uint32_t* __restrict__ wg_flags) {
   __shared__ uint32_t s_job, s_or;
-  const uint32_t j = find_job(job_wg_off, njobs, &s_job);
+  const uint32_t wg = xcd_contiguous(blockIdx.x, gridDim.x);  // a row's tiles share one L2
+  const uint32_t j = find_job(job_wg_off, njobs, &s_job, wg);
   const RowJob J = jobs[j];
   const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(J.src);
   uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(J.dst);
-  const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
+  const uint32_t base = (wg - job_wg_off[j]) * kRowTile;
   constexpr int kItems = kRowTile / kBlock;
   uint32_t s1[kItems];
 #pragma unroll
@@ -268,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restri
     }
   }
   const uint32_t w = block_or(bits, &s_or);
-  if (threadIdx.x == 0) wg_flags[blockIdx.x] = w;
+  if (threadIdx.x == 0) wg_flags[wg] = w;
 }
 
 // flags[j] = OR of the workgroup flags of job j (one workgroup per job).
@@ -479,9 +496,12 @@ __global__ __launch_bounds__(kBlock) void k_signature(
   uint64_t h[SI];
   uint32_t frag[SI], lp[SI], jj[SI], gg[SI], glo[SI], ghi[SI];
   bool valid[SI], cfirst[SI];
+  // batched: neighbouring tiles (mostly one instance's states) on one XCD
+  // (one instance gathers from its whole block array: no locality to keep)
+  const uint32_t wg = BATCH ? xcd_contiguous(blockIdx.x, gridDim.x) : blockIdx.x;
 #pragma unroll
   for (int e = 0; e < SI; ++e) {
-    const uint32_t j = blockIdx.x * kTile + e * kBlock + threadIdx.x;
+    const uint32_t j = wg * kTile + e * kBlock + threadIdx.x;
     jj[e] = j;
     gg[e] = 0;
     glo[e] = 0;
@@ -766,13 +786,14 @@ __global__ __launch_bounds__(kBlock) void k_queue_levels(QueueDbl q, const uint6
                                                          const Ctrl* __restrict__ ctrl) {
   __shared__ uint32_t s_job;
   if (ctrl->stop) return;
-  const uint32_t t = find_job(q.wgoff, q.count, &s_job);
+  const uint32_t wg = xcd_contiguous(blockIdx.x, gridDim.x);
+  const uint32_t t = find_job(q.wgoff, q.count, &s_job, wg);
   const uint32_t lvl = q.need[t];
   if (!lvl) return;
   const uint32_t* __restrict__ src = reinterpret_cast<const uint32_t*>(rows[q.rbase[t] + lvl - 1]);
   uint32_t* __restrict__ dst = reinterpret_cast<uint32_t*>(rows[q.rbase[t] + lvl]);
   const uint32_t n = q.n[t];
-  const uint32_t base = (blockIdx.x - q.wgoff[t]) * kRowTile;
+  const uint32_t base = (wg - q.wgoff[t]) * kRowTile;
 #pragma unroll
   for (int e = 0; e < kRowTile / kBlock; ++e) {
     const uint32_t x = base + e * kBlock + threadIdx.x;
