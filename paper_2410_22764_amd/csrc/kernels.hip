@@ -240,13 +240,30 @@ __global__ __launch_bounds__(kBlock) void k_row_check(const RowJob* __restrict__
   const uint32_t* __restrict__ row = reinterpret_cast<const uint32_t*>(J.src);
   const uint32_t base = (blockIdx.x - job_wg_off[j]) * kLongTile;
   uint32_t bits = 0;
+  auto check = [&](uint32_t v, uint32_t q) {
+    if (v >= J.n) bits |= kFlagBad;
+    if (v != q) bits |= kFlagNonId;
+  };
+  // 16-byte loads over the row from its first 16-byte boundary on: the
+  // `lead` (0-3) entries before it are checked one by one by the first
+  // workgroup, and each workgroup's tile is shifted by lead (the tiles still
+  // cover the row, since kLongTile times the row's workgroups is at least n)
+  const uint32_t lead = (uint32_t)(((16u - (J.src & 15u)) & 15u) >> 2);
+  if (base == 0 && threadIdx.x < lead && threadIdx.x < J.n) check(row[threadIdx.x], threadIdx.x);
+  const uint4* __restrict__ row4 = reinterpret_cast<const uint4*>(row + lead);
 #pragma unroll
-  for (int e = 0; e < kLongTile / kBlock; ++e) {
-    uint32_t q = base + e * kBlock + threadIdx.x;
-    if (q < J.n) {
-      uint32_t v = row[q];
-      if (v >= J.n) bits |= kFlagBad;
-      if (v != q) bits |= kFlagNonId;
+  for (int e = 0; e < kLongTile / (4 * kBlock); ++e) {
+    const uint32_t u = base + 4u * (e * kBlock + threadIdx.x);  // offset after the lead
+    const uint32_t q = lead + u;
+    if (q + 3u < J.n) {
+      const uint4 v = row4[u >> 2];
+      check(v.x, q);
+      check(v.y, q + 1u);
+      check(v.z, q + 2u);
+      check(v.w, q + 3u);
+    } else {
+      for (uint32_t t = 0; t < 4u; ++t)
+        if (q + t < J.n) check(row[q + t], q + t);
     }
   }
   const uint32_t w = block_or(bits, &s_or);

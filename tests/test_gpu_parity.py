@@ -425,6 +425,36 @@ def test_table_insertion_orders_agree(ctx, monkeypatch, order):
         assert np.array_equal(o, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]), d.name
 
 
+def test_validation_sees_every_row_entry(ctx):
+    """The validation pass reads each δ row in 16-byte loads from its first
+    16-byte boundary and the (up to three) entries before it one by one.
+    Rows start misaligned when n is not a multiple of 4.  A single bad
+    transition, or a single non-identity entry, placed at each of the first
+    entries, just after the boundary, and at the row's end, must be seen:
+    the bad one as E_BAD_DFA, the non-identity one by the partition (letters
+    0 and 2 are the identity and only state n-1 accepts, so letter 1 sending
+    p to n-1 is the only thing that separates p from states 0..n-2)."""
+    from paper_2410_22764_amd import dfamin
+    for n in (5, 6, 7, 4097, 8191, 8194):
+        ids = np.arange(n, dtype=np.uint32)
+        acc = np.zeros(n, bool)
+        acc[n - 1] = True
+        for p in sorted({0, 1, 2, 3, 4, 5, n // 2, n - 3, n - 2} & set(range(n - 1))):
+            rows = np.stack([ids, ids.copy(), ids])
+            rows[1][p] = n - 1
+            d = W.from_rows(rows, acc, name=f"identity-but-{p} n={n}")
+            bad = W.from_rows(np.stack([ids, ids, ids]), acc, name=f"bad-{p} n={n}")
+            bad.delta[n + p] = n  # letter 1, state p: out of range
+            print(f"[case] validation n={n} p={p}", flush=True)
+            # a batch puts every instance at a 16-byte aligned offset, so the
+            # rows of letters 1 and 2 start misaligned when n % 4 != 0
+            outs, res = dfamin.dfamin_minimize_batch(ctx, [W.random_dfa(3, 2, 1), d], None)
+            want = oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]
+            assert np.array_equal(outs[1], want) and res[1]["num_blocks"] == 3, (n, p)
+            _, res = dfamin.dfamin_minimize_batch(ctx, [W.random_dfa(3, 2, 1), bad], None, check=False)
+            assert res[1]["status"] == dfamin.DFAMIN_E_BAD_DFA and res[0]["status"] == 0, (n, p)
+
+
 def _mixed_case(rng, i):
     kind = rng.choice(["random", "chain", "pchain", "fib", "coarse", "cycle"])
     n = int(2 ** rng.uniform(0, 12)) + 1
