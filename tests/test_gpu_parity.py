@@ -455,6 +455,31 @@ def test_validation_sees_every_row_entry(ctx):
             assert res[1]["status"] == dfamin.DFAMIN_E_BAD_DFA and res[0]["status"] == 0, (n, p)
 
 
+def test_fresh_context_first_call_is_a_large_batch():
+    """Uploads are staged in page-locked arenas that start empty and grow
+    (draining the stream first) when a phase of a call needs more: on a
+    fresh context whose first call is a batch of 3,000 instances, the job
+    lists, descriptors and row pointers outgrow them several times within
+    the call.  Every instance matches the oracle, and so does a second,
+    differently shaped call on the grown arenas."""
+    from paper_2410_22764_amd import dfamin
+    rng = np.random.default_rng(77)
+    ds = []
+    for t in range(3000):
+        n = int(rng.integers(2, 300))
+        ds.append(W.random_dfa(n, int(rng.integers(1, 6)), 1000 + t) if t % 4 else
+                  W.permuted_chain_dfa(n, 1, 5000 + t))
+    with dfamin.dfamin_create(0) as c:
+        print("[case] fresh context, 3,000-instance batch", flush=True)
+        outs, res = dfamin.dfamin_minimize_batch(c, ds, "auto")
+        for d, o, r in zip(ds, outs, res):
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert r["num_blocks"] == nb and np.array_equal(o, want), d.name
+        d = W.random_dfa(50000, 3, 9)
+        out, r = dfamin.dfamin_minimize(c, d, "off")
+        assert np.array_equal(out, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0])
+
+
 def _mixed_case(rng, i):
     kind = rng.choice(["random", "chain", "pchain", "fib", "coarse", "cycle"])
     n = int(2 ** rng.uniform(0, 12)) + 1
