@@ -72,10 +72,14 @@ typedef struct {
   uint32_t q0;            /* initial state < n; reported (out[q0]), not used by refinement */
 } dfamin_dfa;
 
-/* Closure policy (Section 3.4). */
-#define DFAMIN_CLOSURE_OFF   0u  /* refine on Sigma only */
-#define DFAMIN_CLOSURE_ON    1u  /* build Sigma^T before the first round */
-#define DFAMIN_CLOSURE_AUTO  2u  /* refine on Sigma; build Sigma^T if still refining after auto_rounds rounds */
+/* Closure policy (Section 3.4).  AUTO is 0, so a NULL or zeroed options
+ * struct selects it. */
+#define DFAMIN_CLOSURE_AUTO  0u  /* refine on Sigma; an instance with one non-identity letter refines by
+                                    doubling from the first round (one closure level per round, each
+                                    built when first read); any other instance gets Sigma^T built if
+                                    it is still refining after auto_rounds rounds */
+#define DFAMIN_CLOSURE_OFF   1u  /* refine on Sigma only */
+#define DFAMIN_CLOSURE_ON    2u  /* build Sigma^T before the first round */
 
 /* Refinement method. */
 #define DFAMIN_METHOD_SIGNATURE 0u  /* signature rounds (Section 3.3, Algorithm 4): each round groups
@@ -96,7 +100,7 @@ typedef struct {
                                        round's independent work overlapped) measure as fast or faster */
 
 typedef struct {
-  uint32_t closure;      /* DFAMIN_CLOSURE_*; a zeroed struct means OFF */
+  uint32_t closure;      /* DFAMIN_CLOSURE_*; 0 (a zeroed struct, or opts == NULL) means AUTO */
   uint32_t max_levels;   /* closure levels 0..L with L = min(floor(log2 n), max_levels); 0 = no cap */
   uint32_t auto_rounds;  /* AUTO: plain rounds before the closure is built; 0 = default (8) */
   uint32_t max_rounds;   /* give up with DFAMIN_E_INTERNAL after this many rounds; 0 = n + 1 */

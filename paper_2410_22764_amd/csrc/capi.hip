@@ -33,7 +33,9 @@ int check_dfa_shape(const dfamin_dfa* d) {
 }
 
 int check_opts(const dfamin_opts* o) {
-  if (o && (o->closure > DFAMIN_CLOSURE_AUTO || o->method > DFAMIN_METHOD_LEADER ||
+  const bool closure_ok = !o || o->closure == DFAMIN_CLOSURE_AUTO || o->closure == DFAMIN_CLOSURE_OFF ||
+                          o->closure == DFAMIN_CLOSURE_ON;
+  if (o && (!closure_ok || o->method > DFAMIN_METHOD_LEADER ||
             (o->flags & ~(DFAMIN_FLAG_NO_GRAPH | DFAMIN_FLAG_QUEUE))))
     return DFAMIN_E_INVAL;
   return DFAMIN_OK;

@@ -27,7 +27,7 @@ DFAMIN_E_CANCELLED = -6
 DFAMIN_E_BUSY = -7
 DFAMIN_E_INTERNAL = -8
 
-CLOSURE = {"off": 0, "on": 1, "auto": 2}
+CLOSURE = {"auto": 0, "off": 1, "on": 2}  # 0 (AUTO) is what a zeroed or NULL options struct means
 
 # Every symbol the header declares (checked by the CPU test suite).
 EXPORTS = [
@@ -144,7 +144,7 @@ FLAG_NO_GRAPH = 1
 FLAG_QUEUE = 2
 
 
-def make_opts(closure="off", max_levels=0, auto_rounds=0, max_rounds=0, method="signature", no_graph=False,
+def make_opts(closure="auto", max_levels=0, auto_rounds=0, max_rounds=0, method="signature", no_graph=False,
               queue=False):
     c = CLOSURE[closure] if isinstance(closure, str) else int(closure)
     m = METHOD[method] if isinstance(method, str) else int(method)

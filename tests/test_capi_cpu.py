@@ -93,3 +93,15 @@ def test_wait_refuses_an_output_shorter_than_the_ticket():
 
     with pytest.raises(ValueError, match="room"):
         dfamin.dfamin_wait(FakeCtx(), 7, 99)
+
+
+def test_zeroed_options_mean_closure_auto():
+    """A NULL or zeroed dfamin_opts selects closure AUTO: the header gives
+    DFAMIN_CLOSURE_AUTO the value 0, and the binding agrees (its default
+    options are a zeroed struct)."""
+    text = open(os.path.join(ROOT, "include", "dfamin.h")).read()
+    vals = {m: int(v) for m, v in re.findall(r"#define DFAMIN_CLOSURE_(\w+)\s+(\d+)u", text)}
+    assert vals == {"AUTO": 0, "OFF": 1, "ON": 2}
+    assert dfamin.CLOSURE == {"auto": 0, "off": 1, "on": 2}
+    o = dfamin.make_opts()
+    assert bytes(o) == bytes(dfamin.Opts())

@@ -3,6 +3,9 @@
 Every result must be identical alone and in any mix (tolerance 0: the output
 is an exact integer partition) and identical to the CPU oracle.
 """
+import hashlib
+import json
+import os
 import time
 
 import numpy as np
@@ -12,6 +15,12 @@ import oracle
 from paper_2410_22764_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+EXPECTED = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "expected_workloads.json")))
+
+
+def digest(out):
+    return hashlib.sha256(np.ascontiguousarray(out, dtype="<u4").tobytes()).hexdigest()[:32]
 
 
 @pytest.fixture(scope="module")
@@ -139,3 +148,33 @@ def test_pageable_staging_when_pinned_cap_is_zero(monkeypatch):
             assert res["num_blocks"] == nb and np.array_equal(out, want), d.name
     finally:
         c.close()
+
+
+def test_serving_pool_at_full_sizes_bit_exact(ctx):
+    """Requests of the serving workload at its own sizes (n up to 2^22,
+    |Sigma| up to 16, permuted chains of over 2^20 states among them), all
+    submitted at once so that they share the device: every result equals
+    the oracle's (digest, block count, initial block, written by the golden
+    script with the CPU oracle only) and the same DFA minimised alone."""
+    from paper_2410_22764_amd import dfamin
+    exp = EXPECTED["serving_pool"]
+    _, specs = W.serving_stream(exp["seed"], exp["draws"], 1.0)
+    reqs = exp["requests"]
+    assert any(e["n"] >= 1 << 20 and e["k"] == 16 for e in reqs)
+    assert any(e["kind"] == "chain" and e["n"] >= 1 << 20 for e in reqs)
+    print(f"[case] serving pool of {len(reqs)} at full sizes: generating", flush=True)
+    pool = [W.make_request(specs[e["index"]]) for e in reqs]
+    print("[case] serving pool: submitting all", flush=True)
+    tickets = [dfamin.dfamin_submit(ctx, d, "auto") for d in pool]
+    mixed = []
+    for d, e, t in zip(pool, reqs, tickets):
+        assert (d.n, d.k) == (e["n"], e["k"])
+        rc, out, res = dfamin.dfamin_wait(ctx, t, d.n, timeout_us=60_000_000)
+        assert rc == dfamin.DFAMIN_OK, (e, rc)
+        assert res["num_blocks"] == e["num_blocks"] and res["initial_block"] == e["initial_block"], e
+        assert digest(out) == e["sha"], e
+        mixed.append((digest(out), res["refine_rounds"]))
+    print("[case] serving pool: each request alone", flush=True)
+    for d, e, (dg, rr) in zip(pool, reqs, mixed):
+        alone, ra = dfamin.dfamin_minimize(ctx, d, "auto")
+        assert digest(alone) == dg and ra["refine_rounds"] == rr, e

@@ -29,13 +29,14 @@ def ctx():
     c.close()
 
 
-def test_plain_large_full_size(ctx):
-    """Random DFA, n = 2^24, |Sigma| = 4, seed 1, through the device entry point
-    with the closure policy the benchmark uses."""
+@pytest.mark.parametrize("seed", ["1", "2", "3"])
+def test_plain_large_full_size(ctx, seed):
+    """Random DFA, n = 2^24, |Sigma| = 4, seeds 1..3, through the device entry
+    point with the closure policy the benchmark uses."""
     import torch
     from paper_2410_22764_amd import dfamin
-    print("[case] plain_large seed 1", flush=True)
-    d = W.plain_large(1)
+    print(f"[case] plain_large seed {seed}", flush=True)
+    d = W.plain_large(int(seed))
     dev = torch.device("cuda:0")
     delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
     accept = torch.from_numpy(d.accept).to(dev)
@@ -44,9 +45,10 @@ def test_plain_large_full_size(ctx):
                                         out.data_ptr(), opts="auto",
                                         stream=torch.cuda.current_stream().cuda_stream)
     got = out.cpu().numpy().view(np.uint32)
-    exp = EXPECTED["plain_large"]["1"]
+    exp = EXPECTED["plain_large"][seed]
     assert res["num_blocks"] == exp["num_blocks"]
     assert digest(got) == exp["sha"]
+    del delta, accept, out
 
 
 @pytest.mark.parametrize("closure", ["auto", "on"])
