@@ -157,6 +157,34 @@ int dfamin_minimize(dfamin_ctx *ctx, const dfamin_dfa *host_dfa, const dfamin_op
 int dfamin_minimize_device(dfamin_ctx *ctx, const dfamin_dfa *dev_dfa, const dfamin_opts *opts,
                            uint32_t *dev_out, dfamin_result *result, void *hip_stream);
 
+/* Size of the static device array behind dfamin_minimize_device_noalloc. */
+#define DFAMIN_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate: code around HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Same arguments, results
+ * and errors as dfamin_minimize_device, but the call allocates nothing: no
+ * hipMalloc / hipFree, no page-locked host memory, no events, no graphs.
+ * Every device buffer of the call (block ids, active lists, hash table,
+ * signature records, closure levels, scan status, control block) is carved
+ * from one static device array of DFAMIN_NOALLOC_SCRATCH_BYTES bytes, which
+ * the library holds on each device it runs on until the process ends; the
+ * host-side staging it uses was set up by dfamin_create.  The caller still
+ * passes delta, accept and dev_out in device memory.
+ *   - Size limit: n * (66 + 16 * (k + 1)) + 2^20 must not exceed
+ *     DFAMIN_NOALLOC_SCRATCH_BYTES (about 579,000 states at k = 2);
+ *     larger inputs return DFAMIN_E_NOMEM before any work and leave
+ *     dev_out untouched.
+ *   - opts: method SIGNATURE only, and no DFAMIN_FLAG_QUEUE (both would
+ *     instantiate HIP graphs): DFAMIN_E_INVAL otherwise.
+ *   - Kernel timing (dfamin_set_profiling) is suspended for the call.
+ *   - The array is shared by every context and every call on a device and
+ *     keeps the last call's contents (each call clears what it needs).
+ *     Calls that overlap on one device race: the caller must serialize
+ *     them, across contexts and threads.
+ * Returns when the work has completed, like dfamin_minimize_device. */
+int dfamin_minimize_device_noalloc(dfamin_ctx *ctx, const dfamin_dfa *dev_dfa, const dfamin_opts *opts,
+                                   uint32_t *dev_out, dfamin_result *result, void *hip_stream);
+
 /* Minimize `count` independent DFAs (host memory) together: all instances
  * are refined by the same kernel launches, one fused round at a time
  * (block ids are global state ids, so instances never mix), and each

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <thread>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -19,9 +20,54 @@ struct dfamin_ctx {
   dfamin::Context c;
 };
 
+// Device memory of dfamin_minimize_device_noalloc: one array per device,
+// held from the module's load until the process ends.  In host code its name
+// is a host-side stand-in, never a device address: kernels receive the
+// address that hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) unsigned char scratch[DFAMIN_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 using dfamin::Context;
+
+constexpr int kMaxDevices = 64;
+// page-locked bytes of each host buffer of a fixed-region engine (control
+// block and result readbacks, job lists, the two upload arenas)
+constexpr size_t kFixedHostBytes = 256u << 10;
+// the array's last bytes are left out of the region, as a margin behind the
+// last carved buffer
+constexpr size_t kScratchTail = 64u << 10;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current; looked up
+// once per device.
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return DFAMIN_E_INVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return DFAMIN_E_DEVICE;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return DFAMIN_OK;
+}
+
+// Device bytes a single-instance call of dfamin_minimize_device_noalloc may
+// carve, per state: block, act, act2, slot_of and nb (4 B each), keep (1),
+// rank (4), dense numbers (4), a hash table of up to 2^ceil(log2 2n) 8-byte
+// slots (at most 32 B), and signature records of k + 1 words counted four
+// times over (the plain letters' records, then those of closure levels,
+// which take at most a third of what is left); plus 1 MiB of job lists,
+// descriptors and scan status.
+uint64_t noalloc_bytes(uint32_t n, uint32_t k) {
+  return (uint64_t)n * (66ull + 16ull * ((uint64_t)k + 1)) + (1ull << 20);
+}
 using dfamin::InstInput;
 using dfamin::InstOutcome;
 
@@ -249,6 +295,22 @@ int dfamin_create(int hip_device, uint64_t hbm_budget_bytes, dfamin_ctx** out) {
     delete ctx;
     return DFAMIN_E_DEVICE;
   }
+  // set-up of dfamin_minimize_device_noalloc, so that the call itself needs
+  // no allocation: this device's scratch address, the fixed engine's
+  // page-locked host buffers and events, and the tile autotuner's events
+  void* sp = nullptr;
+  int rc = scratch_address(hip_device, &sp);
+  if (rc == DFAMIN_OK) rc = ctx->c.fixed_engine.set_fixed_region(sp, DFAMIN_NOALLOC_SCRATCH_BYTES - kScratchTail,
+                                                                kFixedHostBytes);
+  if (rc == DFAMIN_OK && !ctx->c.tuner.have_events) {
+    for (hipEvent_t& e : ctx->c.tuner.ev)
+      if (hipEventCreate(&e) != hipSuccess) rc = DFAMIN_E_DEVICE;
+    ctx->c.tuner.have_events = true;
+  }
+  if (rc != DFAMIN_OK) {
+    dfamin_destroy(ctx);
+    return rc;
+  }
   *out = ctx;
   return DFAMIN_OK;
 }
@@ -354,6 +416,36 @@ int dfamin_minimize_device(dfamin_ctx* ctx, const dfamin_dfa* dev_dfa, const dfa
   in[0].out = dev_out;
   std::vector<InstOutcome> res;
   rc = ctx->c.engine.run(in, o, static_cast<hipStream_t>(hip_stream), res);
+  if (rc == DFAMIN_OK || rc == DFAMIN_E_BAD_DFA) to_result(res[0], result);
+  return rc;
+}
+
+int dfamin_minimize_device_noalloc(dfamin_ctx* ctx, const dfamin_dfa* dev_dfa, const dfamin_opts* opts,
+                                   uint32_t* dev_out, dfamin_result* result, void* hip_stream) {
+  if (!ctx || !dev_out) return DFAMIN_E_INVAL;
+  int rc = check_dfa_shape(dev_dfa);
+  if (rc == DFAMIN_OK) rc = check_opts(opts);
+  // leader rounds and queued rounds instantiate HIP graphs
+  if (rc == DFAMIN_OK && opts && (opts->method != DFAMIN_METHOD_SIGNATURE || (opts->flags & DFAMIN_FLAG_QUEUE)))
+    rc = DFAMIN_E_INVAL;
+  if (rc != DFAMIN_OK) return rc;
+  if (noalloc_bytes(dev_dfa->n, dev_dfa->k) > DFAMIN_NOALLOC_SCRATCH_BYTES) return DFAMIN_E_NOMEM;
+  if (!ctx->c.fixed_engine.fixed()) return DFAMIN_E_INTERNAL;
+  if ((rc = set_device(ctx->c)) != DFAMIN_OK) return rc;
+  const dfamin_opts o = opts_or_default(opts);
+  std::vector<InstInput> in(1);
+  in[0].n = dev_dfa->n;
+  in[0].k = dev_dfa->k;
+  in[0].q0 = dev_dfa->q0;
+  in[0].closure = o.closure;
+  in[0].delta = dev_dfa->delta;
+  in[0].accept = dev_dfa->accept;
+  in[0].out = dev_out;
+  std::vector<InstOutcome> res;
+  // kernel timing would create events: off for this call
+  const bool prof_was = ctx->c.prof.swap_enabled(false);
+  rc = ctx->c.fixed_engine.run(in, o, static_cast<hipStream_t>(hip_stream), res);
+  ctx->c.prof.swap_enabled(prof_was);
   if (rc == DFAMIN_OK || rc == DFAMIN_E_BAD_DFA) to_result(res[0], result);
   return rc;
 }

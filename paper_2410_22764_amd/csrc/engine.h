@@ -40,6 +40,12 @@ class Profiler {
   ~Profiler();
   void set_enabled(bool on);
   bool enabled() const { return on_; }
+  // Turn timing on or off without clearing the stats; returns the old state.
+  bool swap_enabled(bool on) {
+    const bool was = on_;
+    on_ = on;
+    return was;
+  }
   // Record a start event for kernel `name`; `alg_bytes` is what it must move.
   void begin(hipStream_t s, const char* name, double alg_bytes);
   void end(hipStream_t s);
@@ -93,12 +99,25 @@ class Engine {
   int run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
           std::vector<InstOutcome>& res);
   uint64_t device_bytes() const;
+  // Fixed-region mode, for callers that cannot allocate.  Every device
+  // buffer of a call is carved from [base, base + cap), which the engine
+  // does not own; carving restarts at every call.  The host buffers are
+  // page-locked here once with host_bytes each and never grow: a call that
+  // would need more fails with DFAMIN_E_NOMEM, as does one whose device
+  // buffers do not fit in the region.  Call once, at set-up.
+  int set_fixed_region(void* base, size_t cap, size_t host_bytes);
+  bool fixed() const { return fixed_base_ != nullptr; }
 
  private:
   int run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
                std::vector<InstOutcome>& res);
   int ensure(DevBuf& b, size_t bytes);
   int ensure_host(HostBuf& b, size_t bytes);
+  // Closure level storage a call may still take: half of the context's
+  // remaining budget, or a third of what is left of the fixed region (the
+  // signature records of the levels need about as much again).
+  uint64_t closure_cap() const;
+  void reset_fixed_region();
   int build_closure(const std::vector<uint32_t>& which, const dfamin_opts& opts, hipStream_t s);
   // Closure levels of unary doubling instances, computed round by round.
   struct LevelTodo {
@@ -194,6 +213,9 @@ class Engine {
                     uint64_t& executed);
   DevBuf d_qdbl_;   // per-instance doubling state of queued rounds
   HostBuf h_qdbl_;
+  // fixed-region mode (set_fixed_region)
+  char* fixed_base_ = nullptr;
+  size_t fixed_cap_ = 0, fixed_off_ = 0;
 };
 
 // Signature-tile autotuner state of a context: a forced variant, or the
@@ -216,6 +238,9 @@ class Context {
   Profiler prof;
   Tuner tuner;
   Engine engine{this};
+  // the engine of dfamin_minimize_device_noalloc: its device buffers live in
+  // the library's static scratch array of this device (fixed-region mode)
+  Engine fixed_engine{this};
   // staging for host-input calls
   DevBuf in_delta, in_accept, in_out;
   HostBuf h_in, h_out;

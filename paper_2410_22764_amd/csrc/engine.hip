@@ -135,10 +135,13 @@ Engine::~Engine() {
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
                     &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_};
-  for (DevBuf* b : bufs)
-    if (b->p) (void)hipFree(b->p);
-  for (DevBuf& b : closure_bufs_)
-    if (b.p) (void)hipFree(b.p);
+  // device buffers of the fixed-region mode belong to the region
+  if (!fixed()) {
+    for (DevBuf* b : bufs)
+      if (b->p) (void)hipFree(b->p);
+    for (DevBuf& b : closure_bufs_)
+      if (b.p) (void)hipFree(b.p);
+  }
   HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_rb_, &h_qdbl_,
                    &stage_[0].buf, &stage_[1].buf};
   for (HostBuf* b : hb)
@@ -168,6 +171,16 @@ int Engine::check_hip(hipError_t e) {
 int Engine::ensure(DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
   if (b.cap >= bytes) return DFAMIN_OK;
+  if (fixed()) {
+    // carved from the region; what the buffer held before stays unused
+    // until the next call restarts the carving
+    const size_t at = (fixed_off_ + 255) & ~size_t(255);
+    if (at > fixed_cap_ || bytes > fixed_cap_ - at) return DFAMIN_E_NOMEM;
+    b.p = fixed_base_ + at;
+    b.cap = bytes;
+    fixed_off_ = at + bytes;
+    return DFAMIN_OK;
+  }
   size_t want = bytes + bytes / 8;  // head-room for the next, slightly larger call
   want = (want + 4095) & ~size_t(4095);
   if (b.p) {
@@ -194,6 +207,7 @@ int Engine::ensure(DevBuf& b, size_t bytes) {
 int Engine::ensure_host(HostBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 64;
   if (b.cap >= bytes) return DFAMIN_OK;
+  if (fixed() && b.p) return DFAMIN_E_NOMEM;  // sized once at set-up
   if (b.p) (void)hipHostFree(b.p);
   b.p = b.dp = nullptr;
   b.cap = 0;
@@ -214,6 +228,35 @@ int Engine::ensure_host(HostBuf& b, size_t bytes) {
   return DFAMIN_OK;
 }
 
+int Engine::set_fixed_region(void* base, size_t cap, size_t host_bytes) {
+  if (!base || fixed() || device_bytes() != 0) return DFAMIN_E_INTERNAL;
+  HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_rb_, &h_qdbl_,
+                   &stage_[0].buf, &stage_[1].buf};
+  for (HostBuf* b : hb) TRY(ensure_host(*b, host_bytes));
+  if (!ev_rb_) HIP(hipEventCreateWithFlags(&ev_rb_, hipEventDisableTiming));
+  fixed_base_ = static_cast<char*>(base);
+  fixed_cap_ = cap;
+  fixed_off_ = 0;
+  return DFAMIN_OK;
+}
+
+void Engine::reset_fixed_region() {
+  DevBuf* bufs[] = {&d_desc_, &d_rows_, &d_jobs_, &d_joboff_, &d_flags_, &d_inst_off_, &d_minF_,
+                    &d_minN_, &d_inst_of_, &d_block_, &d_act_, &d_act2_, &d_slot_of_, &d_nb_,
+                    &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
+                    &d_results_, &d_wgflags_, &d_part_, &d_dense_,
+                    &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_ctrl_, &d_refine_, &d_counts_};
+  for (DevBuf* b : bufs) *b = DevBuf{};
+  closure_bufs_.clear();
+  fixed_off_ = 0;
+}
+
+uint64_t Engine::closure_cap() const {
+  if (fixed()) return fixed_cap_ > fixed_off_ ? (fixed_cap_ - fixed_off_) / 3 : 0;
+  return ctx_->budget > ctx_->used ? (ctx_->budget - ctx_->used) / 2 : 0;
+}
+
 int Engine::upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (!bytes) return DFAMIN_OK;
   Stage& st = stage_[stage_cur_];
@@ -223,7 +266,9 @@ int Engine::upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
     // arena then grows to twice what this phase has asked for
     HIP(stream_wait(s));
     stage_idle();
-    TRY(ensure_host(st.buf, std::max<size_t>(2 * (at + bytes), size_t(64) << 10)));
+    // (a fixed-region engine reuses its arena from the start, never grows it)
+    if (!fixed() || st.buf.cap < bytes)
+      TRY(ensure_host(st.buf, std::max<size_t>(2 * (at + bytes), size_t(64) << 10)));
     at = 0;
   }
   std::memcpy(st.buf.as<char>() + at, src, bytes);
@@ -279,7 +324,7 @@ int Engine::build_closure(const std::vector<uint32_t>& which, const dfamin_opts&
     specs[w].letters = nonid_[i];
     specs[w].L = l;
   }
-  const uint64_t cap = ctx_->budget > ctx_->used ? (ctx_->budget - ctx_->used) / 2 : 0;
+  const uint64_t cap = closure_cap();
   uint64_t taken = 0;
   ClosureScratch scratch;
   DevBuf* bufs[4] = {&d_jobs_, &d_joboff_, &d_flags_, &d_wgflags_};
@@ -344,7 +389,7 @@ int Engine::lazy_levels(const std::vector<uint32_t>& which, const dfamin_opts& o
   };
   uint64_t words = 0;
   for (uint32_t i : uni) words += (uint64_t)levels_of(i) * in_[i].n;
-  const uint64_t cap = ctx_->budget > ctx_->used ? (ctx_->budget - ctx_->used) / 2 : 0;
+  const uint64_t cap = closure_cap();
   char* base = nullptr;
   if (words) {
     if (words * 4 > cap) {
@@ -1261,6 +1306,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
   if (N >= kMaxStates) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
   N_ = N;
+  if (fixed()) reset_fixed_region();
   closure_cursor_ = 0;
   // the previous call ended with its stream drained (run() drains on errors)
   stage_idle();

@@ -34,7 +34,7 @@ EXPORTS = [
     "dfamin_create", "dfamin_destroy", "dfamin_minimize", "dfamin_minimize_device",
     "dfamin_minimize_batch", "dfamin_minimize_batch_device", "dfamin_submit", "dfamin_wait",
     "dfamin_cancel", "dfamin_status_str", "dfamin_set_profiling", "dfamin_get_kernel_stats",
-    "dfamin_set_tuning", "dfamin_minimal_dfa",
+    "dfamin_set_tuning", "dfamin_minimal_dfa", "dfamin_minimize_device_noalloc",
 ]
 
 
@@ -108,6 +108,8 @@ def load():
     lib.dfamin_minimize.restype = i32
     lib.dfamin_minimize_device.argtypes = [vp, P(Dfa), P(Opts), vp, P(Result), vp]
     lib.dfamin_minimize_device.restype = i32
+    lib.dfamin_minimize_device_noalloc.argtypes = [vp, P(Dfa), P(Opts), vp, P(Result), vp]
+    lib.dfamin_minimize_device_noalloc.restype = i32
     lib.dfamin_minimize_batch.argtypes = [vp, u32, P(Dfa), P(Opts), P(vp), P(Result)]
     lib.dfamin_minimize_batch.restype = i32
     lib.dfamin_minimize_batch_device.argtypes = [vp, u32, P(Dfa), P(Opts), P(vp), P(Result), vp]
@@ -242,6 +244,30 @@ def dfamin_minimize_device(ctx, n, k, delta_ptr, accept_ptr, q0, out_ptr, opts=N
     r = res.as_dict()
     r["rc"] = rc
     return r
+
+
+def dfamin_minimize_device_noalloc(ctx, n, k, delta_ptr, accept_ptr, q0, out_ptr, opts=None, stream=0,
+                                   check=True):
+    """As dfamin_minimize_device, through the entry point that allocates
+    nothing (its device buffers live in the library's static scratch array)."""
+    s = Dfa(int(n), int(k), int(delta_ptr), int(accept_ptr), int(q0))
+    res = Result()
+    rc = load().dfamin_minimize_device_noalloc(ctx.handle, ctypes.byref(s), _opts(opts), int(out_ptr),
+                                               ctypes.byref(res), int(stream) or None)
+    if check and rc != DFAMIN_OK:
+        raise DfaminError(rc, "dfamin_minimize_device_noalloc")
+    r = res.as_dict()
+    r["rc"] = rc
+    return r
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def noalloc_fits(n, k):
+    """Whether dfamin_minimize_device_noalloc accepts an instance of n
+    states and k letters (the size limit stated with its declaration)."""
+    return n * (66 + 16 * (k + 1)) + (1 << 20) <= NOALLOC_SCRATCH_BYTES
 
 
 def dfamin_minimize_batch(ctx, dfas, opts=None, check=True):

@@ -36,6 +36,7 @@ def test_null_arguments_rejected_without_device_work():
     lib = dfamin.load()
     assert lib.dfamin_minimize(None, None, None, None, None) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_minimize_device(None, None, None, None, None, None) == dfamin.DFAMIN_E_INVAL
+    assert lib.dfamin_minimize_device_noalloc(None, None, None, None, None, None) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_minimize_batch(None, 0, None, None, None, None) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_submit(None, None, None, None) == dfamin.DFAMIN_E_INVAL
     assert lib.dfamin_cancel(None, 1) == dfamin.DFAMIN_E_INVAL
@@ -105,3 +106,13 @@ def test_zeroed_options_mean_closure_auto():
     assert dfamin.CLOSURE == {"auto": 0, "off": 1, "on": 2}
     o = dfamin.make_opts()
     assert bytes(o) == bytes(dfamin.Opts())
+
+
+def test_noalloc_size_limit_matches_header():
+    """The binding's size check and scratch size are those the header states."""
+    import re as _re
+    text = open(os.path.join(ROOT, "include", "dfamin.h")).read()
+    m = _re.search(r"#define DFAMIN_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == dfamin.NOALLOC_SCRATCH_BYTES
+    assert "n * (66 + 16 * (k + 1)) + 2^20" in text
+    assert dfamin.noalloc_fits(579_000, 2) and not dfamin.noalloc_fits(579_500, 2)
