@@ -124,6 +124,34 @@ def copy_peak_gbps(reps=5, mib=1024):
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
+def host_info():
+    """The host the CPU baselines ran on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"nproc": os.cpu_count(), "usable_cpus": usable, "cpu_model": model}
+
+
+def pool_threads():
+    """Worker threads for the CPU baselines over many instances: every usable
+    host core, at most 16 (the host's share per GPU on a shared box)."""
+    return max(1, min(16, host_info()["usable_cpus"] or 1))
+
+
+def pct(xs, q):
+    import numpy as np
+    return round(float(np.percentile(xs, q)), 4)
+
+
 def cpu_baseline(spec, seed, budget_s=20.0):
     """The oracle (Hopcroft, single thread) on a bounded sample of the same
     kind of input, scaled to transitions/s."""
@@ -148,8 +176,90 @@ def cpu_baseline(spec, seed, budget_s=20.0):
         if time.perf_counter() - t0 > budget_s / 2 or reps >= 5:
             break
     wall = (time.perf_counter() - t0) / reps
-    return {"value": d.n * d.k / wall, "unit": "transitions/s", "cores": 1, "kind": "oracle",
-            "sample": f"Hopcroft (C, 1 thread) on {d.name}, {reps} run(s), {wall:.2f} s each"}
+    out = {"value": d.n * d.k / wall, "unit": "transitions/s", "cores": 1, "kind": "oracle",
+           "sample": f"Hopcroft (C, 1 thread: a sequential algorithm) on {d.name}, {reps} run(s), "
+                     f"{wall:.2f} s each"}
+    out.update(host_info())
+    return out
+
+
+def cpu_baseline_batch(batch):
+    """The oracle over every instance of a batch, one Hopcroft per instance on
+    a thread pool over the usable host cores (the C calls release the GIL)."""
+    import oracle
+    threads = pool_threads()
+    tup = [(d.n, d.k, d.delta, d.accept) for d in batch]
+    t0 = time.perf_counter()
+    oracle.hopcroft_many(tup, threads=threads)
+    wall = time.perf_counter() - t0
+    trans = sum(d.n * d.k for d in batch)
+    out = {"value": trans / wall, "unit": "transitions/s", "cores": threads, "kind": "oracle",
+           "ms": round(1e3 * wall, 1),
+           "sample": f"Hopcroft (C) on all {len(batch)} instances, {threads} threads"}
+    out.update(host_info())
+    return out
+
+
+def time_device_steps(step, reps, warmup=3):
+    """Wall time of `reps` calls of step() (each returns when its work is
+    done), after `warmup` untimed ones: p50 / p99 / mean in ms."""
+    import statistics
+    for _ in range(warmup):
+        step()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        step()
+        lat.append(1e3 * (time.perf_counter() - t0))
+    return {"repeats": reps, "ms_p50": pct(lat, 50), "ms_p99": pct(lat, 99),
+            "ms_mean": round(statistics.fmean(lat), 4)}
+
+
+def config_legs(ctx, reps=30):
+    """The small single-instance configurations, each timed over `reps`
+    device-resident calls: the random DFA of 16,384 states (seeds 1..5) and
+    the 2^20-state chain (closure AUTO, the default, and ON), with the oracle
+    on the same input beside each."""
+    import numpy as np
+    import torch
+    import oracle
+    from paper_2410_22764_amd import dfamin, workloads as W
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def leg(d, closure, reps):
+        delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
+        accept = torch.from_numpy(d.accept).to(dev)
+        out = torch.empty(d.n, dtype=torch.int32, device=dev)
+        res = {}
+
+        def step():
+            res.update(dfamin.dfamin_minimize_device(ctx, d.n, d.k, delta.data_ptr(), accept.data_ptr(), d.q0,
+                                                     out.data_ptr(), opts={"closure": closure}, stream=stream))
+        t = time_device_steps(step, reps)
+        t["value_p50"] = d.n * d.k / (t["ms_p50"] * 1e-3)
+        t["result"] = result_summary(res)
+        t0 = time.perf_counter()
+        oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        t["cpu_oracle_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+        return t
+
+    print("[bench] configs: plain_single seeds 1..5, deep_chain", file=sys.stderr, flush=True)
+    single = {}
+    for seed in range(1, 6):
+        single[str(seed)] = leg(W.random_dfa(16384, 2, seed), "auto", reps)
+    chain = W.chain_dfa(1 << 20, 2)
+    return {
+        "plain_single": {"workload": "random DFA, n=16384, |Sigma|=2, closure auto, seeds 1..5",
+                         "transitions": 32768, "seeds": single,
+                         "ms_p50_median_over_seeds": round(statistics.median(
+                             x["ms_p50"] for x in single.values()), 4)},
+        "deep_chain_auto": dict(workload="chain DFA, n=2^20, |Sigma|=2, closure auto (doubling)",
+                                transitions=2 << 20, **leg(chain, "auto", reps)),
+        "deep_chain_on": dict(workload="chain DFA, n=2^20, |Sigma|=2, closure on (Algorithm 5 up front)",
+                              transitions=2 << 20, **leg(chain, "on", max(20, reps // 2))),
+        "cpu_oracle_note": "cpu_oracle_ms: Hopcroft (C, 1 thread) on the same input, once",
+    }
 
 
 def upload_batch(dfas, dev):
@@ -181,8 +291,9 @@ def upload_batch(dfas, dev):
     return specs, outs, (td, ta, to)
 
 
-def batched_vs_plain(ctx, seed=1, reps=3):
-    """Batched workload: 4,096 uneven DFAs in one call vs. one call per DFA."""
+def batched_vs_plain(ctx, seed=1, reps=10, plain_passes=2):
+    """Batched workload: 4,096 uneven DFAs in one call vs. one call per DFA,
+    and the oracle over the same instances on a host thread pool."""
     import torch
     from paper_2410_22764_amd import dfamin, workloads as W
     print("[bench] batch: generating 4096 DFAs", file=sys.stderr, flush=True)
@@ -193,84 +304,112 @@ def batched_vs_plain(ctx, seed=1, reps=3):
     trans = sum(d.n * d.k for d in batch)
     opts = {"closure": "auto"}
     prepared = dfamin.BatchDevice(specs, outs)  # ctypes arguments built once
-    prepared.run(ctx, opts, stream)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        prepared.run(ctx, opts, stream)
-    torch.cuda.synchronize()
-    tb = (time.perf_counter() - t0) / reps
+    tbat = time_device_steps(lambda: prepared.run(ctx, opts, stream), reps, warmup=1)
+    tb = tbat["ms_p50"] * 1e-3
     print("[bench] batch: plain per-instance loop", file=sys.stderr, flush=True)
     for sp, o in zip(specs[:64], outs[:64]):  # warm-up
         dfamin.dfamin_minimize_device(ctx, *sp, o, opts=opts, stream=stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for sp, o in zip(specs, outs):
-        dfamin.dfamin_minimize_device(ctx, *sp, o, opts=opts, stream=stream)
-    torch.cuda.synchronize()
-    tp = time.perf_counter() - t0
+    passes = []
+    for _ in range(plain_passes):
+        t0 = time.perf_counter()
+        for sp, o in zip(specs, outs):
+            dfamin.dfamin_minimize_device(ctx, *sp, o, opts=opts, stream=stream)
+        torch.cuda.synchronize()
+        passes.append(time.perf_counter() - t0)
+    tp = statistics.median(passes)
+    print("[bench] batch: cpu oracle on a thread pool", file=sys.stderr, flush=True)
+    cpu = cpu_baseline_batch(batch)
     return {"workload": "batch_mixed: 4096 DFAs, n log-uniform in [64, 65536], |Sigma| in 2..8, "
                         "25% permuted chains, seed 1, closure auto",
-            "transitions": trans, "batched_ms": round(1e3 * tb, 3), "plain_loop_ms": round(1e3 * tp, 3),
-            "batched_value": trans / tb, "plain_loop_value": trans / tp, "ratio": round(tp / tb, 2)}
+            "transitions": trans, "batched_ms": round(1e3 * tb, 3),
+            "batched_ms_p50": tbat["ms_p50"], "batched_ms_p99": tbat["ms_p99"], "batched_repeats": reps,
+            "plain_loop_ms": round(1e3 * tp, 3), "plain_loop_passes_ms": [round(1e3 * x, 1) for x in passes],
+            "batched_value": trans / tb, "plain_loop_value": trans / tp, "ratio": round(tp / tb, 2),
+            "cpu_baseline": cpu, "vs_cpu_pool": round((trans / tb) / cpu["value"], 1)}
 
 
-def serving_run(ctx, seed, count, pool_size, load, threads=64):
+def serving_run(ctx, seed, count, pool_size, load, threads=256, submitters=16):
     """Serving workload: Poisson arrivals of minimization requests at `load`
-    times the saturation throughput measured on the same request pool."""
+    times the saturation throughput measured on the same request pool.
+
+    The arrival loop only schedules: each request is submitted at its
+    scheduled arrival time by a worker thread, and its latency runs from
+    that scheduled time to the end of its dfamin_wait.  Time a request
+    spends behind other submits' input copies, or waiting for a free worker,
+    therefore counts against it."""
     import numpy as np
     from concurrent.futures import ThreadPoolExecutor
     from paper_2410_22764_amd import dfamin, workloads as W
     print(f"[bench] serving: generating a pool of {pool_size} requests", file=sys.stderr, flush=True)
     _, specs = W.serving_stream(seed, pool_size, 1.0)
-    pool = [W.make_request(sp) for sp in specs]
+    with ThreadPoolExecutor(max_workers=pool_threads()) as ex:  # numpy releases the GIL
+        pool = list(ex.map(W.make_request, specs))
     opts = {"closure": "auto"}
-    # saturation: submit the whole pool at once, closed loop; the first pass
-    # warms the library's caches (device pool, page-locked staging, tuned
-    # tiles) and is not timed
-    print("[bench] serving: saturation", file=sys.stderr, flush=True)
-    for timed in (False, True):
-        t0 = time.perf_counter()
-        ts = [dfamin.dfamin_submit(ctx, d, opts) for d in pool]
-        for d, t in zip(pool, ts):
+
+    def closed_loop():
+        # the whole pool at once, submitted by `submitters` threads
+        def one(d):
+            t = dfamin.dfamin_submit(ctx, d, opts)
             rc, _, _ = dfamin.dfamin_wait(ctx, t, d.n)
             assert rc == 0
-        sat = len(pool) / (time.perf_counter() - t0)
+        with ThreadPoolExecutor(max_workers=submitters) as ex:
+            t0 = time.perf_counter()
+            list(ex.map(one, pool))
+            return len(pool) / (time.perf_counter() - t0)
+
+    # saturation, closed loop; the first pass warms the library's caches
+    # (device pool, page-locked staging, tuned tiles) and is not timed
+    print("[bench] serving: saturation", file=sys.stderr, flush=True)
+    closed_loop()
+    sat = closed_loop()
     rate = load * sat
     arrivals, _ = W.serving_stream(seed + 1, count, rate)
     order = W.uniform_below(W.stream_key(seed, "serve", "order"), count, pool_size)
     lat = [0.0] * count
+    lag = [0.0] * count
+    done = [0.0] * count
     print(f"[bench] serving: {count} requests at {rate:.1f}/s", file=sys.stderr, flush=True)
-
-    def waiter(i, t, n, t_arr):
-        rc, _, _ = dfamin.dfamin_wait(ctx, t, n)
-        assert rc == 0
-        lat[i] = time.perf_counter() - t_arr
-
     ex = ThreadPoolExecutor(max_workers=threads)
+    start = time.perf_counter() + 0.01
+
+    def job(i):
+        d = pool[int(order[i])]
+        t_sched = start + float(arrivals[i])
+        t = dfamin.dfamin_submit(ctx, d, opts)
+        lag[i] = time.perf_counter() - t_sched
+        rc, _, _ = dfamin.dfamin_wait(ctx, t, d.n)
+        assert rc == 0
+        done[i] = time.perf_counter()
+        lat[i] = done[i] - t_sched
+
     futs = []
-    start = time.perf_counter()
     for i in range(count):
-        target = start + arrivals[i]
+        target = start + float(arrivals[i])
         while True:
             now = time.perf_counter()
             if now >= target:
                 break
-            time.sleep(min(target - now, 0.001))
-        d = pool[int(order[i])]
-        t_arr = time.perf_counter()
-        t = dfamin.dfamin_submit(ctx, d, opts)
-        futs.append(ex.submit(waiter, i, t, d.n, t_arr))
+            time.sleep(min(target - now, 0.0005))
+        futs.append(ex.submit(job, i))
     for f in futs:
         f.result()
-    wall = time.perf_counter() - start
     ex.shutdown()
+    span = float(arrivals[-1])
+    wall = max(done) - start
     trans = sum(pool[int(o)].transitions for o in order)
     return {"requests": count, "pool": pool_size, "offered_rate_per_s": round(rate, 2),
+            "offered_rate_realised_per_s": round(count / span, 2),
             "saturation_dfas_per_s": round(sat, 2), "load": load, "dfas_per_s": round(count / wall, 2),
+            "achieved_over_offered": round((count / wall) / (count / span), 4),
             "transitions_per_s": trans / wall,
             "latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
-                           "p99": round(1e3 * float(np.percentile(lat, 99)), 3)}}
+                           "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
+                           "from": "scheduled arrival time"},
+            "submit_lag_ms": {"p50": round(1e3 * float(np.percentile(lag, 50)), 3),
+                              "p99": round(1e3 * float(np.percentile(lag, 99)), 3)},
+            "client": f"arrivals scheduled by one thread, submitted by a pool of {threads} worker threads; "
+                      f"saturation from {submitters} submitting threads, closed loop over the pool"}
 
 
 def main():
@@ -290,12 +429,12 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no HIP-event kernel timing")
     ap.add_argument("--profile-steps", type=int, default=5, help="extra steps timed per kernel")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain and end-to-end legs")
-    ap.add_argument("--requests", type=int, default=400, help="serving: measured requests")
-    ap.add_argument("--pool", type=int, default=128, help="serving: distinct pre-generated requests")
+    ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests")
+    ap.add_argument("--pool", type=int, default=256, help="serving: distinct pre-generated requests")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / saturation")
-    ap.add_argument("--serving-requests", type=int, default=200,
+    ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the serving leg in the default run (0: none)")
-    ap.add_argument("--serving-pool", type=int, default=64,
+    ap.add_argument("--serving-pool", type=int, default=256,
                     help="distinct requests of the serving leg in the default run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB a few times (for scaling "
@@ -427,13 +566,19 @@ def main():
                     "avg_launch_us": round(per_launch_ms * 1e3, 2),
                     "alg_bytes_per_launch": round(per_launch_bytes)}
         if traffic:
-            # measured HBM bytes per launch over the same launch time
-            roofline["traffic_GBps"] = round(traffic / (per_launch_ms * 1e-3) / 1e9, 1)
-            roofline["traffic_frac"] = round(roofline["traffic_GBps"] / HBM_PEAK_GBS, 4)
+            # counter bytes per launch over the same launch time.  FETCH_SIZE
+            # and WRITE_SIZE count what leaves the L2 for the memory fabric:
+            # hits in the memory-side cache are included, so this rate is not
+            # a fraction of HBM bandwidth (it can exceed a device copy's)
+            roofline["counter_GBps"] = round(traffic / (per_launch_ms * 1e-3) / 1e9, 1)
+            roofline["traffic_note"] = ("traffic: FETCH_SIZE x2 + WRITE_SIZE per launch (copy-calibrated), "
+                                        "bytes between L2 and the memory fabric, memory-side cache hits included")
         if not args.no_batch:
             roofline["copy_GBps"] = round(copy_peak_gbps(), 1)
     batched = None
+    configs = None
     if not args.no_batch and args.workload == "plain_large":
+        configs = config_legs(ctx)
         batched = batched_vs_plain(ctx, args.seed)
     minimal = None
     if spec["kind"] != "batch" and not args.no_batch:
@@ -480,6 +625,7 @@ def main():
                     for s in stats],
         "end_to_end": end_to_end,
         "minimal_dfa": minimal,
+        "configs": configs,
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,
