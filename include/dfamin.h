@@ -116,8 +116,8 @@ typedef struct {
   uint32_t rounds_executed;  /* refine_rounds + 1 (the last round finds no split) */
   uint32_t closure_levels;   /* closure levels built (L, or fewer when a letter reaches a repeated
                                 or identity level); for a one-letter instance refining by doubling
-                                under AUTO, the levels its rounds read, each built when first read;
-                                0 if no closure was built */
+                                under AUTO, the highest level read by a round that split a block
+                                (each level is built when first read); 0 if no closure was built */
   uint32_t closure_letters;  /* letters of Sigma^T kept for refinement (identity letters and
                                 repeated levels are dropped: they cannot split a block), else 0 */
   int32_t status;            /* per-instance status (batch): DFAMIN_OK or DFAMIN_E_BAD_DFA */

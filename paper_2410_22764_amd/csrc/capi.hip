@@ -366,7 +366,11 @@ int dfamin_minimal_dfa(dfamin_ctx* ctx, const dfamin_dfa* host_dfa, const dfamin
   uint32_t* outs[1] = {out};
   dfamin_result r{};
   const dfamin_opts o = opts_or_default(opts);
+  // the reachability search and the quotient read the round engine's
+  // buffers (block ids, closure rows): this instance goes through it
+  ctx->c.engine.no_fused = true;
   rc = run_host_batch(ctx->c, 1, host_dfa, o, outs, &r);
+  ctx->c.engine.no_fused = false;
   if (rc != DFAMIN_OK) return rc;
   dfamin::MinimalInfo mi;
   const uint32_t* d_delta = nullptr;

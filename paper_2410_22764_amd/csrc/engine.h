@@ -109,8 +109,27 @@ class Engine {
   bool fixed() const { return fixed_base_ != nullptr; }
 
  private:
+  // Instances of `in` in small_ ones minimized whole by the fused kernels
+  // and the others by the round engine (run_path).
+  int run_all(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+              std::vector<InstOutcome>& res);
+  // nonid: the non-identity letters of each instance when the call has
+  // already validated them (validation is then skipped), else nullptr.
   int run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
-               std::vector<InstOutcome>& res);
+               std::vector<InstOutcome>& res, const std::vector<std::vector<uint32_t>>* nonid = nullptr);
+  // Validation of every instance of in_ (entries < n) and its non-identity
+  // letters (nonid_); DFAMIN_E_BAD_DFA marks res[i].status of bad ones.
+  int validate(hipStream_t s, std::vector<InstOutcome>& res);
+  // Largest instance the fused kernels take under these options (0: none).
+  uint32_t fused_limit(const dfamin_opts& opts) const;
+  // Queues the fused kernels for the instances `which` of `in` and the copy
+  // of their results to h_fres_ (read after the stream has drained).
+  int fused_issue(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,
+                  const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
+  // Results of fused_issue's instances: res entries of the finished ones,
+  // the handed-back ones in handoff; DFAMIN_E_BAD_DFA / _E_INTERNAL.
+  int fused_collect(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,
+                    std::vector<InstOutcome>& res, std::vector<uint32_t>& handoff);
   int ensure(DevBuf& b, size_t bytes);
   int ensure_host(HostBuf& b, size_t bytes);
   // Closure level storage a call may still take: half of the context's
@@ -213,6 +232,15 @@ class Engine {
                     uint64_t& executed);
   DevBuf d_qdbl_;   // per-instance doubling state of queued rounds
   HostBuf h_qdbl_;
+  // fused kernels: jobs in class order, their results, and where each sits
+  DevBuf d_fjobs_, d_fres_;
+  HostBuf h_fjobs_, h_fres_;
+  std::vector<uint32_t> fused_pos_;  // per entry of `which`: index in the job array
+ public:
+  // Set by callers that read the round engine's buffers after run() (the
+  // minimal DFA): every instance then goes through the round engine.
+  bool no_fused = false;
+ private:
   // fixed-region mode (set_fixed_region)
   char* fixed_base_ = nullptr;
   size_t fixed_cap_ = 0, fixed_off_ = 0;

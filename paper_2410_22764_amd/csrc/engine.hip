@@ -134,7 +134,7 @@ Engine::~Engine() {
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_};
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_};
   // device buffers of the fixed-region mode belong to the region
   if (!fixed()) {
     for (DevBuf* b : bufs)
@@ -143,7 +143,7 @@ Engine::~Engine() {
       if (b.p) (void)hipFree(b.p);
   }
   HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_rb_, &h_qdbl_,
-                   &stage_[0].buf, &stage_[1].buf};
+                   &stage_[0].buf, &stage_[1].buf, &h_fjobs_, &h_fres_};
   for (HostBuf* b : hb)
     if (b->p) (void)hipHostFree(b->p);
 }
@@ -154,7 +154,7 @@ uint64_t Engine::device_bytes() const {
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                           &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                           &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_};
+                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -231,7 +231,7 @@ int Engine::ensure_host(HostBuf& b, size_t bytes) {
 int Engine::set_fixed_region(void* base, size_t cap, size_t host_bytes) {
   if (!base || fixed() || device_bytes() != 0) return DFAMIN_E_INTERNAL;
   HostBuf* hb[] = {&h_ctrl_, &h_flags_, &h_results_, &h_counts_, &h_jobs_, &h_rb_, &h_qdbl_,
-                   &stage_[0].buf, &stage_[1].buf};
+                   &stage_[0].buf, &stage_[1].buf, &h_fjobs_, &h_fres_};
   for (HostBuf* b : hb) TRY(ensure_host(*b, host_bytes));
   if (!ev_rb_) HIP(hipEventCreateWithFlags(&ev_rb_, hipEventDisableTiming));
   fixed_base_ = static_cast<char*>(base);
@@ -246,7 +246,8 @@ void Engine::reset_fixed_region() {
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_ctrl_, &d_refine_, &d_counts_};
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_ctrl_, &d_refine_, &d_counts_,
+                    &d_fjobs_, &d_fres_};
   for (DevBuf* b : bufs) *b = DevBuf{};
   closure_bufs_.clear();
   fixed_off_ = 0;
@@ -511,8 +512,8 @@ int Engine::queued_rounds(uint64_t m, uint32_t tbits, int variant, int items, ui
     launch_compact(batch, a, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
                    d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(), b,
                    d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), items, s, 1);
-    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
-                     d_ctrl_.as<Ctrl>(), s, nullptr, 0, 1);
+    launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(),
+                     dq ? const_cast<uint32_t*>(dq->last) : nullptr, d_ctrl_.as<Ctrl>(), s, nullptr, 0, 1);
     if (dq) launch_queue_advance(*dq, d_ctrl_.as<Ctrl>(), s);
     launch_round_step(d_ctrl_.as<Ctrl>(), s);
   };
@@ -703,7 +704,6 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         for (uint32_t l = built[i] + 1; l <= lvl; ++l) todo.push_back({i, l, l - built[i] - 1});
         built[i] = lvl;
       }
-      used[i] = std::max(used[i], lvl);
       if (desc_[i].rows_off != row_base_[i] + lvl || desc_[i].kp != 1) {
         desc_[i].rows_off = row_base_[i] + lvl;
         desc_[i].kp = 1;
@@ -846,7 +846,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     if (queue_dbl) {
       const uint32_t T = (uint32_t)alist.size();
       const size_t bytes = 8ull * T + 36ull * T;
-      TRY(ensure(d_qdbl_, bytes));
+      TRY(ensure(d_qdbl_, bytes + 4ull * I));  // then one changed flag per instance
       TRY(ensure_host(h_qdbl_, bytes));
       uint64_t* hmj = h_qdbl_.as<uint64_t>();
       uint32_t* h32 = reinterpret_cast<uint32_t*>(hmj + T);
@@ -883,6 +883,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       dq.used = d32 + 6 * T;
       dq.n = d32 + 7 * T;
       dq.wgoff = d32 + 8 * T;
+      dq.last = d32 + 9 * T;
       dq.count = T;
       dq.wgs = wgs;
     }
@@ -1081,6 +1082,11 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       if (cnt_ok[i]) ub[i] = std::max<uint64_t>(cnt[i], 1);
       mj[i] += dbl[i] ? step[i] : 1;
       active[i] = rc[i] == rounds;
+      // closure levels reported: the highest one a splitting round read
+      if (dbl[i] && active[i]) used[i] = std::max<uint32_t>(used[i], floor_log2_u64(step[i]));
+      // every block a singleton: stable, whatever the other instances do
+      // (it plans no further level and reads none)
+      if (cnt_ok[i] && cnt[i] >= in_[i].n) active[i] = 0;
     }
     alist.erase(std::remove_if(alist.begin(), alist.end(), [&](uint32_t i) { return !active[i]; }), alist.end());
     std::swap(cur, nxt);
@@ -1284,9 +1290,175 @@ int Engine::minimal_dfa(const dfamin_opts& opts, hipStream_t s, uint32_t nb, uin
   return DFAMIN_OK;
 }
 
+// ---------------------------------------------------------- fused kernels
+uint32_t Engine::fused_limit(const dfamin_opts& opts) const {
+  // the round engine's testing knobs (hash width, table insertion order)
+  // and queued rounds concern its own rounds: those calls keep to it
+  if (no_fused || opts.method != DFAMIN_METHOD_SIGNATURE || (opts.flags & DFAMIN_FLAG_QUEUE)) return 0;
+  if (std::getenv("DFAMIN_HASH_BITS") || std::getenv("DFAMIN_CAS_FIRST")) return 0;
+  uint32_t lim = kFusedMaxStates;
+  if (const char* e = std::getenv("DFAMIN_FUSED_MAX_STATES")) {  // testing: 0 turns the fused path off
+    const long v = std::atol(e);
+    lim = v <= 0 ? 0u : (uint32_t)std::min<long>(v, (long)kFusedMaxStates);
+  }
+  return lim;
+}
+
+int Engine::fused_issue(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,
+                        const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s) {
+  const size_t F = which.size();
+  TRY(ensure(d_fjobs_, F * sizeof(FusedJob)));
+  TRY(ensure(d_fres_, F * sizeof(FusedRes)));
+  TRY(ensure_host(h_fjobs_, F * sizeof(FusedJob)));
+  TRY(ensure_host(h_fres_, F * sizeof(FusedRes)));
+  // jobs grouped by size class, largest class first
+  FusedJob* hj = h_fjobs_.as<FusedJob>();
+  fused_pos_.assign(F, 0);
+  uint32_t at = 0, start[4] = {0, 0, 0, 0};
+  double bytes = 0;
+  for (int cls = 2; cls >= 0; --cls) {
+    start[cls] = at;
+    for (size_t w = 0; w < F; ++w) {
+      const InstInput& x = in[which[w]];
+      if (fused_class(x.n) != cls) continue;
+      FusedJob& J = hj[at];
+      J.delta = reinterpret_cast<uint64_t>(x.delta);
+      J.accept = reinterpret_cast<uint64_t>(x.accept);
+      J.out = reinterpret_cast<uint64_t>(x.out);
+      J.n = x.n;
+      J.k = x.k;
+      J.q0 = x.q0;
+      J.closure = x.closure;
+      uint32_t L = floor_log2_u32(x.n);
+      if (opts.max_levels && opts.max_levels < L) L = opts.max_levels;
+      J.levels = L;
+      J.auto_rounds = opts.auto_rounds ? opts.auto_rounds : kDefaultAutoRounds;
+      J.max_rounds = (uint32_t)std::min<uint64_t>(max_rounds, 0xFFFFFFFFull);
+      J.pad = 0;
+      fused_pos_[w] = at++;
+      // transitions read once for validation, accept bits, the output write
+      bytes += 4.0 * x.n * x.k + x.n / 8.0 + 4.0 * x.n;
+    }
+  }
+  start[3] = at;
+  launch_copy_bytes(d_fjobs_.p, h_fjobs_.dp, F * sizeof(FusedJob), s);
+  Profiler& prof = ctx_->prof;
+  prof.begin(s, "fused", bytes);
+  for (int cls = 2; cls >= 0; --cls) {
+    const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
+    launch_fused(d_fjobs_.as<FusedJob>() + b, d_fres_.as<FusedRes>() + b, e - b, cls, s);
+  }
+  prof.end(s);
+  HIP(hipGetLastError());
+  return readback(h_fres_, d_fres_.p, F * sizeof(FusedRes), s);
+}
+
+int Engine::fused_collect(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,
+                          std::vector<InstOutcome>& res, std::vector<uint32_t>& handoff) {
+  (void)in;
+  const FusedRes* r = h_fres_.as<FusedRes>();
+  int rc = DFAMIN_OK;
+  for (size_t w = 0; w < which.size(); ++w) {
+    const FusedRes& f = r[fused_pos_[w]];
+    InstOutcome& o = res[which[w]];
+    switch (f.status) {
+      case kFusedOk:
+        o.num_blocks = f.num_blocks;
+        o.initial_block = f.initial_block;
+        o.refine_rounds = f.refine_rounds;
+        o.rounds_executed = f.refine_rounds + 1;
+        // a doubling instance reports the levels its rounds read, as the
+        // round engine does
+        o.closure_levels = f.doubling ? f.levels_used : 0;
+        o.closure_letters = f.doubling ? f.levels_used + 1 : 0;
+        o.status = DFAMIN_OK;
+        break;
+      case kFusedHandOff:
+        handoff.push_back(which[w]);
+        break;
+      case kFusedBad:
+        o.status = DFAMIN_E_BAD_DFA;
+        if (rc == DFAMIN_OK) rc = DFAMIN_E_BAD_DFA;
+        break;
+      default:
+        rc = DFAMIN_E_INTERNAL;
+        break;
+    }
+  }
+  return rc;
+}
+
+// Small instances are minimized whole by the fused kernels (one workgroup
+// each, every round in LDS), the others by the round engine.  A single
+// small instance is validated inside its kernel; a batch is validated as a
+// whole first, so that a bad instance leaves every output untouched.  The
+// fused kernels go to the stream ahead of the round engine's work; an
+// instance they hand back (it needs closure letters) then runs through the
+// round engine as well.
+int Engine::run_all(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+                    std::vector<InstOutcome>& res) {
+  const size_t I = in.size();
+  const uint32_t lim = fused_limit(opts);
+  std::vector<uint32_t> small, big;
+  uint32_t nmax = 0;
+  uint64_t N = 0;
+  for (size_t i = 0; i < I; ++i) {
+    nmax = std::max(nmax, in[i].n);
+    N += in[i].n;
+    const bool ok = in[i].n <= lim && in[i].k <= kFusedMaxLetters &&
+                    (in[i].closure == DFAMIN_CLOSURE_AUTO || in[i].closure == DFAMIN_CLOSURE_OFF);
+    (ok ? small : big).push_back((uint32_t)i);
+  }
+  if (small.empty() || N >= kMaxStates) return run_path(in, opts, s, res);
+  const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
+  res.assign(I, InstOutcome{});
+  std::vector<uint32_t> handoff;
+  auto subset = [&](const std::vector<uint32_t>& idx, std::vector<InstInput>& sub,
+                    std::vector<std::vector<uint32_t>>& sub_nonid, const std::vector<std::vector<uint32_t>>& all) {
+    sub.clear();
+    sub_nonid.clear();
+    for (uint32_t i : idx) {
+      sub.push_back(in[i]);
+      sub_nonid.push_back(all[i]);
+    }
+  };
+  auto run_subset = [&](const std::vector<uint32_t>& idx, const std::vector<std::vector<uint32_t>>& all) {
+    std::vector<InstInput> sub;
+    std::vector<std::vector<uint32_t>> sub_nonid;
+    subset(idx, sub, sub_nonid, all);
+    std::vector<InstOutcome> sub_res;
+    const int rc = run_path(sub, opts, s, sub_res, &sub_nonid);
+    if (rc == DFAMIN_OK)
+      for (size_t t = 0; t < idx.size(); ++t) res[idx[t]] = sub_res[t];
+    return rc;
+  };
+  if (I == 1) {
+    stage_idle();
+    TRY(fused_issue(in, small, opts, max_rounds, s));
+    HIP(stream_wait(s));
+    ctx_->prof.collect();
+    TRY(fused_collect(in, small, res, handoff));
+    if (handoff.empty()) return DFAMIN_OK;
+    return run_path(in, opts, s, res);
+  }
+  in_ = in;
+  stage_idle();
+  stage_cur_ = 0;
+  TRY(validate(s, res));
+  const std::vector<std::vector<uint32_t>> nonid_all = nonid_;
+  TRY(fused_issue(in, small, opts, max_rounds, s));
+  if (!big.empty()) TRY(run_subset(big, nonid_all));
+  HIP(stream_wait(s));
+  ctx_->prof.collect();
+  TRY(fused_collect(in, small, res, handoff));
+  if (!handoff.empty()) TRY(run_subset(handoff, nonid_all));
+  return DFAMIN_OK;
+}
+
 int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
                 std::vector<InstOutcome>& res) {
-  const int rc = run_path(in, opts, s, res);
+  if (fixed()) reset_fixed_region();
+  const int rc = run_all(in, opts, s, res);
   // A call that stops early may leave work queued behind its last wait (the
   // next round's level passes and table clear): let it finish before the
   // buffers are handed to another call.
@@ -1294,31 +1466,11 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
   return rc;
 }
 
-int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
-                     std::vector<InstOutcome>& res) {
-  in_ = in;
+// Validation (Section 2: every transition target < n) and the non-identity
+// letters of every instance of in_: one row job per (instance, letter).
+int Engine::validate(hipStream_t s, std::vector<InstOutcome>& res) {
   const size_t I = in_.size();
-  res.assign(I, InstOutcome{});
-  if (I == 0) return DFAMIN_OK;
-  const bool batch = I > 1;
-  uint64_t N = 0;
-  uint32_t nmax = 0;
-  for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
-  if (N >= kMaxStates) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
-  N_ = N;
-  if (fixed()) reset_fixed_region();
-  closure_cursor_ = 0;
-  // the previous call ended with its stream drained (run() drains on errors)
-  stage_idle();
-  stage_cur_ = 0;
   Profiler& prof = ctx_->prof;
-  // host time per phase of the call (printed with DFAMIN_TRACE)
-  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
-  auto now = [] { return std::chrono::steady_clock::now(); };
-  auto us = [](auto a, auto b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
-  const auto t_start = now();
-
-  // ---- 1. validation + identity letters: one row job per (instance, letter)
   // (the job vectors are members, so a call of the same shape allocates nothing)
   size_t njobs = 0;
   for (auto& x : in_) njobs += x.k;
@@ -1357,11 +1509,9 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     prof.end(s);
     HIP(hipGetLastError());
   }
-  const auto t_issue = now();
   TRY(readback(h_flags_, d_flags_.p, jobs.size() * 4, s));
   HIP(stream_wait(s));
   stage_idle();
-  const auto t_vwait = now();
   prof.collect();
   bool any_bad = false;
   nonid_.resize(I);
@@ -1382,7 +1532,38 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
       }
     }
   }
-  if (any_bad) return DFAMIN_E_BAD_DFA;
+  return any_bad ? DFAMIN_E_BAD_DFA : DFAMIN_OK;
+}
+
+int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, hipStream_t s,
+                     std::vector<InstOutcome>& res, const std::vector<std::vector<uint32_t>>* nonid) {
+  in_ = in;
+  const size_t I = in_.size();
+  res.assign(I, InstOutcome{});
+  if (I == 0) return DFAMIN_OK;
+  const bool batch = I > 1;
+  uint64_t N = 0;
+  uint32_t nmax = 0;
+  for (auto& x : in_) { N += x.n; nmax = std::max(nmax, x.n); }
+  if (N >= kMaxStates) return DFAMIN_E_INVAL;  // state ids are 31-bit in hash slots
+  N_ = N;
+  closure_cursor_ = 0;
+  // the previous call ended with its stream drained (run() drains on errors)
+  stage_idle();
+  stage_cur_ = 0;
+  Profiler& prof = ctx_->prof;
+  // host time per phase of the call (printed with DFAMIN_TRACE)
+  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
+  auto now = [] { return std::chrono::steady_clock::now(); };
+  auto us = [](auto a, auto b) { return std::chrono::duration<double, std::micro>(b - a).count(); };
+  const auto t_start = now();
+
+  // ---- 1. validation + identity letters (unless the call has done it)
+  if (nonid) {
+    nonid_ = *nonid;
+  } else {
+    TRY(validate(s, res));
+  }
   const auto t_valid = now();
 
   // ---- 2. descriptors and signature letters
@@ -1527,10 +1708,10 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   if (h_ctrl_.as<Ctrl>()->fault) return DFAMIN_E_INTERNAL;
   if (trace)
     std::fprintf(stderr,
-                 "[dfamin] call of %zu instances, host us: validation %.0f (issue %.0f, wait %.0f, flags %.0f), "
+                 "[dfamin] call of %zu instances, host us: validation %.0f, "
                  "setup %.0f (descriptors %.0f, closure %.0f, buffers %.0f, layout %.0f, init %.0f), "
                  "rounds %.0f, numbering %.0f\n",
-                 I, us(t_start, t_valid), us(t_start, t_issue), us(t_issue, t_vwait), us(t_vwait, t_valid),
+                 I, us(t_start, t_valid),
                  us(t_valid, t_setup), us(t_valid, t_desc), us(t_desc, t_closure), us(t_closure, t_bufs),
                  us(t_bufs, t_layout), us(t_layout, t_setup), us(t_setup, t_rounds), us(t_rounds, now()));
   const ResultDev* r = h_results_.as<ResultDev>();

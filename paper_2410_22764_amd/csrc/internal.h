@@ -146,6 +146,37 @@ struct ResultDev {
   uint32_t pad;
 };
 
+// Whole minimization of small instances, one workgroup each (fused.hip).
+// Instances of up to kFusedMaxStates states and kFusedMaxLetters letters,
+// closure OFF or AUTO, signature rounds.
+struct FusedJob {
+  uint64_t delta, accept, out;  // device addresses (letter-major rows, bitmap, n outputs)
+  uint32_t n, k, q0, closure;
+  uint32_t levels;       // highest closure level a doubling round may read (floor(log2 n) or max_levels)
+  uint32_t auto_rounds;  // AUTO: rounds after which an instance with >= 2 non-identity letters
+                         // that is still splitting is handed back to the round engine
+  uint32_t max_rounds;   // round cap
+  uint32_t pad;
+};
+struct FusedRes {
+  int32_t status;  // kFused*
+  uint32_t num_blocks, initial_block, refine_rounds;
+  uint32_t levels_used;  // doubling: the highest closure level a round read
+  uint32_t doubling;     // 1: refined by doubling (one non-identity letter, AUTO)
+  uint32_t pad[2];
+};
+constexpr int32_t kFusedOk = 0;
+constexpr int32_t kFusedBad = 1;       // some entry >= n; the output is not written
+constexpr int32_t kFusedHandOff = 2;   // needs closure letters: run it through the round engine
+constexpr int32_t kFusedRoundCap = 3;  // max_rounds reached
+constexpr int32_t kFusedFault = 4;     // a bounded probe ran out (never expected)
+constexpr uint32_t kFusedMaxStates = 16384;
+constexpr uint32_t kFusedMaxLetters = 32;
+// size class of a fused instance: 0 up to 2,048 states (256 threads),
+// 1 up to 8,192 (512 threads), 2 up to 16,384 (1,024 threads, 160 KB of LDS)
+inline int fused_class(uint32_t n) { return n <= 2048 ? 0 : (n <= 8192 ? 1 : 2); }
+void launch_fused(const FusedJob* jobs, FusedRes* res, uint32_t njobs, int cls, hipStream_t s);
+
 // Row-check flag bits.
 constexpr uint32_t kFlagBad = 1u;      // entry >= n
 constexpr uint32_t kFlagNonId = 2u;    // entry != its own index
@@ -226,11 +257,13 @@ void launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 // round, plan points the descriptor at this round's level (and notes a
 // level to build: at most one, since j at least doubles) and levels builds
 // it (dst = src o src, Algorithm 5) over the instance's states; after a
-// round that was not redone, advance adds 2^l to j.  All return at once when
-// ctrl->stop is set.
+// round that was not redone, advance adds 2^l to j and, if the instance
+// split a block in it, raises its highest level read (used).  All return at
+// once when ctrl->stop is set.
 struct QueueDbl {
   uint64_t* mj;
   uint32_t *list, *built, *lmax, *rbase, *need, *lv, *used, *n, *wgoff;
+  uint32_t* last;  // per instance (all of the call): split a block in this round
   uint32_t count, wgs;
 };
 void launch_queue_plan(const QueueDbl& q, InstDesc* desc, const Ctrl* ctrl, hipStream_t s);

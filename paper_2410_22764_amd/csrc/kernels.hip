@@ -796,7 +796,6 @@ __global__ __launch_bounds__(kBlock) void k_queue_plan(QueueDbl q, InstDesc* __r
   q.need[t] = lvl > q.built[t] ? lvl : 0u;
   if (lvl > q.built[t]) q.built[t] = lvl;
   q.lv[t] = lvl;
-  if (lvl > q.used[t]) q.used[t] = lvl;
 }
 
 __global__ __launch_bounds__(kBlock) void k_queue_levels(QueueDbl q, const uint64_t* __restrict__ rows,
@@ -822,6 +821,7 @@ __global__ __launch_bounds__(kBlock) void k_queue_advance(QueueDbl q, const Ctrl
   const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
   if (t >= q.count || ctrl->stop || ctrl->collision) return;
   q.mj[t] += 1ull << q.lv[t];
+  if (q.last[q.list[t]] && q.lv[t] > q.used[t]) q.used[t] = q.lv[t];  // the highest level a splitting round read
 }
 
 __global__ void k_round_step(Ctrl* __restrict__ ctrl) {

@@ -23,6 +23,16 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(autouse=True, params=["fused", "rounds"])
+def engine_path(request, monkeypatch):
+    """Every test here runs twice: instances of up to 16,384 states through
+    the fused one-workgroup kernels (the default), and every instance
+    through the round engine."""
+    if request.param == "rounds":
+        monkeypatch.setenv("DFAMIN_FUSED_MAX_STATES", "0")
+    return request.param
+
+
 def _run(ctx, d, closure="off", **kw):
     from paper_2410_22764_amd import dfamin
     print(f"[case] {d.name} n={d.n} k={d.k} closure={closure}", flush=True)
