@@ -273,6 +273,13 @@ struct Resident {
   // pointers to all L level buffers; `built` of them are filled)
   bool lazy = false;
   uint32_t built = 0;
+  uint32_t used = 0;  // the highest level a round that split a block read
+  bool uploaded = false;  // inputs on the device (or on their way: see `up`)
+  // in the resident set (joined): only then do its descriptor, states and
+  // output take part in rounds and retirement; until then it only holds
+  // its slot and buffers while its inputs upload
+  bool joined = false;
+  hipEvent_t up = nullptr;  // recorded behind the input upload
 };
 
 }  // namespace
@@ -309,6 +316,12 @@ struct Serving::Impl {
 
   // ---- device state (worker thread only)
   hipStream_t stream = nullptr;
+  // Inputs of admitted requests go to the device on their own stream while
+  // the resident set's rounds run on `stream`; a request joins once the
+  // event behind its upload has completed.
+  hipStream_t ustream = nullptr;
+  std::vector<Resident*> staged;  // admitted, inputs on their way (in admission order)
+  std::vector<hipEvent_t> free_events;
   uint64_t cap = 0;  // state arena capacity
   DevicePool pool;
   RangeAlloc arena;
@@ -327,8 +340,8 @@ struct Serving::Impl {
   size_t rows_cap = 0;
   uint64_t table_cap = 0;
   // scratch that grows
-  DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux;
-  HostBuf h_flags, h_ctrl, h_last, h_results;
+  DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux, s_fjobs, s_fres;
+  HostBuf h_flags, h_ctrl, h_last, h_results, h_fres;
 
   void shutdown() {
     {
@@ -381,6 +394,8 @@ struct Serving::Impl {
     return true;
   }
   void free_device() {
+    if (ustream) (void)hipStreamSynchronize(ustream);  // uploads still reading host staging
+    staged.clear();
     for (Resident* r : slots)
       if (r) release_resident(r);
     slots.clear();
@@ -389,19 +404,23 @@ struct Serving::Impl {
                    &d_minF, &d_minN, &d_ctrl, &d_results, &d_totals};
     for (void** p : ps)
       if (*p) { (void)hipFree(*p); *p = nullptr; }
-    DevBuf* db[] = {&s_jobs, &s_off, &s_flags, &s_wg, &s_part, &s_slot, &s_aux};
+    DevBuf* db[] = {&s_jobs, &s_off, &s_flags, &s_wg, &s_part, &s_slot, &s_aux, &s_fjobs, &s_fres};
     for (DevBuf* b : db)
       if (b->p) { (void)hipFree(b->p); b->p = nullptr; b->cap = 0; }
-    HostBuf* hb[] = {&h_flags, &h_ctrl, &h_last, &h_results};
+    HostBuf* hb[] = {&h_flags, &h_ctrl, &h_last, &h_results, &h_fres};
     for (HostBuf* b : hb)
       if (b->p) { (void)hipHostFree(b->p); b->p = nullptr; b->cap = 0; }
     pool.release_all();
+    for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+    free_events.clear();
     if (stream) { (void)hipStreamDestroy(stream); stream = nullptr; }
+    if (ustream) { (void)hipStreamDestroy(ustream); ustream = nullptr; }
   }
 
   int init_device() {
     if (hipSetDevice(ctx->device) != hipSuccess) return DFAMIN_E_DEVICE;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return DFAMIN_E_DEVICE;
+    if (hipStreamCreateWithFlags(&ustream, hipStreamNonBlocking) != hipSuccess) return DFAMIN_E_DEVICE;
     // arena sized from the budget: ~37 bytes per state of fixed buffers,
     // 16 per state of hash table, the rest for request buffers
     cap = kDefaultArenaStates;
@@ -445,6 +464,7 @@ struct Serving::Impl {
   }
 
   void release_resident(Resident* r) {
+    if (r->up) free_events.push_back(r->up);
     pool.free(r->d_delta, r->sz_delta);
     pool.free(r->d_accept, r->sz_accept);
     pool.free(r->d_out, r->sz_out);
@@ -555,7 +575,7 @@ struct Serving::Impl {
     rows_host.clear();
     for (uint32_t s = 0; s < kSlots; ++s) {
       Resident* r = slots[s];
-      if (!r) continue;
+      if (!r || !r->joined) continue;
       desc[s].rows_off = (uint32_t)rows_host.size();
       desc[s].kp = (uint32_t)r->rows.size();
       if (r->dbl) {  // the single closure level 2^l <= mj + 1
@@ -638,10 +658,134 @@ struct Serving::Impl {
     return DFAMIN_OK;
   }
 
-  // Bring newly admitted requests onto the device.
+  // Inputs of newly admitted requests go to the device on the upload
+  // stream, each followed by its event.
+  int stage(const std::vector<Resident*>& rs) {
+    for (Resident* r : rs) {
+      if (free_events.empty()) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return DFAMIN_E_DEVICE;
+        free_events.push_back(e);
+      }
+      r->up = free_events.back();
+      free_events.pop_back();
+      if (hipMemcpyAsync(r->d_delta, r->req->delta(), r->sz_delta, hipMemcpyHostToDevice, ustream) !=
+              hipSuccess ||
+          hipMemcpyAsync(r->d_accept, r->req->accept(), r->req->accept_bytes(), hipMemcpyHostToDevice,
+                         ustream) != hipSuccess ||
+          hipEventRecord(r->up, ustream) != hipSuccess)
+        return DFAMIN_E_DEVICE;
+      r->uploaded = true;
+      staged.push_back(r);
+    }
+    return DFAMIN_OK;
+  }
+
+  // A request of up to kFusedMaxStates states (closure OFF or AUTO) is
+  // minimized whole by one workgroup of the fused kernel as it joins: no
+  // rounds of the resident set, and it is done when its inputs and output
+  // have crossed.  The kernel hands back an instance that needs closure
+  // letters; those join the resident set as any other request.
+  static bool fusable(const Request& q) {
+    return q.n <= kFusedMaxStates && q.k <= kFusedMaxLetters &&
+           (q.opts.closure == DFAMIN_CLOSURE_AUTO || q.opts.closure == DFAMIN_CLOSURE_OFF) &&
+           q.opts.method == DFAMIN_METHOD_SIGNATURE;
+  }
+  int join_fused(std::vector<Resident*>& fs, std::vector<Resident*>& handed_back) {
+    const size_t F = fs.size();
+    std::vector<FusedJob> jobs(F);
+    std::vector<uint32_t> pos(F);
+    uint32_t at = 0, start[4] = {0, 0, 0, 0};
+    for (int cls = 2; cls >= 0; --cls) {
+      start[cls] = at;
+      for (size_t w = 0; w < F; ++w) {
+        Resident* r = fs[w];
+        const Request& q = *r->req;
+        if (fused_class(q.n) != cls) continue;
+        FusedJob& J = jobs[at];
+        J = FusedJob{};
+        J.delta = reinterpret_cast<uint64_t>(r->d_delta);
+        J.accept = reinterpret_cast<uint64_t>(r->d_accept);
+        J.out = reinterpret_cast<uint64_t>(r->d_out);
+        J.n = q.n;
+        J.k = q.k;
+        J.q0 = q.q0;
+        J.closure = q.opts.closure;
+        uint32_t L = floor_log2_u32(q.n);
+        if (q.opts.max_levels && q.opts.max_levels < L) L = q.opts.max_levels;
+        J.levels = L;
+        J.auto_rounds = q.opts.auto_rounds ? q.opts.auto_rounds : kDefaultAutoRounds;
+        J.max_rounds = q.opts.max_rounds ? q.opts.max_rounds : q.n + 1u;
+        pos[w] = at++;
+      }
+    }
+    start[3] = at;
+    if (!grow(s_fjobs, F * sizeof(FusedJob)) || !grow(s_fres, F * sizeof(FusedRes)) ||
+        !grow_host(h_fres, F * sizeof(FusedRes)))
+      return DFAMIN_E_NOMEM;
+    for (Resident* r : fs) {
+      if (r->uploaded) continue;
+      if (hipMemcpyAsync(r->d_delta, r->req->delta(), r->sz_delta, hipMemcpyHostToDevice, stream) !=
+              hipSuccess ||
+          hipMemcpyAsync(r->d_accept, r->req->accept(), r->req->accept_bytes(), hipMemcpyHostToDevice,
+                         stream) != hipSuccess)
+        return DFAMIN_E_DEVICE;
+      r->uploaded = true;
+    }
+    if (hipMemcpyAsync(s_fjobs.p, jobs.data(), F * sizeof(FusedJob), hipMemcpyHostToDevice, stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    for (int cls = 2; cls >= 0; --cls) {
+      const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
+      launch_fused(s_fjobs.as<FusedJob>() + b, s_fres.as<FusedRes>() + b, e - b, cls, stream);
+    }
+    if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
+    // every output comes back with the results (a bad or handed-back one is
+    // simply not published)
+    for (Resident* r : fs) {
+      if (!r->req->out.make(pinned, 4ull * r->req->n)) return DFAMIN_E_NOMEM;
+      if (hipMemcpyAsync(r->req->out.data(), r->d_out, 4ull * r->req->n, hipMemcpyDeviceToHost, stream) !=
+          hipSuccess)
+        return DFAMIN_E_DEVICE;
+    }
+    if (hipMemcpyAsync(h_fres.p, s_fres.p, F * sizeof(FusedRes), hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        stream_wait(stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    const FusedRes* fr = h_fres.as<FusedRes>();
+    for (size_t w = 0; w < F; ++w) {
+      Resident* r = fs[w];
+      const FusedRes& f = fr[pos[w]];
+      if (f.status == kFusedHandOff) {
+        handed_back.push_back(r);
+        continue;
+      }
+      auto req = r->req;
+      int st = DFAMIN_OK;
+      if (f.status == kFusedOk) {
+        dfamin_result& o = req->result;
+        o.num_blocks = f.num_blocks;
+        o.initial_block = f.initial_block;
+        o.refine_rounds = f.refine_rounds;
+        o.rounds_executed = f.refine_rounds + 1;
+        o.closure_levels = f.doubling ? f.levels_used : 0;
+        o.closure_letters = f.doubling ? f.levels_used + 1 : 0;
+        o.status = DFAMIN_OK;
+      } else {
+        st = f.status == kFusedBad ? DFAMIN_E_BAD_DFA : DFAMIN_E_INTERNAL;
+      }
+      req->in.release();
+      if (st != DFAMIN_OK) req->out.release();
+      const bool cancelled = req->cancelled;
+      release_resident(r);
+      finish(req, cancelled && st == DFAMIN_OK ? DFAMIN_E_CANCELLED : st);
+    }
+    return DFAMIN_OK;
+  }
+
+  // Bring newly admitted requests into the resident set.
   int join(std::vector<Resident*>& js) {
     // upload inputs
     for (Resident* r : js) {
+      if (r->uploaded) continue;
       if (hipMemcpyAsync(r->d_delta, r->req->delta(), r->sz_delta, hipMemcpyHostToDevice, stream) !=
               hipSuccess ||
           hipMemcpyAsync(r->d_accept, r->req->accept(), r->req->accept_bytes(), hipMemcpyHostToDevice,
@@ -706,6 +850,7 @@ struct Serving::Impl {
       D.accept = reinterpret_cast<uint64_t>(r->d_accept);
       D.out = reinterpret_cast<uint64_t>(r->d_out);
       D.sig = reinterpret_cast<uint64_t>(r->d_sig);
+      r->joined = true;  // its descriptor is set: layout and rounds include it from here
       ok.push_back(r);
       if (r->req->opts.closure == DFAMIN_CLOSURE_ON) need_closure.push_back(r);
       if (r->req->opts.closure == DFAMIN_CLOSURE_AUTO && r->nonid.size() == 1) (void)plan_lazy_levels(r);
@@ -814,8 +959,8 @@ struct Serving::Impl {
         o.initial_block = res[w].initial_block;
         o.refine_rounds = res[w].refine_rounds;
         o.rounds_executed = res[w].refine_rounds + 1;
-        o.closure_levels = !r->closure ? 0 : (r->lazy ? r->built : r->levels);
-        o.closure_letters = !r->closure ? 0 : (r->lazy ? r->built + 1 : (uint32_t)r->rows.size());
+        o.closure_levels = !r->closure ? 0 : (r->lazy ? r->used : r->levels);
+        o.closure_letters = !r->closure ? 0 : (r->lazy ? r->used + 1 : (uint32_t)r->rows.size());
         o.status = DFAMIN_OK;
       }
     }
@@ -834,7 +979,7 @@ struct Serving::Impl {
     bool dirty = false;
     for (uint32_t s = 0; s < kSlots; ++s) {
       Resident* r = slots[s];
-      if (r && !r->dead && r->req->cancelled) {
+      if (r && r->joined && !r->dead && r->req->cancelled) {
         r->dead = true;
         const uint32_t one = 1;
         if (hipMemcpyAsync(static_cast<uint32_t*>(d_dead) + s, &one, 4, hipMemcpyHostToDevice, stream) !=
@@ -897,12 +1042,13 @@ struct Serving::Impl {
     bool desc_dirty = false;
     for (uint32_t s = 0; s < kSlots; ++s) {
       Resident* r = slots[s];
-      if (!r) continue;
+      if (!r || !r->joined) continue;  // admitted, inputs still uploading
       r->rounds += 1;
       if (!last[s] || r->dead) {
         done.push_back(r);
         continue;
       }
+      if (r->dbl) r->used = std::max<uint32_t>(r->used, (uint32_t)__builtin_ctzll(r->step));
       r->mj += r->dbl ? r->step : 1;
       if (r->dbl) desc_dirty = true;  // next level
       if (desc[s].dsrc) {  // accept bits only describe the first round's partition
@@ -928,13 +1074,21 @@ struct Serving::Impl {
     return DFAMIN_OK;
   }
 
+  // a slot held (joined or still uploading)
   bool any_resident() const {
     for (Resident* r : slots)
       if (r) return true;
     return false;
   }
+  bool any_joined() const {
+    for (Resident* r : slots)
+      if (r && r->joined) return true;
+    return false;
+  }
 
   void fail_all(int rc) {
+    if (ustream) (void)hipStreamSynchronize(ustream);  // uploads still reading host staging
+    staged.clear();
     std::vector<std::shared_ptr<Request>> rs;
     {
       std::lock_guard<std::mutex> g(mu);
@@ -961,11 +1115,12 @@ struct Serving::Impl {
       }
       return;
     }
+    std::vector<Resident*> admitted;
     while (true) {
       std::vector<Resident*> joining;
       {
         std::unique_lock<std::mutex> lk(mu);
-        cv_work.wait(lk, [&] { return stop || !queue.empty() || any_resident(); });
+        cv_work.wait(lk, [&] { return stop || !queue.empty() || any_resident() || !staged.empty(); });
         if (stop) break;
         // admission by footprint, first come first served
         while (!queue.empty()) {
@@ -983,7 +1138,7 @@ struct Serving::Impl {
           const size_t fp = footprint(*q);
           const bool fits = slot < kSlots && pool.live() + fp <= pool.budget() && arena.alloc(q->n, &off);
           if (!fits) {
-            if (!any_resident() && joining.empty()) {
+            if (!any_resident() && admitted.empty() && staged.empty()) {
               // can never fit: reject instead of waiting forever
               queue.pop_front();
               q->status = DFAMIN_E_NOMEM;
@@ -1007,7 +1162,7 @@ struct Serving::Impl {
           slots[slot] = r;
           if (!r->d_delta || !r->d_accept || !r->d_out || !r->d_sig) {
             release_resident(r);
-            if (!any_resident() && joining.empty()) {
+            if (!any_resident() && admitted.empty() && staged.empty()) {
               queue.pop_front();
               q->status = DFAMIN_E_NOMEM;
               cv_done.notify_all();
@@ -1016,14 +1171,37 @@ struct Serving::Impl {
             break;
           }
           queue.pop_front();
-          joining.push_back(r);
+          admitted.push_back(r);
         }
       }
-      int rc = DFAMIN_OK;
+      int rc = stage(admitted);
+      admitted.clear();
+      // requests whose inputs are on the device join, in admission order;
+      // with nothing else to run, wait for the oldest upload
+      if (rc == DFAMIN_OK && !staged.empty()) {
+        if (!any_joined() && hipEventSynchronize(staged.front()->up) != hipSuccess) rc = DFAMIN_E_DEVICE;
+        size_t take = 0;
+        while (rc == DFAMIN_OK && take < staged.size()) {
+          const hipError_t e = hipEventQuery(staged[take]->up);
+          if (e == hipErrorNotReady) break;
+          if (e != hipSuccess) rc = DFAMIN_E_DEVICE;
+          ++take;
+        }
+        if (rc == DFAMIN_OK) {
+          joining.assign(staged.begin(), staged.begin() + take);
+          staged.erase(staged.begin(), staged.begin() + take);
+        }
+      }
       const auto t0 = std::chrono::steady_clock::now();
-      if (!joining.empty()) rc = join(joining);
+      if (!joining.empty()) {
+        std::vector<Resident*> fs, rest;
+        for (Resident* r : joining) (fusable(*r->req) ? fs : rest).push_back(r);
+        if (!fs.empty()) rc = join_fused(fs, rest);
+        joining.swap(rest);
+      }
+      if (rc == DFAMIN_OK && !joining.empty()) rc = join(joining);
       const auto t1 = std::chrono::steady_clock::now();
-      if (rc == DFAMIN_OK && any_resident()) rc = round();
+      if (rc == DFAMIN_OK && any_joined()) rc = round();
       const auto t2 = std::chrono::steady_clock::now();
       t_join += std::chrono::duration<double, std::micro>(t1 - t0).count();
       t_round += std::chrono::duration<double, std::micro>(t2 - t1).count();

@@ -178,3 +178,23 @@ def test_serving_pool_at_full_sizes_bit_exact(ctx):
     for d, e, (dg, rr) in zip(pool, reqs, mixed):
         alone, ra = dfamin.dfamin_minimize(ctx, d, "auto")
         assert digest(alone) == dg and ra["refine_rounds"] == rr, e
+
+
+def test_doubling_requests_report_as_alone(ctx):
+    """Chains under AUTO refine by doubling, in the fused kernel (up to
+    16,384 states) or in the resident set: each request's round count and
+    closure levels (the highest level a splitting round read) are those of
+    the same DFA minimised alone."""
+    from paper_2410_22764_amd import dfamin
+    ds = [W.permuted_chain_dfa(n, k, n + k) for n, k in [(3, 2), (900, 2), (16384, 3), (16385, 2), (70000, 4)]]
+    ds.append(W.random_dfa(3000, 1, 5))
+    print("[case] serving doubling requests", flush=True)
+    tickets = [dfamin.dfamin_submit(ctx, d, "auto") for d in ds]
+    for d, t in zip(ds, tickets):
+        rc, out, res = dfamin.dfamin_wait(ctx, t, d.n, timeout_us=20_000_000)
+        assert rc == dfamin.DFAMIN_OK, d.name
+        alone, ra = dfamin.dfamin_minimize(ctx, d, "auto")
+        assert np.array_equal(alone, out), d.name
+        for f in ("num_blocks", "initial_block", "refine_rounds", "rounds_executed", "closure_levels",
+                  "closure_letters"):
+            assert res[f] == ra[f], (d.name, f, res, ra)
