@@ -236,6 +236,12 @@ class Engine {
   DevBuf d_fjobs_, d_fres_;
   HostBuf h_fjobs_, h_fres_;
   std::vector<uint32_t> fused_pos_;  // per entry of `which`: index in the job array
+  // A batch's fused kernels run on their own stream beside the round
+  // engine's work (created at the first batch; not in fixed-region mode,
+  // which creates nothing after set-up): fused_ready_ on the caller's
+  // stream after validation, fused_done_ behind the results' copy.
+  hipStream_t fused_stream_ = nullptr;
+  hipEvent_t fused_ready_ = nullptr, fused_done_ = nullptr;
  public:
   // Set by callers that read the round engine's buffers after run() (the
   // minimal DFA): every instance then goes through the round engine.

@@ -126,6 +126,12 @@ int Profiler::copy_stats(dfamin_kernel_stat* out, int cap) const {
 
 // ------------------------------------------------------------------ Engine
 Engine::~Engine() {
+  if (fused_stream_) {
+    (void)hipStreamSynchronize(fused_stream_);
+    (void)hipStreamDestroy(fused_stream_);
+  }
+  if (fused_ready_) (void)hipEventDestroy(fused_ready_);
+  if (fused_done_) (void)hipEventDestroy(fused_done_);
   if (graph_exec_) (void)hipGraphExecDestroy(graph_exec_);
   if (queue_exec_) (void)hipGraphExecDestroy(queue_exec_);
   if (ev_rb_) (void)hipEventDestroy(ev_rb_);
@@ -1446,9 +1452,31 @@ int Engine::run_all(const std::vector<InstInput>& in, const dfamin_opts& opts, h
   stage_cur_ = 0;
   TRY(validate(s, res));
   const std::vector<std::vector<uint32_t>> nonid_all = nonid_;
-  TRY(fused_issue(in, small, opts, max_rounds, s));
-  if (!big.empty()) TRY(run_subset(big, nonid_all));
+  // With larger instances in the call, the fused kernels run on their own
+  // stream beside the round engine's rounds (whose host syncs leave the GPU
+  // idle now and then), after this call's validation.
+  hipStream_t fs = s;
+  // (with kernel timing on, everything stays on one stream: the profiler
+  // collects a launch's events after that stream's waits)
+  if (!big.empty() && !fixed() && !ctx_->prof.enabled()) {
+    if (!fused_stream_) {
+      HIP(hipStreamCreateWithFlags(&fused_stream_, hipStreamNonBlocking));
+      HIP(hipEventCreateWithFlags(&fused_ready_, hipEventDisableTiming));
+      HIP(hipEventCreateWithFlags(&fused_done_, hipEventDisableTiming));
+    }
+    HIP(hipEventRecord(fused_ready_, s));
+    HIP(hipStreamWaitEvent(fused_stream_, fused_ready_, 0));
+    fs = fused_stream_;
+  }
+  int frc = fused_issue(in, small, opts, max_rounds, fs);
+  if (frc == DFAMIN_OK && fs != s) frc = check_hip(hipEventRecord(fused_done_, fs));
+  if (frc == DFAMIN_OK && !big.empty()) frc = run_subset(big, nonid_all);
+  if (frc != DFAMIN_OK) {
+    if (fs != s && !ctx_->device_lost) (void)hipStreamSynchronize(fs);  // nothing of the call left queued
+    return frc;
+  }
   HIP(stream_wait(s));
+  if (fs != s) HIP(hipEventSynchronize(fused_done_));
   ctx_->prof.collect();
   TRY(fused_collect(in, small, res, handoff));
   if (!handoff.empty()) TRY(run_subset(handoff, nonid_all));
