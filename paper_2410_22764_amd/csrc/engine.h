@@ -192,6 +192,7 @@ class Engine {
   DevBuf d_inst_of_, d_block_, d_act_, d_act2_, d_slot_of_, d_nb_, d_keep_, d_rank_;
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
+  DevBuf d_notify_;  // one byte per state: a joiner marked this lone slot claimer
   DevBuf d_visit_, d_bfs_rows_, d_min_delta_, d_min_acc_;
   DevBuf d_lvl_, d_lvl_wg_, d_lvl_flags_;  // level jobs of lazily built closure levels
   DevBuf d_rb_;  // owns d_ctrl_, d_refine_ and d_counts_ (views into it, reset every run)

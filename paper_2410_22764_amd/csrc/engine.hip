@@ -140,7 +140,7 @@ Engine::~Engine() {
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_};
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_};
   // device buffers of the fixed-region mode belong to the region
   if (!fixed()) {
     for (DevBuf* b : bufs)
@@ -160,7 +160,7 @@ uint64_t Engine::device_bytes() const {
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                           &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                           &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_};
+                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -253,7 +253,7 @@ void Engine::reset_fixed_region() {
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
                     &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_ctrl_, &d_refine_, &d_counts_,
-                    &d_fjobs_, &d_fres_};
+                    &d_fjobs_, &d_fres_, &d_notify_};
   for (DevBuf* b : bufs) *b = DevBuf{};
   closure_bufs_.clear();
   fixed_off_ = 0;
@@ -968,7 +968,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                        d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
                        d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
-                       variant, s, (int)cas_bits_);
+                       variant, s, (int)cas_bits_, d_notify_.as<uint8_t>());
       prof.end(s);
     }
     prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
@@ -976,7 +976,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
                    d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
                    d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(), d_keep_.as<uint8_t>(),
                    d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                   d_status_.as<unsigned long long>(), ntiles, s);
+                   d_status_.as<unsigned long long>(), ntiles, s, 0,
+                   tuned_now ? nullptr : d_notify_.as<uint8_t>());
     prof.end(s);
     prof.begin(s, "compact", md * (4 + inst_b + 4 + 1 + 4));
     launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
@@ -1631,6 +1632,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   TRY(ensure(d_slot_of_, N * 4));
   TRY(ensure(d_nb_, N * 4));
   TRY(ensure(d_keep_, N));
+  TRY(ensure(d_notify_, N));
   TRY(ensure(d_rank_, (N + 1) * 4));
   const uint64_t max_tiles = scan_tiles(N, kScanItemsSmall) + 1;
   TRY(ensure(d_status_, max_tiles * 8));
@@ -1677,6 +1679,9 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   TRY(upload(d_inst_off_.p, inst_off.data(), I * 4, s));
   TRY(ensure(d_part_, (size_t)init_wgs * 8));
   HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
+  // joiners' marks of lone slot claimers (each round's resolve step returns
+  // the ones it reads to 0)
+  HIP(hipMemsetAsync(d_notify_.p, 0, N, s));
   HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
   HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
   // testing: force the table insertion order of every signature round

@@ -79,6 +79,11 @@ struct InstDesc {
 typedef unsigned long long Slot;
 constexpr uint32_t kSlotShared = 0x80000000u;
 constexpr uint32_t kSlotIndexMask = 0x7fffffffu;
+// slot_of[j] bit 31 (tables of at most 2^31 slots): state j claimed an empty
+// slot with no other state of its tile in its group.  Unless a later joiner
+// marked it in the round's notify bytes, it is then alone in its group, and
+// the resolve step needs no read of the slot.
+constexpr uint32_t kSlotClaimedAlone = 0x80000000u;
 
 // Control block shared by the round kernels and read by the host.  The flags
 // only go from 0 to 1 within a kernel (plain stores of one value); the tile
@@ -208,11 +213,13 @@ void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, 
 // stored dense_width (1, 2 or 4) bytes per state.  gmode bit 0 as above;
 // bits 1 and 2: hash-mode / exact-key states insert their group with a CAS
 // on the home slot before reading it (table_insert).
+// notify (nullable): one byte per global state, all 0 before the round; the
+// resolve step of the round returns them to 0.
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
                       uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s,
-                      int gmode = 0);
+                      int gmode = 0, uint8_t* notify = nullptr);
 // dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
 // instance's blocks in order of least member, dense_width bytes wide (every
 // number must fit).
@@ -226,7 +233,7 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
                     const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
-                    uint32_t ntiles, hipStream_t s, int gmode = 0);
+                    uint32_t ntiles, hipStream_t s, int gmode = 0, uint8_t* notify = nullptr);
 // dead (nullable): instances whose states leave the active list (cancelled).
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,

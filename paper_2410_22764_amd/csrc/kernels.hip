@@ -445,24 +445,37 @@ __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table
 // value just leads to a CAS that returns the current one, and slot words
 // change monotonically (claimed once, index only lowered within the same
 // instance, shared bit only set).
+//
+// `created` tells the caller that this call claimed an empty slot.  The
+// first state to join a slot that was not yet shared marks its claimer in
+// `notify` (nullable; one byte per global state id): a claimer left
+// unmarked is then known to be alone in its group without reading the slot.
 __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint64_t mask, uint64_t h,
                                                  uint32_t frag, uint32_t g, bool shared, uint32_t lo,
-                                                 uint32_t hi, bool cas_first, Ctrl* __restrict__ ctrl) {
+                                                 uint32_t hi, bool cas_first, Ctrl* __restrict__ ctrl,
+                                                 uint8_t* __restrict__ notify, bool& created) {
   uint64_t p = h & mask;
+  created = false;
   const unsigned long long mine =
       ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)g;
   for (uint64_t probes = 0; probes <= mask; ++probes) {
     unsigned long long cur;
     if (cas_first) {
       cur = atomicCAS(&table[p], 0ull, mine);
-      if (cur == 0ull) return (uint32_t)p;
+      if (cur == 0ull) {
+        created = true;
+        return (uint32_t)p;
+      }
     } else {
       cur = table[p];
     }
     while (true) {
       if (cur == 0ull) {
         const unsigned long long prev = atomicCAS(&table[p], 0ull, mine);
-        if (prev == 0ull) return (uint32_t)p;
+        if (prev == 0ull) {
+          created = true;
+          return (uint32_t)p;
+        }
         cur = prev;
         continue;
       }
@@ -473,7 +486,11 @@ __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint6
       if (want_lo == cw) return (uint32_t)p;
       const unsigned long long want = (cur & 0xffffffff00000000ull) | want_lo;
       const unsigned long long prev = atomicCAS(&table[p], cur, want);
-      if (prev == cur) return (uint32_t)p;
+      if (prev == cur) {
+        // the first joiner: the slot's least member so far is its claimer
+        if (notify && !(cw & kSlotShared)) notify[cg] = 1;
+        return (uint32_t)p;
+      }
       cur = prev;  // re-examined from the top: empty, other key or same key
     }
     p = (p + 1) & mask;
@@ -494,7 +511,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
     const uint32_t* __restrict__ block, const void* __restrict__ dense,
     Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
-    Ctrl* __restrict__ ctrl, uint32_t gmode) {
+    Ctrl* __restrict__ ctrl, uint32_t gmode, uint8_t* __restrict__ notify) {
   if (gmode & 1u) {  // a queued round: live count and salt from the control block
     if (ctrl->stop) return;
     m = ctrl->m_cur;
@@ -610,11 +627,18 @@ __global__ __launch_bounds__(kBlock) void k_signature(
   }
   __syncthreads();
   const uint64_t mask = (1ull << tbits) - 1ull;
+  // slot ids below 2^31: bit 31 of slot_of marks a state that claimed its
+  // slot alone (no other state of its tile in its group)
+  uint8_t* const nt = tbits <= 31u ? notify : nullptr;
 #pragma unroll
   for (int e = 0; e < SI; ++e) {
-    if (valid[e] && lmin[lp[e]] == gg[e])
-      lslot[lp[e]] =
-          table_insert(table, mask, h[e], frag[e], gg[e], lcnt[lp[e]] > 1u, glo[e], ghi[e], cfirst[e], ctrl);
+    if (valid[e] && lmin[lp[e]] == gg[e]) {
+      bool created = false;
+      const bool alone = lcnt[lp[e]] == 1u;
+      const uint32_t p = table_insert(table, mask, h[e], frag[e], gg[e], !alone, glo[e], ghi[e], cfirst[e],
+                                      ctrl, nt, created);
+      lslot[lp[e]] = p | ((nt && created && alone) ? kSlotClaimedAlone : 0u);
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -634,7 +658,8 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
     const Slot* __restrict__ table, const uint32_t* __restrict__ slot_of,
     const uint32_t* __restrict__ block, uint32_t* __restrict__ nb, uint8_t* __restrict__ keep,
     uint32_t* __restrict__ changed_inst, Ctrl* __restrict__ ctrl,
-    unsigned long long* __restrict__ scan_status, uint32_t ntiles, uint32_t gmode) {
+    unsigned long long* __restrict__ scan_status, uint32_t ntiles, uint32_t gmode,
+    uint8_t* __restrict__ notify) {
   if (gmode) {
     if (ctrl->stop) return;
     m = ctrl->m_cur;
@@ -647,7 +672,19 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
   if (j < m) {
     const uint32_t g = act[j];
     i = BATCH ? inst_of[g] : 0u;
-    const uint32_t w = (uint32_t)table[slot_of[j]];
+    const uint32_t so = slot_of[j];
+    uint32_t w;
+    if (notify && (so & kSlotClaimedAlone)) {
+      // claimed its slot alone: still alone unless a joiner marked it
+      if (notify[g]) {
+        notify[g] = 0;
+        w = (uint32_t)table[so & ~kSlotClaimedAlone];
+      } else {
+        w = g;  // its own group, not shared
+      }
+    } else {
+      w = (uint32_t)table[so];
+    }
     const uint32_t gc = w & kSlotIndexMask;  // least member of the group
     const uint32_t rep = gc;
     if (gc != g) {
@@ -1409,33 +1446,33 @@ template <bool BATCH, int SI>
 void launch_signature_si(int dw, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                          const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                          const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
-                         Ctrl* ctrl, hipStream_t s, uint32_t gm) {
+                         Ctrl* ctrl, hipStream_t s, uint32_t gm, uint8_t* notify) {
   const dim3 grid(grid_for(m, kBlock * SI));
   if (dw == 1)
     hipLaunchKernelGGL((k_signature<BATCH, 1, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl, gm);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify);
   else if (dw == 2)
     hipLaunchKernelGGL((k_signature<BATCH, 2, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl, gm);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify);
   else
     hipLaunchKernelGGL((k_signature<BATCH, 4, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl, gm);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify);
 }
 
 template <bool BATCH>
 void launch_signature_w(int dw, int variant, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                         const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                         const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
-                        Ctrl* ctrl, hipStream_t s, uint32_t gm) {
+                        Ctrl* ctrl, hipStream_t s, uint32_t gm, uint8_t* notify) {
   if (variant == 0)
     launch_signature_si<BATCH, 1>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s, gm);
+                                  ctrl, s, gm, notify);
   else if (variant == 2)
     launch_signature_si<BATCH, 4>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s, gm);
+                                  ctrl, s, gm, notify);
   else
     launch_signature_si<BATCH, 2>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s, gm);
+                                  ctrl, s, gm, notify);
 }
 
 template <bool BATCH>
@@ -1455,14 +1492,14 @@ void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
                       uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s,
-                      int gmode) {
+                      int gmode, uint8_t* notify) {
   if (!m) return;
   if (batch)
     launch_signature_w<true>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
-                             slot_of, salt, ctrl, s, (uint32_t)gmode);
+                             slot_of, salt, ctrl, s, (uint32_t)gmode, notify);
   else
     launch_signature_w<false>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
-                              slot_of, salt, ctrl, s, (uint32_t)gmode);
+                              slot_of, salt, ctrl, s, (uint32_t)gmode, notify);
 }
 
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
@@ -1486,15 +1523,15 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
                     const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
-                    uint32_t ntiles, hipStream_t s, int gmode) {
+                    uint32_t ntiles, hipStream_t s, int gmode, uint8_t* notify) {
   if (!m) return;
   const uint32_t grid = grid_for(std::max(m, ntiles), kBlock);
   if (batch)
     hipLaunchKernelGGL(k_resolve<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
-                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode);
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode, notify);
   else
     hipLaunchKernelGGL(k_resolve<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
-                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode);
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode, notify);
 }
 
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
