@@ -59,7 +59,7 @@ WORKLOADS = {
 # Sources that decide what the benchmarked kernels do (the kernels, their
 # launch parameters and the engine's choices); the serving loop and the C-ABI
 # wrappers do not take part in these workloads.
-KERNEL_SOURCES = ("kernels.hip", "internal.h", "engine.hip", "engine.h", "closure.hip", "closure.h")
+KERNEL_SOURCES = ("kernels.hip", "internal.h", "engine.hip", "engine.h", "closure.hip", "closure.h", "fused.hip")
 
 
 def kernel_source_hash():
