@@ -193,6 +193,9 @@ class Engine {
   DevBuf d_sig_, d_table_, d_status_, d_changed_, d_refine_, d_results_, d_ctrl_;
   DevBuf d_wgflags_, d_part_, d_dense_, d_counts_, d_djobs_;
   DevBuf d_notify_;  // one byte per state: a joiner marked this lone slot claimer
+  DevBuf d_lbl_;     // first round by labels: least member and number per (instance, label)
+  DevBuf d_gcount_;  // group counters of a signature round
+  DevBuf d_dtab_;    // direct count table of an exact-key round
   DevBuf d_visit_, d_bfs_rows_, d_min_delta_, d_min_acc_;
   DevBuf d_lvl_, d_lvl_wg_, d_lvl_flags_;  // level jobs of lazily built closure levels
   DevBuf d_rb_;  // owns d_ctrl_, d_refine_ and d_counts_ (views into it, reset every run)
@@ -209,6 +212,12 @@ class Engine {
   std::vector<uint8_t> lazy_;    // per instance: levels built as the doubling rounds read them
   uint32_t cas_bits_ = 2;        // signature gmode bits 1-2 (table insertion order) of the round
   int cas_forced_ = -1;          // testing override of cas_bits_
+  bool label_off_ = false;       // testing: the first round groups through the table
+  bool slots_off_ = false;       // testing: no slot labels
+  bool direct_off_ = false;      // testing: slot labels through the hash table only
+  bool labels_planned_ = false;  // this call's first signature round goes by labels
+  uint32_t init_wgs_ = 0;        // kRowTile-state jobs over all instances (d_inst_off_)
+  bool all_single_ = false;      // single instance: the rounds ended with every block a singleton
   // captured leader-election rounds, reused while pointers and sizes match
   struct GraphKey {
     uint32_t n, ninst, parity;

@@ -140,7 +140,7 @@ Engine::~Engine() {
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_};
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
   // device buffers of the fixed-region mode belong to the region
   if (!fixed()) {
     for (DevBuf* b : bufs)
@@ -160,7 +160,7 @@ uint64_t Engine::device_bytes() const {
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                           &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                           &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_};
+                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -253,7 +253,7 @@ void Engine::reset_fixed_region() {
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
                     &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_ctrl_, &d_refine_, &d_counts_,
-                    &d_fjobs_, &d_fres_, &d_notify_};
+                    &d_fjobs_, &d_fres_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
   for (DevBuf* b : bufs) *b = DevBuf{};
   closure_bufs_.clear();
   fixed_off_ = 0;
@@ -659,6 +659,35 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   };
   std::vector<uint32_t> exact, scan;
   std::vector<uint32_t> alist(I);  // instances still refining, in order
+  // After a round (not redone): per-instance bounds, j, the closure levels
+  // read, and which instances still refine (rc: refine counters).
+  auto settle = [&](const uint32_t* rc) {
+    for (uint32_t i : alist) {
+      // a round maps each block to at most B^(kp+1) signatures
+      const uint64_t kp1 = desc_[i].kp + 1ull;
+      const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(ub[i]));
+      ub[i] = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
+      if (cnt_ok[i]) ub[i] = std::max<uint64_t>(cnt[i], 1);
+      mj[i] += dbl[i] ? step[i] : 1;
+      active[i] = rc[i] == rounds;
+      // closure levels reported: the highest one a splitting round read
+      if (dbl[i] && active[i]) used[i] = std::max<uint32_t>(used[i], floor_log2_u64(step[i]));
+      // every block a singleton: stable, whatever the other instances do
+      // (it plans no further level and reads none)
+      if (cnt_ok[i] && cnt[i] >= in_[i].n) active[i] = 0;
+    }
+    alist.erase(std::remove_if(alist.begin(), alist.end(), [&](uint32_t i) { return !active[i]; }), alist.end());
+  };
+  // the dense numbers of the coming round were written by the first round's labels
+  bool dense_from_labels = false;
+  all_single_ = false;
+  // slot labels (launch_compact) for one instance, unless rounds are queued
+  // (their resolve steps compare ids) or a testing knob turns them off; and
+  // whether block[] holds such labels from the last round
+  const bool slots_ok = !batch && !slots_off_ && !(opts.flags & DFAMIN_FLAG_QUEUE);
+  bool slot_prev = false;
+  TRY(ensure(d_gcount_, 2 * kGroupCounters * 4));
+  uint32_t* const gcount = d_gcount_.as<uint32_t>();
   for (size_t i = 0; i < I; ++i) alist[i] = (uint32_t)i;
   TRY(ensure(d_djobs_, 4 * I * 4 + 64));
   TRY(ensure_host(h_jobs_, 4 * I * 4 + 64));
@@ -760,11 +789,13 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         es += in_[exact[j]].n;
       }
       TRY(ensure(d_dense_, N * 4));
-      TRY(upload_if_changed(up_dense, hj, dj, 2 * ne));
-      prof.begin(s, "dense", (8.0 + dense_width) * es);
-      launch_dense_jobs(d_desc_.as<InstDesc>(), dj, dj + ne, ne, wgs, d_block_.as<uint32_t>(),
-                        d_rank_.as<uint32_t>(), d_dense_.p, dense_width, s);
-      prof.end(s);
+      if (!dense_from_labels) {
+        TRY(upload_if_changed(up_dense, hj, dj, 2 * ne));
+        prof.begin(s, "dense", (8.0 + dense_width) * es);
+        launch_dense_jobs(d_desc_.as<InstDesc>(), dj, dj + ne, ne, wgs, d_block_.as<uint32_t>(),
+                          d_rank_.as<uint32_t>(), d_dense_.p, dense_width, s);
+        prof.end(s);
+      }
     }
     if (dirty) {
       const auto td = now();
@@ -773,6 +804,69 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         t_desc += us(td, now());
         ++n_dirty;
       }
+    }
+    // The first round by labels (launch_label): every instance has at most
+    // kMaxLabelLetters signature letters.  One instance keeps every state
+    // active (no compaction); a batch compacts away the instances that did
+    // not split.
+    const bool label_round = rounds == 0 && labels_planned_ && !alist.empty();
+    if (label_round) {
+      // planned by run_path, which then left out the initial partition
+      for (uint32_t i : alist)
+        if (desc_[i].kp > kMaxLabelLetters) return DFAMIN_E_INTERNAL;
+      TRY(ensure(d_dense_, N * 4));
+      TRY(ensure(d_lbl_, I * 256 * 5));
+      uint32_t* lmin = d_lbl_.as<uint32_t>();
+      uint8_t* rank8 = reinterpret_cast<uint8_t*>(lmin + I * 256);
+      HIP(hipMemsetAsync(lmin, 0xff, I * 256 * 4, s));
+      const int litems = scan_items_for(m);
+      const uint32_t ltiles = scan_tiles(m, litems);
+      double lb = 0;
+      // own bit, kp row entries and bitmap bytes, the label written, read and
+      // rewritten, the id and the list entry [instance map, keep flag]
+      for (size_t i = 0; i < I; ++i)
+        lb += (double)in_[i].n * (0.125 + 5.0 * desc_[i].kp + 11.0 + (batch ? 5.0 : 0.0));
+      prof.begin(s, "label", lb);
+      launch_label(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs_,
+                   d_rows_.as<uint64_t>(), lmin, rank8, d_dense_.as<uint8_t>(), d_counts_.as<uint32_t>(),
+                   d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(), d_block_.as<uint32_t>(),
+                   batch ? d_nb_.as<uint32_t>() : nullptr, d_keep_.as<uint8_t>(),
+                   d_status_.as<unsigned long long>(), ltiles, batch ? 0u : 1u, (uint32_t)m,
+                   d_act_.as<uint32_t>(), batch ? d_inst_of_.as<uint32_t>() : nullptr, s);
+      prof.end(s);
+      if (batch) {
+        prof.begin(s, "compact", (double)m * (4 + 4 + 4 + 1 + 4));
+        launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
+                       d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(),
+                       nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), litems, s);
+        prof.end(s);
+      }
+      launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
+                       d_ctrl_.as<Ctrl>(), s);
+      HIP(hipGetLastError());
+      // control block, refine counters and every instance's label count
+      TRY(readback(h_rb_, d_rb_.p, sizeof(Ctrl) + 8 * I, s));
+      HIP(stream_wait(s));
+      stage_flip();
+      prof.collect();
+      const Ctrl c = *h_rb_.as<Ctrl>();
+      const uint32_t* h_refine = reinterpret_cast<const uint32_t*>(h_rb_.as<char>() + sizeof(Ctrl));
+      if (c.fault) return DFAMIN_E_INTERNAL;
+      for (size_t i = 0; i < I; ++i) {
+        cnt[i] = h_refine[I + i];
+        cnt_ok[i] = 1;
+      }
+      if (trace) t_issue += us(tp0, now());
+      ++rounds;
+      settle(h_refine);
+      dense_from_labels = true;
+      if (I == 1) all_single_ = cnt[0] >= in_[0].n;
+      if (batch) {
+        std::swap(cur, nxt);
+        m = c.m_next;
+      }
+      if (!c.any_changed) break;
+      continue;
     }
     // Table: twice the number of groups this round can form, at most m.  An
     // exact-key instance forms at most 2^((kp+1) * ebits) groups.
@@ -916,13 +1010,30 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         }
       }
       rounds += executed;
+      all_single_ = false;
       if (rounds > max_rounds) return DFAMIN_E_INTERNAL;
       if (trace) std::fprintf(stderr, "[dfamin] %llu queued rounds from m=%llu\n", (unsigned long long)executed,
                               (unsigned long long)m);
       break;
     }
+    // Slot labels (launch_compact): one instance in an exact-key round whose
+    // block count is known, followed by a hash round with no count scan
+    // (which reads labels as well as ids and then restores least-member
+    // ids).  The resolve step and its random read of a slot per state are
+    // left out.  Where the key space is small enough (at most
+    // 2^kDirectMaxBits keys, at most 8 per active state) the groups form in
+    // a direct count table instead of the hash table.
+    const uint32_t i0 = alist.empty() ? 0u : alist[0];
+    const bool slot_cand = slots_ok && !slot_prev && alist.size() == 1 && desc_[i0].ebits && cnt_ok[i0] &&
+                           cnt[i0] + m >= in_[i0].n && !would_scan(i0);
+    const uint32_t dwidth = (desc_[i0].kp + 1u) * desc_[i0].ebits;
+    // (not in the fixed region, whose size is set for the hash table)
+    const bool direct =
+        slot_cand && !fixed() && !direct_off_ && dwidth <= kDirectMaxBits && (1ull << dwidth) <= 8ull * m;
     if (tu.forced >= 0) {
       variant = tu.forced;
+    } else if (direct) {
+      if (tuned != tu.best.end()) variant = tuned->second;
     } else if (m >= kTuneMinStates) {
       auto it = tuned;
       if (it != tu.best.end()) {
@@ -933,12 +1044,12 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
           tu.have_events = true;
         }
         for (int v = 0; v < kSigVariants; ++v) {
-          launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+          launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 0, gcount);
           HIP(hipEventRecord(tu.ev[2 * v], s));
           launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                            d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
                            d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
-                           v, s, (int)cas_bits_);
+                           v, s, (int)cas_bits_, nullptr, gcount);
           HIP(hipEventRecord(tu.ev[2 * v + 1], s));
         }
         HIP(hipGetLastError());
@@ -957,33 +1068,64 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       }
     }
     const bool cleared = spec_clear >= tsize;  // by the previous round's tail
-    spec_clear = 0;
-    if (!tuned_now) {
+    if (direct) {
+      // (the group counters are cleared with the count table: a hash table
+      // cleared ahead would no longer come with cleared counters)
+      spec_clear = 0;
+      TRY(ensure(d_dtab_, 4ull << dwidth));
+      prof.begin(s, "clear_table", 4.0 * (double)(1ull << dwidth));
+      launch_clear_table(d_dtab_.as<Slot>(), 1ull << (dwidth - 1), d_ctrl_.as<Ctrl>(), s, 0, gcount);
+      prof.end(s);
+      prof.begin(s, "signature", md * sig_bytes());
+      launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                       d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
+                       d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
+                       variant, s, (int)cas_bits_, nullptr, gcount, d_dtab_.as<uint32_t>());
+      prof.end(s);
+    } else if (!tuned_now) {
+      spec_clear = 0;
       if (!cleared) {
         prof.begin(s, "clear_table", 8.0 * (double)tsize);
-        launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+        launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 0, gcount);
         prof.end(s);
       }
       prof.begin(s, "signature", md * sig_bytes());
       launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                        d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
                        d_table_.as<Slot>(), tbits, d_slot_of_.as<uint32_t>(), salt, d_ctrl_.as<Ctrl>(),
-                       variant, s, (int)cas_bits_, d_notify_.as<uint8_t>());
+                       variant, s, (int)cas_bits_, d_notify_.as<uint8_t>(), gcount);
+      prof.end(s);
+    } else {
+      spec_clear = 0;
+    }
+    // (through the hash table, lone claimers must be marked: no tuning run)
+    const bool slot_round = slot_cand && (direct || (!tuned_now && tbits <= 31));
+    if (slot_round) {
+      // blocks among the active states: every state off the list is a
+      // singleton block of its own
+      const uint64_t before = cnt[i0] - (in_[i0].n - m);
+      launch_prep_scan(d_status_.as<unsigned long long>(), ntiles, d_ctrl_.as<Ctrl>(), s);
+      prof.begin(s, "compact", md * (4 + 4 + 1 + 4 + 4));
+      launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), nullptr, nullptr,
+                     d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(), nxt, d_ctrl_.as<Ctrl>(),
+                     d_status_.as<unsigned long long>(), citems, s, 0, d_slot_of_.as<uint32_t>(),
+                     d_notify_.as<uint8_t>(), gcount, (uint32_t)before, direct ? d_dtab_.as<uint32_t>() : nullptr);
+      prof.end(s);
+    } else {
+      prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
+      launch_resolve(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                     d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
+                     d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(), d_keep_.as<uint8_t>(),
+                     d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                     d_status_.as<unsigned long long>(), ntiles, s, 0,
+                     tuned_now ? nullptr : d_notify_.as<uint8_t>(), slot_prev ? gcount : nullptr);
+      prof.end(s);
+      prof.begin(s, "compact", md * (4 + inst_b + 4 + 1 + 4));
+      launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
+                     d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(),
+                     nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), citems, s);
       prof.end(s);
     }
-    prof.begin(s, "resolve", md * (4 + inst_b + 4 + 8 + 4 + 4 + 1));
-    launch_resolve(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-                   d_table_.as<Slot>(), d_slot_of_.as<uint32_t>(),
-                   d_block_.as<uint32_t>(), d_nb_.as<uint32_t>(), d_keep_.as<uint8_t>(),
-                   d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                   d_status_.as<unsigned long long>(), ntiles, s, 0,
-                   tuned_now ? nullptr : d_notify_.as<uint8_t>());
-    prof.end(s);
-    prof.begin(s, "compact", md * (4 + inst_b + 4 + 1 + 4));
-    launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
-                   d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(),
-                   nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), citems, s);
-    prof.end(s);
     // Exact block counts for the next round, queued before the one sync of
     // the round: instances that were refining before this round and whose
     // next signature could fit 31 bits, B <= min(n, B^(kp+1)) after it.
@@ -1047,7 +1189,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         todo.clear();
       }
       if (tsize <= kClearAheadSlots) {
-        launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s);
+        launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 0, gcount);
         HIP(hipGetLastError());
         spec_clear = tsize;
       }
@@ -1080,22 +1222,12 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     }
     ++rounds;
     retries = 0;  // the bound is on redoing one round
-    const uint32_t* rc = h_refine;
-    for (uint32_t i : alist) {
-      // a round maps each block to at most B^(kp+1) signatures
-      const uint64_t kp1 = desc_[i].kp + 1ull;
-      const uint32_t bits = std::max<uint32_t>(1, ceil_log2_u64(ub[i]));
-      ub[i] = (kp1 * bits >= 40) ? in_[i].n : std::min<uint64_t>(in_[i].n, 1ull << (kp1 * bits));
-      if (cnt_ok[i]) ub[i] = std::max<uint64_t>(cnt[i], 1);
-      mj[i] += dbl[i] ? step[i] : 1;
-      active[i] = rc[i] == rounds;
-      // closure levels reported: the highest one a splitting round read
-      if (dbl[i] && active[i]) used[i] = std::max<uint32_t>(used[i], floor_log2_u64(step[i]));
-      // every block a singleton: stable, whatever the other instances do
-      // (it plans no further level and reads none)
-      if (cnt_ok[i] && cnt[i] >= in_[i].n) active[i] = 0;
-    }
-    alist.erase(std::remove_if(alist.begin(), alist.end(), [&](uint32_t i) { return !active[i]; }), alist.end());
+    settle(h_refine);
+    dense_from_labels = false;
+    slot_prev = slot_round;
+    // one instance, and this round split blocks and kept no state (every
+    // block is a singleton), or counted n blocks
+    if (I == 1) all_single_ = (c.any_changed && c.m_next == 0) || (cnt_ok[0] && cnt[0] >= in_[0].n);
     std::swap(cur, nxt);
     m = c.m_next;
     t_post += us(tp3, now());
@@ -1676,6 +1808,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     inst_off[i] = init_wgs;
     init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
   }
+  init_wgs_ = init_wgs;
   TRY(upload(d_inst_off_.p, inst_off.data(), I * 4, s));
   TRY(ensure(d_part_, (size_t)init_wgs * 8));
   HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
@@ -1688,6 +1821,15 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   // (DFAMIN_CAS_FIRST=b: bit 0 hash-mode states, bit 1 exact-key states)
   cas_forced_ = -1;
   if (const char* e = std::getenv("DFAMIN_CAS_FIRST")) cas_forced_ = (std::atoi(e) & 3) << 1;
+  // testing: bit 0, the first round groups through the table as later
+  // rounds do; bit 1, no slot labels; bit 2, no direct count tables
+  {
+    const char* e = std::getenv("DFAMIN_NO_LABELS");
+    const int v = e ? std::atoi(e) : 0;
+    label_off_ = (v & 1) != 0;
+    slots_off_ = (v & 2) != 0;
+    direct_off_ = (v & 4) != 0;
+  }
   if (const char* e = std::getenv("DFAMIN_HASH_BITS")) {
     // testing: weak signature hashes (see Ctrl::hash_mask)
     const int bits = std::atoi(e);
@@ -1697,21 +1839,30 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     }
   }
 
-  // ---- 4. initial partition {F, Q\F}
-  prof.begin(s, "init_minmax", (double)N / 8.0);
-  launch_init_minmax(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
-                     d_part_.as<unsigned long long>(), d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(), s);
-  prof.end(s);
-  prof.begin(s, "init_block", (8.125 + (batch ? 4.0 : 0.0)) * (double)N);
-  launch_init_block(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
-                    d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(),
-                    batch ? d_inst_of_.as<uint32_t>() : nullptr, d_block_.as<uint32_t>(),
-                    d_act_.as<uint32_t>(), s);
-  prof.end(s);
-  HIP(hipGetLastError());
+  // ---- 4. initial partition {F, Q\F}: not needed when the first round
+  // goes by labels (every instance with at most kMaxLabelLetters signature
+  // letters in that round; one-letter AUTO instances read one level), whose
+  // kernels write every block id, the active list and the instance map
+  labels_planned_ = opts.method == DFAMIN_METHOD_SIGNATURE && !label_off_;
+  for (size_t i = 0; i < I && labels_planned_; ++i)
+    if ((lazy_[i] ? 1u : (uint32_t)inst_rows_[i].size()) > kMaxLabelLetters) labels_planned_ = false;
+  if (!labels_planned_) {
+    prof.begin(s, "init_minmax", (double)N / 8.0);
+    launch_init_minmax(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
+                       d_part_.as<unsigned long long>(), d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(), s);
+    prof.end(s);
+    prof.begin(s, "init_block", (8.125 + (batch ? 4.0 : 0.0)) * (double)N);
+    launch_init_block(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,
+                      d_minF_.as<uint32_t>(), d_minN_.as<uint32_t>(),
+                      batch ? d_inst_of_.as<uint32_t>() : nullptr, d_block_.as<uint32_t>(),
+                      d_act_.as<uint32_t>(), s);
+    prof.end(s);
+    HIP(hipGetLastError());
+  }
 
   // ---- 5. rounds
   const auto t_setup = now();
+  all_single_ = false;
   {
     const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
     TRY(opts.method == DFAMIN_METHOD_LEADER ? leader_rounds(opts, max_rounds, s)
@@ -1720,19 +1871,27 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
 
   // ---- 6. canonical numbering and emission
   const auto t_rounds = now();
-  const int fitems = scan_items_for(N);
-  const uint32_t ntilesN = scan_tiles(N, fitems);
-  launch_prep_scan(d_status_.as<unsigned long long>(), ntilesN, d_ctrl_.as<Ctrl>(), s);
-  prof.begin(s, "scan_reps", 8.0 * (double)N);
-  launch_scan_reps(d_block_.as<uint32_t>(), (uint32_t)N, d_rank_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
-                   d_status_.as<unsigned long long>(), fitems, s);
-  prof.end(s);
-  prof.begin(s, "emit", (12.0 + (batch ? 4.0 : 0.0)) * (double)N);
-  launch_emit(batch, (uint32_t)N, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
-              d_block_.as<uint32_t>(), d_rank_.as<uint32_t>(), s);
-  prof.end(s);
-  launch_results((uint32_t)I, d_desc_.as<InstDesc>(), d_rank_.as<uint32_t>(),
-                 d_refine_.as<uint32_t>(), d_results_.as<ResultDev>(), s);
+  if (opts.method == DFAMIN_METHOD_SIGNATURE && !batch && all_single_) {
+    // every block a singleton: each state is its own least member
+    prof.begin(s, "emit", 4.0 * (double)N);
+    launch_identity_out(d_desc_.as<InstDesc>(), (uint32_t)N, d_refine_.as<uint32_t>(),
+                        d_results_.as<ResultDev>(), s);
+    prof.end(s);
+  } else {
+    const int fitems = scan_items_for(N);
+    const uint32_t ntilesN = scan_tiles(N, fitems);
+    launch_prep_scan(d_status_.as<unsigned long long>(), ntilesN, d_ctrl_.as<Ctrl>(), s);
+    prof.begin(s, "scan_reps", 8.0 * (double)N);
+    launch_scan_reps(d_block_.as<uint32_t>(), (uint32_t)N, d_rank_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                     d_status_.as<unsigned long long>(), fitems, s);
+    prof.end(s);
+    prof.begin(s, "emit", (12.0 + (batch ? 4.0 : 0.0)) * (double)N);
+    launch_emit(batch, (uint32_t)N, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
+                d_block_.as<uint32_t>(), d_rank_.as<uint32_t>(), s);
+    prof.end(s);
+    launch_results((uint32_t)I, d_desc_.as<InstDesc>(), d_rank_.as<uint32_t>(),
+                   d_refine_.as<uint32_t>(), d_results_.as<ResultDev>(), s);
+  }
   HIP(hipGetLastError());
   TRY(readback(h_results_, d_results_.p, I * sizeof(ResultDev), s));
   TRY(readback(h_ctrl_, d_ctrl_.p, sizeof(Ctrl), s));

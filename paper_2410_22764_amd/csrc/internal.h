@@ -84,6 +84,23 @@ constexpr uint32_t kSlotIndexMask = 0x7fffffffu;
 // marked it in the round's notify bytes, it is then alone in its group, and
 // the resolve step needs no read of the slot.
 constexpr uint32_t kSlotClaimedAlone = 0x80000000u;
+// Group counters of a signature round (gcount, 2 * kGroupCounters words,
+// zeroed by the table clear before the round): workgroup w adds to word
+// w % kGroupCounters the slots it claimed (groups formed) and, at offset
+// kGroupCounters, the slots that became shared through it (claimed by a
+// tile group of two or more, or joined for the first time).  Spreading
+// the sums over many words keeps any one word from taking an atomic from
+// every workgroup.
+constexpr uint32_t kGroupCounters = 64;
+// Slot labels: after an exact-key round whose groups are counted, a state
+// of a shared group may carry kSlotLabel | (its group's slot) as its block
+// label instead of the least member (a state id, below 2^31): the labels
+// tell the same partition.  A state alone in its group carries its own id,
+// which is its least member.
+constexpr uint32_t kSlotLabel = 0x80000000u;
+// Direct count tables (launch_signature's dtab) of at most 2^kDirectMaxBits
+// words: 128 MB, which the memory-side cache can hold.
+constexpr uint32_t kDirectMaxBits = 25;
 
 // Control block shared by the round kernels and read by the host.  The flags
 // only go from 0 to 1 within a kernel (plain stores of one value); the tile
@@ -100,7 +117,8 @@ struct Ctrl {
   uint32_t retries;       // queued signature rounds: times the coming round was redone (hash collision)
   uint64_t salt;          // queued signature rounds: hash salt of the coming round
   uint64_t hash_mask;     // testing: nonzero keeps only these bits of a signature hash
-  uint32_t pad0[20];
+  uint32_t prev_shared;   // shared groups of the last round that ended with slot labels
+  uint32_t pad0[19];
   uint32_t tile_counter;  // dynamic tile ids for the look-back scans
   uint32_t pad1[31];
 };
@@ -208,18 +226,26 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
 // round whose kernels return at once when ctrl->stop is set and otherwise
 // take the active count (m) and the salt from ctrl->m_cur and ctrl->salt; m
 // is then an upper bound that only sizes the grid.
-void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode = 0);
+// gcount (nullable): the group counters, zeroed with the table.
+void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode = 0,
+                        uint32_t* gcount = nullptr);
 // dense / dense_width: dense block numbers (exact-key rounds that read them),
 // stored dense_width (1, 2 or 4) bytes per state.  gmode bit 0 as above;
 // bits 1 and 2: hash-mode / exact-key states insert their group with a CAS
 // on the home slot before reading it (table_insert).
 // notify (nullable): one byte per global state, all 0 before the round; the
 // resolve step of the round returns them to 0.
+// gcount (nullable): the round's group counters.
+// dtab (nullable; exact keys of one instance): a direct count table of
+// 2^((kp+1)*ebits) words, all 0 before the round, takes the place of the
+// hash table: each local group adds its size to the word its key indexes,
+// the key is the slot id, and a lone claimer is known by its word's count.
 void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
                       uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s,
-                      int gmode = 0, uint8_t* notify = nullptr);
+                      int gmode = 0, uint8_t* notify = nullptr, uint32_t* gcount = nullptr,
+                      uint32_t* dtab = nullptr);
 // dense[g] = rank[block[g]] - rank[state_off]: the block's number among the
 // instance's blocks in order of least member, dense_width bytes wide (every
 // number must fit).
@@ -229,16 +255,39 @@ void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDes
 // counts[i] = number of blocks of instance i (from rank).
 void launch_block_counts(uint32_t ninst, const InstDesc* desc, const uint32_t* rank,
                          uint32_t* counts, hipStream_t s);
+// notify must be what the round's launch_signature was given (both null, or
+// the same bytes): only then are the slot ids it wrote free of the
+// claimed-alone bit, or is that bit read as such.
+// count_gcount (nullable, one instance only): the round follows one that
+// left slot labels, so a state's old label is no least member; the
+// instance split iff this round formed more groups (from these counters)
+// than that round left shared (ctrl->prev_shared).
 void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
-                    uint32_t ntiles, hipStream_t s, int gmode = 0, uint8_t* notify = nullptr);
+                    uint32_t ntiles, hipStream_t s, int gmode = 0, uint8_t* notify = nullptr,
+                    const uint32_t* count_gcount = nullptr);
 // dead (nullable): instances whose states leave the active list (cancelled).
+// Slot labels (slot_of non-null; one instance, an exact-key round with
+// lone claimers marked in notify and groups counted in gcount; takes the
+// place of the resolve step, whose scan status clearing launch_prep_scan
+// does): the instance split iff the round formed more groups than
+// prev_count, the blocks its active states were in before the round.  If
+// so, a state of a shared group (not a lone claimer, or one a joiner
+// marked) gets kSlotLabel | slot and stays active, a state alone gets its
+// own id; changed_inst[0] and ctrl->prev_shared (the shared groups) are
+// set.  If not, no block id changes and no state stays.  The notify bytes
+// read are returned to 0.  With dtab (the round's direct count table) a
+// lone claimer's group is shared iff its word counts two or more, and no
+// notify byte is read.
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
-                    const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
+                    const uint32_t* nb, const uint8_t* keep, uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
-                    unsigned long long* scan_status, int items, hipStream_t s, int gmode = 0);
+                    unsigned long long* scan_status, int items, hipStream_t s, int gmode = 0,
+                    const uint32_t* slot_of = nullptr, uint8_t* notify = nullptr,
+                    const uint32_t* gcount = nullptr, uint32_t prev_count = 0,
+                    const uint32_t* dtab = nullptr);
 // last (nullable) receives this round's per-instance changed flags.
 void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_cnt, uint32_t* last,
                       Ctrl* ctrl, hipStream_t s, unsigned long long* clear_status = nullptr,
@@ -315,6 +364,30 @@ void launch_emit_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t
 void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
                        uint32_t njobs, uint32_t total_wgs, const uint32_t* block, const uint32_t* rank,
                        void* dense, int dense_width, hipStream_t s);
+// The first signature round from {F, Q\F} by labels (instances of at most
+// kMaxLabelLetters signature letters): the label of q is its accept bit and
+// those of its successors, an exact key below 256.  Per instance (jobs of
+// kRowTile states, job_wg_off as for the init jobs): lmin (256 words per
+// instance, all ones before the call) receives each label's least member,
+// rank8 (256 bytes per instance) the labels' numbers in order, counts[i] the
+// number of labels present, changed_inst[i] = 1 where that exceeds the
+// number of blocks of {F, Q\F}.  label (one byte per state) ends holding
+// dense block numbers and block[g] the least-member ids; with nb given, the
+// ids go to nb and keep[g] = 1 for a compaction that follows (whose scan
+// status words and tile counter are cleared).  act receives every state in
+// order and inst_of (nullable) each state's instance: the initial
+// partition need not be computed first.  The round flags of ctrl are
+// cleared, and with set_m m_next is set to m.
+constexpr uint32_t kMaxLabelLetters = 7;
+void launch_label(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst, uint32_t total_wgs,
+                  const uint64_t* rows, uint32_t* lmin, uint8_t* rank8, uint8_t* label, uint32_t* counts,
+                  uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block, uint32_t* nb, uint8_t* keep,
+                  unsigned long long* scan_status, uint32_t ntiles, uint32_t set_m, uint32_t m,
+                  uint32_t* act, uint32_t* inst_of, hipStream_t s);
+// One instance whose blocks are all singletons: out[q] = q and its results
+// (n blocks, initial block q0).
+void launch_identity_out(const InstDesc* desc, uint32_t n, const uint32_t* refine_cnt, ResultDev* res,
+                         hipStream_t s);
 void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,
                          const uint32_t* totals, const uint32_t* refine_cnt, ResultDev* res,
                          hipStream_t s);

@@ -420,12 +420,14 @@ __global__ __launch_bounds__(kBlock) void k_init_block(const InstDesc* __restric
 // ---------------------------------------------------------------- round
 // Algorithmic bytes: 8 per slot.
 __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table, uint64_t tsize,
-                                                        Ctrl* __restrict__ ctrl, uint32_t gmode) {
+                                                        Ctrl* __restrict__ ctrl, uint32_t gmode,
+                                                        uint32_t* __restrict__ gcount) {
   if (gmode && ctrl->stop) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctrl->any_changed = 0u;
     ctrl->collision = 0u;
   }
+  if (gcount && blockIdx.x == 0 && threadIdx.x < 2 * kGroupCounters) gcount[threadIdx.x] = 0u;
   const uint64_t stride = (uint64_t)gridDim.x * kBlock * 2;
   for (uint64_t s = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) * 2; s < tsize; s += stride) {
     table[s] = 0ull;
@@ -446,16 +448,19 @@ __global__ __launch_bounds__(kBlock) void k_clear_table(Slot* __restrict__ table
 // change monotonically (claimed once, index only lowered within the same
 // instance, shared bit only set).
 //
-// `created` tells the caller that this call claimed an empty slot.  The
-// first state to join a slot that was not yet shared marks its claimer in
-// `notify` (nullable; one byte per global state id): a claimer left
-// unmarked is then known to be alone in its group without reading the slot.
+// `created` tells the caller that this call claimed an empty slot,
+// `first_join` that it made a slot shared that was not.  The first state to
+// join a slot that was not yet shared marks its claimer in `notify`
+// (nullable; one byte per global state id): a claimer left unmarked is then
+// known to be alone in its group without reading the slot.
 __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint64_t mask, uint64_t h,
                                                  uint32_t frag, uint32_t g, bool shared, uint32_t lo,
                                                  uint32_t hi, bool cas_first, Ctrl* __restrict__ ctrl,
-                                                 uint8_t* __restrict__ notify, bool& created) {
+                                                 uint8_t* __restrict__ notify, bool& created,
+                                                 bool& first_join) {
   uint64_t p = h & mask;
   created = false;
+  first_join = false;
   const unsigned long long mine =
       ((unsigned long long)frag << 32) | (shared ? kSlotShared : 0u) | (unsigned long long)g;
   for (uint64_t probes = 0; probes <= mask; ++probes) {
@@ -488,7 +493,10 @@ __device__ __forceinline__ uint32_t table_insert(Slot* __restrict__ table, uint6
       const unsigned long long prev = atomicCAS(&table[p], cur, want);
       if (prev == cur) {
         // the first joiner: the slot's least member so far is its claimer
-        if (notify && !(cw & kSlotShared)) notify[cg] = 1;
+        if (!(cw & kSlotShared)) {
+          first_join = true;
+          if (notify) notify[cg] = 1;
+        }
         return (uint32_t)p;
       }
       cur = prev;  // re-examined from the top: empty, other key or same key
@@ -511,7 +519,8 @@ __global__ __launch_bounds__(kBlock) void k_signature(
     const InstDesc* __restrict__ desc, const uint64_t* __restrict__ rows,
     const uint32_t* __restrict__ block, const void* __restrict__ dense,
     Slot* __restrict__ table, uint32_t tbits, uint32_t* __restrict__ slot_of, uint64_t salt,
-    Ctrl* __restrict__ ctrl, uint32_t gmode, uint8_t* __restrict__ notify) {
+    Ctrl* __restrict__ ctrl, uint32_t gmode, uint8_t* __restrict__ notify, uint32_t* __restrict__ gcount,
+    uint32_t* __restrict__ dtab) {
   if (gmode & 1u) {  // a queued round: live count and salt from the control block
     if (ctrl->stop) return;
     m = ctrl->m_cur;
@@ -521,10 +530,15 @@ __global__ __launch_bounds__(kBlock) void k_signature(
   constexpr uint32_t kTile = kBlock * SI, kSlots = 2 * kTile;
   __shared__ unsigned long long lkey[kSlots];
   __shared__ uint32_t lmin[kSlots], lcnt[kSlots], lslot[kSlots];
+  __shared__ uint32_t s_formed, s_shared;  // slots claimed / made shared by this workgroup
   for (uint32_t s = threadIdx.x; s < kSlots; s += kBlock) {
     lkey[s] = 0ull;
     lmin[s] = 0xffffffffu;
     lcnt[s] = 0u;
+  }
+  if (threadIdx.x == 0) {
+    s_formed = 0u;
+    s_shared = 0u;
   }
   __syncthreads();
   uint64_t h[SI];
@@ -633,14 +647,33 @@ __global__ __launch_bounds__(kBlock) void k_signature(
 #pragma unroll
   for (int e = 0; e < SI; ++e) {
     if (valid[e] && lmin[lp[e]] == gg[e]) {
-      bool created = false;
+      bool created = false, first_join = false;
       const bool alone = lcnt[lp[e]] == 1u;
-      const uint32_t p = table_insert(table, mask, h[e], frag[e], gg[e], !alone, glo[e], ghi[e], cfirst[e],
-                                      ctrl, nt, created);
-      lslot[lp[e]] = p | ((nt && created && alone) ? kSlotClaimedAlone : 0u);
+      uint32_t p;
+      if (dtab) {
+        // direct count table: the exact key is the word's index
+        p = frag[e] - 1u;
+        const uint32_t old = atomicAdd(&dtab[p], lcnt[lp[e]]);
+        created = old == 0u;
+        first_join = old == 1u;
+        lslot[lp[e]] = p | ((created && alone) ? kSlotClaimedAlone : 0u);
+      } else {
+        p = table_insert(table, mask, h[e], frag[e], gg[e], !alone, glo[e], ghi[e], cfirst[e], ctrl, nt,
+                         created, first_join);
+        lslot[lp[e]] = p | ((nt && created && alone) ? kSlotClaimedAlone : 0u);
+      }
+      if (gcount) {
+        if (created) atomicAdd(&s_formed, 1u);
+        if ((created && !alone) || first_join) atomicAdd(&s_shared, 1u);
+      }
     }
   }
   __syncthreads();
+  if (gcount && threadIdx.x == 0) {
+    const uint32_t w = blockIdx.x % kGroupCounters;
+    if (s_formed) atomicAdd(&gcount[w], s_formed);
+    if (s_shared) atomicAdd(&gcount[kGroupCounters + w], s_shared);
+  }
 #pragma unroll
   for (int e = 0; e < SI; ++e)
     if (valid[e]) slot_of[jj[e]] = lslot[lp[e]];
@@ -659,7 +692,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
     const uint32_t* __restrict__ block, uint32_t* __restrict__ nb, uint8_t* __restrict__ keep,
     uint32_t* __restrict__ changed_inst, Ctrl* __restrict__ ctrl,
     unsigned long long* __restrict__ scan_status, uint32_t ntiles, uint32_t gmode,
-    uint8_t* __restrict__ notify) {
+    uint8_t* __restrict__ notify, const uint32_t* __restrict__ count_gcount) {
   if (gmode) {
     if (ctrl->stop) return;
     m = ctrl->m_cur;
@@ -667,6 +700,11 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
   const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
   if (j < ntiles) store_status(&scan_status[j], 0ull);
   if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
+  if (count_gcount && j < 64) {
+    // split iff more groups than the shared groups the labels stand for
+    const uint32_t formed = wave_sum(count_gcount[j]);
+    if (j == 0 && formed > ctrl->prev_shared) changed_inst[0] = 1u;
+  }
   bool changed = false, coll = false;
   uint32_t i = 0xffffffffu;
   if (j < m) {
@@ -699,7 +737,7 @@ __global__ __launch_bounds__(kBlock) void k_resolve(
         for (uint32_t t = 0; t < words; ++t) coll |= (r1[t] != r2[t]);
       }
     }
-    changed = rep != block[g];
+    changed = !count_gcount && rep != block[g];
     nb[j] = rep;
     keep[j] = (w & kSlotShared) ? 1 : 0;
   }
@@ -723,9 +761,11 @@ template <bool BATCH, int ITEMS>
 __global__ __launch_bounds__(kBlock) void k_compact(
     const uint32_t* __restrict__ act, uint32_t m, const uint32_t* __restrict__ inst_of,
     const uint32_t* __restrict__ nb, const uint8_t* __restrict__ keep,
-    const uint32_t* __restrict__ changed_inst, const uint32_t* __restrict__ dead,
+    uint32_t* __restrict__ changed_inst, const uint32_t* __restrict__ dead,
     uint32_t* __restrict__ block, uint32_t* __restrict__ act_next, Ctrl* __restrict__ ctrl,
-    unsigned long long* __restrict__ scan_status, uint32_t gmode) {
+    unsigned long long* __restrict__ scan_status, uint32_t gmode,
+    const uint32_t* __restrict__ slot_of, uint8_t* __restrict__ notify,
+    const uint32_t* __restrict__ gcount, uint32_t prev_count, const uint32_t* __restrict__ dtab) {
   if (gmode) {  // every workgroup reads the same flag: all of them leave, or none
     if (ctrl->stop) return;
     m = ctrl->m_cur;
@@ -734,27 +774,64 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   // written (in a queued round the active list is carried over unchanged),
   // but every tile still takes part in the look-back so that no workgroup
   // can wait for one that left early.
-  __shared__ uint32_t s_tile, s_prefix, s_coll;
+  __shared__ uint32_t s_tile, s_prefix, s_coll, s_split;
   __shared__ TileScanLds<ITEMS> s_scan;
   if (threadIdx.x == 0) {
     s_tile = atomicAdd(&ctrl->tile_counter, 1u);
     s_coll = ctrl->collision;
+  }
+  if (slot_of && threadIdx.x < 64) {
+    // slot labels: the round split iff it formed more groups than before
+    const uint32_t formed = wave_sum(gcount[threadIdx.x]);
+    const uint32_t shared = wave_sum(gcount[kGroupCounters + threadIdx.x]);
+    if (threadIdx.x == 0) {
+      s_split = formed > prev_count ? 1u : 0u;
+      if (blockIdx.x == 0 && s_split) {
+        changed_inst[0] = 1u;
+        ctrl->prev_shared = shared;
+      }
+    }
   }
   __syncthreads();
   const uint32_t tile = s_tile;
   const bool coll = s_coll != 0;
   const uint32_t base = tile * (kBlock * ITEMS);
   uint32_t fb = 0;
+  if (slot_of) {
+    // one instance, exact keys (no collision): ids change only if it split
+    if (s_split) {
 #pragma unroll 8
-  for (int e = 0; e < ITEMS; ++e) {
-    const uint32_t j = base + e * kBlock + threadIdx.x;
-    // a queued round that collided is redone from the next buffer: same list
-    if (gmode && coll && j < m) act_next[j] = act[j];
-    if (j < m && !coll) {
-      const uint32_t g = act[j];
-      block[g] = nb[j];
-      const uint32_t i = BATCH ? inst_of[g] : 0u;
-      if (keep[j] && changed_inst[i] && !(dead && dead[i])) fb |= 1u << e;
+      for (int e = 0; e < ITEMS; ++e) {
+        const uint32_t j = base + e * kBlock + threadIdx.x;
+        if (j < m) {
+          const uint32_t g = act[j];
+          const uint32_t so = slot_of[j];
+          bool shared = !(so & kSlotClaimedAlone);
+          if (!shared) {
+            if (dtab) {
+              shared = dtab[so & ~kSlotClaimedAlone] >= 2u;  // a count table: its word
+            } else if (notify[g]) {
+              notify[g] = 0;
+              shared = true;
+            }
+          }
+          block[g] = shared ? (kSlotLabel | (so & ~kSlotClaimedAlone)) : g;
+          if (shared) fb |= 1u << e;
+        }
+      }
+    }
+  } else {
+#pragma unroll 8
+    for (int e = 0; e < ITEMS; ++e) {
+      const uint32_t j = base + e * kBlock + threadIdx.x;
+      // a queued round that collided is redone from the next buffer: same list
+      if (gmode && coll && j < m) act_next[j] = act[j];
+      if (j < m && !coll) {
+        const uint32_t g = act[j];
+        block[g] = nb[j];
+        const uint32_t i = BATCH ? inst_of[g] : 0u;
+        if (keep[j] && changed_inst[i] && !(dead && dead[i])) fb |= 1u << e;
+      }
     }
   }
   const uint32_t total = tile_ballot_count<ITEMS>(fb, s_scan);
@@ -1348,6 +1425,179 @@ __global__ __launch_bounds__(kBlock) void k_results_jobs(const InstDesc* __restr
   res[j] = r;
 }
 
+// ------------------------------------------------- first round by labels
+// From P_0 = {F, Q\F} the first round of Algorithm 4 needs no grouping: the
+// signature of q is the accept bit of q and of each successor, and with at
+// most kMaxLabelLetters signature letters that bit string (own bit in bit
+// 0, letter t in bit t+1) is itself the exact key and a block label below
+// 256.  k_label writes the labels and the least member of every label
+// (lmin, 256 words per instance, all ones where absent); k_label_rank numbers
+// the labels present (rank8: the dense block numbers of the next round),
+// counts them and flags the instances that split; k_label_apply turns labels
+// into least-member ids and dense numbers.  Each workgroup covers kRowTile
+// states of one instance.
+// Algorithmic bytes per state: 1/8 (own bit) + kp * (4 + 1) (row entry, the
+// successor's bitmap byte) + 1 (label).
+__global__ __launch_bounds__(kBlock) void k_label(const InstDesc* __restrict__ desc,
+                                                  const uint32_t* __restrict__ job_wg_off, uint32_t ninst,
+                                                  const uint64_t* __restrict__ rows,
+                                                  uint32_t* __restrict__ lmin, uint8_t* __restrict__ label) {
+  static_assert(kBlock == 256, "one thread per label");
+  __shared__ uint32_t s_job;
+  __shared__ uint32_t s_min[256];
+  s_min[threadIdx.x] = 0xffffffffu;
+  const uint32_t i = find_job(job_wg_off, ninst, &s_job);
+  const InstDesc D = desc[i];
+  const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
+  const uint64_t* __restrict__ R = rows + D.rows_off;
+  const uint32_t kp = D.kp;
+  const uint32_t base = (blockIdx.x - job_wg_off[i]) * kRowTile;
+  uint32_t lab[4];
+  // every row entry of the tile first, then the bitmap gathers
+  uint32_t s[4][kMaxLabelLetters];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+#pragma unroll
+    for (uint32_t t = 0; t < kMaxLabelLetters; ++t)
+      if (t < kp && q < D.n) s[e][t] = reinterpret_cast<const uint32_t*>(R[t])[q];
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    lab[e] = 0;
+    if (q >= D.n) continue;
+    uint32_t L = (acc[q >> 3] >> (q & 7)) & 1u;
+#pragma unroll
+    for (uint32_t t = 0; t < kMaxLabelLetters; ++t)
+      if (t < kp) L |= ((acc[s[e][t] >> 3] >> (s[e][t] & 7)) & 1u) << (t + 1);
+    lab[e] = L;
+  }
+  __syncthreads();  // s_min initialised
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q >= D.n) continue;
+    label[D.state_off + q] = (uint8_t)lab[e];
+    atomicMin(&s_min[lab[e]], D.state_off + q);
+  }
+  __syncthreads();
+  const uint32_t v = s_min[threadIdx.x];
+  if (v != 0xffffffffu) {
+    // Workgroups of one instance run roughly in state order, so the word
+    // mostly holds a smaller member already.  A plain read can only be
+    // stale upwards (the word only decreases), which at worst costs an
+    // atomic that changes nothing.
+    uint32_t* p = &lmin[(size_t)i * 256 + threadIdx.x];
+    if (*p > v) atomicMin(p, v);
+  }
+}
+
+// One workgroup per instance, one thread per label.  Also clears the round
+// flags of the control block (no table is cleared in this round) and, with
+// set_m, sets m_next to m (every state stays active: no compaction).
+__global__ __launch_bounds__(kBlock) void k_label_rank(const uint32_t* __restrict__ lmin,
+                                                       uint8_t* __restrict__ rank8,
+                                                       uint32_t* __restrict__ counts,
+                                                       uint32_t* __restrict__ changed_inst,
+                                                       Ctrl* __restrict__ ctrl, uint32_t set_m, uint32_t m) {
+  __shared__ uint32_t s_cnt[kWaves], s_par;
+  const uint32_t i = blockIdx.x, L = threadIdx.x, lane = L & 63u, w = L >> 6;
+  if (L == 0) s_par = 0;
+  const bool present = lmin[(size_t)i * 256 + L] != 0xffffffffu;
+  const unsigned long long b = __ballot(present);
+  if (lane == 0) s_cnt[w] = (uint32_t)__popcll(b);
+  __syncthreads();
+  if (present) atomicOr(&s_par, 1u << (L & 1u));  // blocks of P_0 present: accept bit 0 and / or 1
+  uint32_t before = (uint32_t)__popcll(b & ((1ull << lane) - 1ull)), total = 0;
+#pragma unroll
+  for (int v = 0; v < kWaves; ++v) {
+    if (v < (int)w) before += s_cnt[v];
+    total += s_cnt[v];
+  }
+  rank8[(size_t)i * 256 + L] = (uint8_t)before;
+  __syncthreads();
+  if (L == 0) {
+    counts[i] = total;
+    if (total > (uint32_t)__builtin_popcount(s_par)) changed_inst[i] = 1u;
+    if (i == 0) {
+      ctrl->any_changed = 0u;
+      ctrl->collision = 0u;
+      if (set_m) ctrl->m_next = m;
+    }
+  }
+}
+
+// label[g] -> dense number rank8[label] (in place) and the label's least
+// member, written to block[g] or, for a compaction that follows, to nb[g]
+// with keep[g] = 1; act[g] = g (every state in order: list position and
+// state id agree) and inst_of[g] = i where given.  With nb, also clears the
+// scan status words and the tile counter of that compaction.
+// Algorithmic bytes per state: 1 (label) + 1 (dense) + 4 (id) + 4 (act)
+// [+4 inst_of, +1 keep].
+__global__ __launch_bounds__(kBlock) void k_label_apply(const InstDesc* __restrict__ desc,
+                                                        const uint32_t* __restrict__ job_wg_off,
+                                                        uint32_t ninst, const uint32_t* __restrict__ lmin,
+                                                        const uint8_t* __restrict__ rank8,
+                                                        uint8_t* __restrict__ label,
+                                                        uint32_t* __restrict__ block, uint32_t* __restrict__ nb,
+                                                        uint8_t* __restrict__ keep, Ctrl* __restrict__ ctrl,
+                                                        unsigned long long* __restrict__ scan_status,
+                                                        uint32_t ntiles, uint32_t* __restrict__ act,
+                                                        uint32_t* __restrict__ inst_of) {
+  __shared__ uint32_t s_job;
+  if (nb) {
+    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
+    for (uint32_t t = j; t < ntiles; t += gridDim.x * kBlock) store_status(&scan_status[t], 0ull);
+    if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
+  }
+  const uint32_t i = find_job(job_wg_off, ninst, &s_job);
+  const InstDesc D = desc[i];
+  const uint32_t* __restrict__ lm = lmin + (size_t)i * 256;
+  const uint8_t* __restrict__ rk = rank8 + (size_t)i * 256;
+  const uint32_t base = (blockIdx.x - job_wg_off[i]) * kRowTile;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q >= D.n) continue;
+    const uint32_t g = D.state_off + q;
+    const uint32_t L = label[g];
+    label[g] = rk[L];
+    act[g] = g;
+    if (inst_of) inst_of[g] = i;
+    if (nb) {
+      nb[g] = lm[L];
+      keep[g] = 1;
+    } else {
+      block[g] = lm[L];
+    }
+  }
+}
+
+// Every block a singleton (one instance): block q has least member q, so
+// its canonical number is q.  out[q] = q; the results follow.
+// Algorithmic bytes per state: 4 (out).
+__global__ __launch_bounds__(kBlock) void k_identity_out(const InstDesc* __restrict__ desc,
+                                                         const uint32_t* __restrict__ refine_cnt,
+                                                         ResultDev* __restrict__ res) {
+  const InstDesc D = desc[0];
+  uint32_t* __restrict__ out = reinterpret_cast<uint32_t*>(D.out);
+  const uint32_t base = blockIdx.x * kRowTile;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const uint32_t q = base + e * kBlock + threadIdx.x;
+    if (q < D.n) out[q] = q;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ResultDev r;
+    r.num_blocks = D.n;
+    r.initial_block = D.q0;
+    r.refine_rounds = refine_cnt[0];
+    r.pad = 0;
+    res[0] = r;
+  }
+}
+
 inline uint32_t grid_for(uint64_t items, uint64_t per_wg) {
   return (uint32_t)((items + per_wg - 1) / per_wg);
 }
@@ -1390,11 +1640,12 @@ void launch_init_block(const InstDesc* desc, const uint32_t* job_wg_off, uint32_
                      minN, inst_of, block, act);
 }
 
-void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode) {
+void launch_clear_table(Slot* table, uint64_t tsize, Ctrl* ctrl, hipStream_t s, int gmode,
+                        uint32_t* gcount) {
   uint32_t grid = grid_for(tsize, 2 * kBlock);
   if (grid > 65536u) grid = 65536u;
   if (grid == 0) grid = 1;
-  hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl, (uint32_t)gmode);
+  hipLaunchKernelGGL(k_clear_table, dim3(grid), dim3(kBlock), 0, s, table, tsize, ctrl, (uint32_t)gmode, gcount);
 }
 
 void launch_queue_start(Ctrl* ctrl, uint32_t m, uint64_t salt, hipStream_t s) {
@@ -1446,33 +1697,35 @@ template <bool BATCH, int SI>
 void launch_signature_si(int dw, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                          const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                          const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
-                         Ctrl* ctrl, hipStream_t s, uint32_t gm, uint8_t* notify) {
+                         Ctrl* ctrl, hipStream_t s, uint32_t gm, uint8_t* notify, uint32_t* gcount,
+                         uint32_t* dtab) {
   const dim3 grid(grid_for(m, kBlock * SI));
   if (dw == 1)
     hipLaunchKernelGGL((k_signature<BATCH, 1, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify, gcount, dtab);
   else if (dw == 2)
     hipLaunchKernelGGL((k_signature<BATCH, 2, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify, gcount, dtab);
   else
     hipLaunchKernelGGL((k_signature<BATCH, 4, SI>), grid, dim3(kBlock), 0, s, act, m, inst_of, desc, rows,
-                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify);
+                       block, dense, table, tbits, slot_of, salt, ctrl, gm, notify, gcount, dtab);
 }
 
 template <bool BATCH>
 void launch_signature_w(int dw, int variant, uint32_t m, const uint32_t* act, const uint32_t* inst_of,
                         const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                         const void* dense, Slot* table, uint32_t tbits, uint32_t* slot_of, uint64_t salt,
-                        Ctrl* ctrl, hipStream_t s, uint32_t gm, uint8_t* notify) {
+                        Ctrl* ctrl, hipStream_t s, uint32_t gm, uint8_t* notify, uint32_t* gcount,
+                        uint32_t* dtab) {
   if (variant == 0)
     launch_signature_si<BATCH, 1>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s, gm, notify);
+                                  ctrl, s, gm, notify, gcount, dtab);
   else if (variant == 2)
     launch_signature_si<BATCH, 4>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s, gm, notify);
+                                  ctrl, s, gm, notify, gcount, dtab);
   else
     launch_signature_si<BATCH, 2>(dw, m, act, inst_of, desc, rows, block, dense, table, tbits, slot_of, salt,
-                                  ctrl, s, gm, notify);
+                                  ctrl, s, gm, notify, gcount, dtab);
 }
 
 template <bool BATCH>
@@ -1492,14 +1745,14 @@ void launch_signature(bool batch, const uint32_t* act, uint32_t m, const uint32_
                       const InstDesc* desc, const uint64_t* rows, const uint32_t* block,
                       const void* dense, int dense_width, Slot* table, uint32_t tbits,
                       uint32_t* slot_of, uint64_t salt, Ctrl* ctrl, int variant, hipStream_t s,
-                      int gmode, uint8_t* notify) {
+                      int gmode, uint8_t* notify, uint32_t* gcount, uint32_t* dtab) {
   if (!m) return;
   if (batch)
     launch_signature_w<true>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
-                             slot_of, salt, ctrl, s, (uint32_t)gmode, notify);
+                             slot_of, salt, ctrl, s, (uint32_t)gmode, notify, gcount, dtab);
   else
     launch_signature_w<false>(dense_width, variant, m, act, inst_of, desc, rows, block, dense, table, tbits,
-                              slot_of, salt, ctrl, s, (uint32_t)gmode, notify);
+                              slot_of, salt, ctrl, s, (uint32_t)gmode, notify, gcount, dtab);
 }
 
 void launch_dense(bool batch, uint32_t N, const uint32_t* inst_of, const InstDesc* desc,
@@ -1523,38 +1776,47 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
                     const InstDesc* desc, const Slot* table,
                     const uint32_t* slot_of, const uint32_t* block, uint32_t* nb, uint8_t* keep,
                     uint32_t* changed_inst, Ctrl* ctrl, unsigned long long* scan_status,
-                    uint32_t ntiles, hipStream_t s, int gmode, uint8_t* notify) {
+                    uint32_t ntiles, hipStream_t s, int gmode, uint8_t* notify,
+                    const uint32_t* count_gcount) {
   if (!m) return;
   const uint32_t grid = grid_for(std::max(m, ntiles), kBlock);
   if (batch)
     hipLaunchKernelGGL(k_resolve<true>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
-                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode, notify);
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode, notify,
+                       count_gcount);
   else
     hipLaunchKernelGGL(k_resolve<false>, dim3(grid), dim3(kBlock), 0, s, act, m, inst_of, desc, table,
-                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode, notify);
+                       slot_of, block, nb, keep, changed_inst, ctrl, scan_status, ntiles, (uint32_t)gmode, notify,
+                       count_gcount);
 }
 
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
-                    const uint32_t* nb, const uint8_t* keep, const uint32_t* changed_inst,
+                    const uint32_t* nb, const uint8_t* keep, uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
-                    unsigned long long* scan_status, int items, hipStream_t s, int gmode) {
+                    unsigned long long* scan_status, int items, hipStream_t s, int gmode,
+                    const uint32_t* slot_of, uint8_t* notify, const uint32_t* gcount, uint32_t prev_count,
+                    const uint32_t* dtab) {
   if (!m) return;
   const dim3 grid(scan_tiles(m, items));
   const uint32_t gm = (uint32_t)gmode;
   if (items == kScanItemsLarge) {
     if (batch)
       hipLaunchKernelGGL((k_compact<true, kScanItemsLarge>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm,
+                         slot_of, notify, gcount, prev_count, dtab);
     else
       hipLaunchKernelGGL((k_compact<false, kScanItemsLarge>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm,
+                         slot_of, notify, gcount, prev_count, dtab);
   } else {
     if (batch)
       hipLaunchKernelGGL((k_compact<true, kScanItemsSmall>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm,
+                         slot_of, notify, gcount, prev_count, dtab);
     else
       hipLaunchKernelGGL((k_compact<false, kScanItemsSmall>), grid, dim3(kBlock), 0, s, act, m, inst_of, nb,
-                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm);
+                         keep, changed_inst, dead, block, act_next, ctrl, scan_status, gm,
+                         slot_of, notify, gcount, prev_count, dtab);
   }
 }
 
@@ -1621,6 +1883,25 @@ void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_
   else
     hipLaunchKernelGGL(k_dense_jobs<4>, grid, dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs, block, rank,
                        dense);
+}
+
+void launch_label(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst, uint32_t total_wgs,
+                  const uint64_t* rows, uint32_t* lmin, uint8_t* rank8, uint8_t* label, uint32_t* counts,
+                  uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block, uint32_t* nb, uint8_t* keep,
+                  unsigned long long* scan_status, uint32_t ntiles, uint32_t set_m, uint32_t m,
+                  uint32_t* act, uint32_t* inst_of, hipStream_t s) {
+  if (!total_wgs || !ninst) return;
+  hipLaunchKernelGGL(k_label, dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, rows, lmin, label);
+  hipLaunchKernelGGL(k_label_rank, dim3(ninst), dim3(kBlock), 0, s, lmin, rank8, counts, changed_inst, ctrl,
+                     set_m, m);
+  hipLaunchKernelGGL(k_label_apply, dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, lmin, rank8,
+                     label, block, nb, keep, ctrl, scan_status, ntiles, act, inst_of);
+}
+
+void launch_identity_out(const InstDesc* desc, uint32_t n, const uint32_t* refine_cnt, ResultDev* res,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_identity_out, dim3(std::max<uint32_t>(1, grid_for(n, kRowTile))), dim3(kBlock), 0, s,
+                     desc, refine_cnt, res);
 }
 
 void launch_results_jobs(const InstDesc* desc, const uint32_t* slot, uint32_t njobs,

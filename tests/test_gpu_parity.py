@@ -435,6 +435,83 @@ def test_table_insertion_orders_agree(ctx, monkeypatch, order):
         assert np.array_equal(o, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]), d.name
 
 
+def test_first_round_labels_and_table_agree(ctx, monkeypatch):
+    """From {F, Q\\F}, with at most 7 signature letters, the first round
+    labels every state by its own accept bit and those of its successors
+    (an exact key below 256) instead of grouping through the hash table.
+    One instance's exact-key round that a hash round follows leaves slot
+    labels for the states of shared groups instead of least members, with
+    no resolve step, and both rounds decide whether they split by counting
+    groups; where the key space allows, that round groups in a direct count
+    table.  A testing knob turns these off (bit 0: first-round labels, bit
+    1: slot labels, bit 2: direct tables).  Every setting gives the oracle's partition and the
+    same round counts and closure levels, alone and batched.  The batch
+    holds instances whose first round splits nothing (F empty, F = Q, no
+    non-identity letter), which leave it after that round, 1- and 7-letter
+    instances (labels of 2 and 8 bits) and an 8-letter one that keeps the
+    whole batch on the table."""
+    from paper_2410_22764_amd import dfamin
+    empty = W.random_dfa(40000, 3, 11)
+    empty.accept = W.pack_accept(np.zeros(empty.n, bool))
+    full = W.random_dfa(30000, 2, 12)
+    full.accept = W.pack_accept(np.ones(full.n, bool))
+    ident = W.from_rows(np.stack([np.arange(20000, dtype=np.uint32)] * 2),
+                        np.arange(20000) % 3 == 0, name="identity-letters")
+    cases = [W.random_dfa(20000, 3, 7), W.random_dfa(70000, 7, 3), W.random_dfa(5000, 1, 2),
+             W.permuted_chain_dfa(30000, 1, 3), W.chain_dfa(20000, 2), W.fib_dfa(14), empty, full, ident,
+             W.random_dfa(1, 1, 1)]
+    fields = ("num_blocks", "initial_block", "refine_rounds", "closure_levels", "closure_letters")
+    for closure in ("off", "auto"):
+        labelled = {}
+        for d in cases:
+            if closure == "off" and d.name.startswith("chain"):
+                continue  # one state per round: too many rounds to spend here
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            print(f"[case] first round by labels {d.name} closure={closure}", flush=True)
+            out, r = dfamin.dfamin_minimize(ctx, d, closure)
+            assert r["num_blocks"] == nb and np.array_equal(out, want), d.name
+            labelled[d.name] = r
+        for knob in ("1", "2", "3", "4"):
+            monkeypatch.setenv("DFAMIN_NO_LABELS", knob)
+            for d in cases:
+                if d.name not in labelled:
+                    continue
+                print(f"[case] labels off ({knob}) {d.name} closure={closure}", flush=True)
+                out, r = dfamin.dfamin_minimize(ctx, d, closure)
+                assert np.array_equal(out, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]), (knob, d.name)
+                assert all(r[f] == labelled[d.name][f] for f in fields), (knob, d.name, r, labelled[d.name])
+        monkeypatch.delenv("DFAMIN_NO_LABELS")
+    batch = [c for c in cases if not c.name.startswith("chain")]
+    for extra in ([], [W.random_dfa(30000, 8, 5)]):
+        print(f"[case] first round by labels, batch of {len(batch) + len(extra)}", flush=True)
+        outs, res = dfamin.dfamin_minimize_batch(ctx, batch + extra, "off")
+        for d, o, r in zip(batch + extra, outs, res):
+            want, nb, rounds = oracle.moore(d.n, d.k, d.delta, d.accept)
+            assert r["num_blocks"] == nb and np.array_equal(o, want) and r["refine_rounds"] == rounds, d.name
+
+
+def test_all_singleton_results_numbered_directly(ctx):
+    """When one instance's rounds end with every block a singleton (a split
+    round that keeps no state, or a count of n blocks), each state is its
+    own class: out = 0..n-1 without a numbering scan.  Random and chain DFAs
+    whose minimal DFA keeps every state, under both closure modes, and the
+    minimal DFA built from such a result."""
+    from paper_2410_22764_amd import dfamin
+    cases = [(W.permuted_chain_dfa(40000, 2, 9), "auto"), (W.chain_dfa(3000, 1), "off"),
+             (W.random_dfa(2, 1, 3), "off"), (W.random_dfa(100000, 4, 21), "off")]
+    for d, closure in cases:
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        print(f"[case] all singletons {d.name} closure={closure} ({nb} of {d.n} blocks)", flush=True)
+        out, r = dfamin.dfamin_minimize(ctx, d, closure)
+        assert r["num_blocks"] == nb and np.array_equal(out, want) and r["initial_block"] == want[d.q0]
+    d = cases[0][0]
+    assert oracle.hopcroft(d.n, d.k, d.delta, d.accept)[1] == d.n
+    m, dm, am, info, out = dfamin.dfamin_minimal_dfa(ctx, d, "auto")
+    em, edm, eam, eq0, enr = oracle.minimal_dfa(d.n, d.k, d.delta, d.accept, d.q0)
+    assert (m, info["q0"], info["reachable"]) == (em, eq0, enr)
+    assert np.array_equal(dm, edm) and np.array_equal(am, eam) and np.array_equal(out, np.arange(d.n))
+
+
 def test_validation_sees_every_row_entry(ctx):
     """The validation pass reads each δ row in 16-byte loads from its first
     16-byte boundary and the (up to three) entries before it one by one.
