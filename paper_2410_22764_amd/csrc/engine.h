@@ -153,6 +153,11 @@ class Engine {
   // then), stage_idle() after the stream has drained; an arena that runs out
   // drains the stream and grows.
   int upload(void* dst, const void* src, size_t bytes, hipStream_t s);
+  // Copies staged like upload() and byte fills, queued and then issued as
+  // one launch by flush_segs() (which a full queue calls by itself).
+  int stage_copy(void* dst, const void* src, size_t bytes, hipStream_t s);
+  int queue_fill(void* dst, uint32_t byte, size_t bytes, hipStream_t s);
+  int flush_segs(hipStream_t s);
   void stage_flip() {
     stage_cur_ ^= 1;
     stage_[stage_cur_].off = 0;
@@ -171,7 +176,7 @@ class Engine {
                   MinimalInfo& info, const uint32_t** min_delta, const uint8_t** min_acc);
  private:
   int leader_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
-  int upload_layout(hipStream_t s);
+  int upload_layout(hipStream_t s, bool queued = false);
   int check_hip(hipError_t e);
 
   Context* ctx_;
@@ -205,6 +210,7 @@ class Engine {
     size_t off = 0;
   };
   Stage stage_[2];
+  MemSegs segs_{};  // queued copies and fills (stage_copy, queue_fill)
   uint32_t stage_cur_ = 0;
   std::vector<char> lvl_host_;  // level jobs being assembled
   std::vector<RowJob> vjobs_;    // validation jobs of a call

@@ -266,6 +266,7 @@ uint64_t Engine::closure_cap() const {
 
 int Engine::upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   if (!bytes) return DFAMIN_OK;
+  TRY(flush_segs(s));  // queued copies first, in the order they were asked for
   Stage& st = stage_[stage_cur_];
   size_t at = (st.off + 15) & ~size_t(15);
   if (at + bytes > st.buf.cap) {
@@ -284,6 +285,40 @@ int Engine::upload(void* dst, const void* src, size_t bytes, hipStream_t s) {
   return check_hip(hipGetLastError());
 }
 
+int Engine::stage_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (!bytes) return DFAMIN_OK;
+  Stage& st = stage_[stage_cur_];
+  size_t at = (st.off + 15) & ~size_t(15);
+  if (at + bytes > st.buf.cap) {
+    // the queued copies read the arena: issue them before it is reused
+    TRY(flush_segs(s));
+    HIP(stream_wait(s));
+    stage_idle();
+    if (!fixed() || st.buf.cap < bytes)
+      TRY(ensure_host(st.buf, std::max<size_t>(2 * (at + bytes), size_t(64) << 10)));
+    at = 0;
+  }
+  std::memcpy(st.buf.as<char>() + at, src, bytes);
+  st.off = at + bytes;
+  if (segs_.n == kMemSegs) TRY(flush_segs(s));
+  segs_.seg[segs_.n++] = MemSeg{dst, static_cast<const char*>(st.buf.dp) + at, bytes, 0, 0};
+  return DFAMIN_OK;
+}
+
+int Engine::queue_fill(void* dst, uint32_t byte, size_t bytes, hipStream_t s) {
+  if (!bytes) return DFAMIN_OK;
+  if (segs_.n == kMemSegs) TRY(flush_segs(s));
+  segs_.seg[segs_.n++] = MemSeg{dst, nullptr, bytes, byte & 0xffu, 0};
+  return DFAMIN_OK;
+}
+
+int Engine::flush_segs(hipStream_t s) {
+  if (!segs_.n) return DFAMIN_OK;
+  launch_mem_segs(segs_, s);
+  segs_.n = 0;
+  return check_hip(hipGetLastError());
+}
+
 int Engine::readback(HostBuf& h, const void* src, size_t bytes, hipStream_t s) {
   if (!bytes) return DFAMIN_OK;
   if (h.cap < bytes || !h.dp) return DFAMIN_E_INTERNAL;
@@ -292,8 +327,9 @@ int Engine::readback(HostBuf& h, const void* src, size_t bytes, hipStream_t s) {
 }
 
 // Rebuild descriptors, row pointers and signature-record offsets from the
-// per-instance row lists and upload them.
-int Engine::upload_layout(hipStream_t s) {
+// per-instance row lists and upload them (queued: left in the copy queue for
+// the caller's flush_segs).
+int Engine::upload_layout(hipStream_t s, bool queued) {
   const size_t I = in_.size();
   rows_.clear();
   uint64_t sig_words = 0;
@@ -310,9 +346,9 @@ int Engine::upload_layout(hipStream_t s) {
   for (size_t i = 0; i < I; ++i) desc_[i].sig = reinterpret_cast<uint64_t>(d_sig_.p) + 4 * desc_[i].sig;
   TRY(ensure(d_desc_, I * sizeof(InstDesc)));
   TRY(ensure(d_rows_, std::max<size_t>(rows_.size(), 1) * 8));
-  TRY(upload(d_desc_.p, desc_.data(), I * sizeof(InstDesc), s));
-  if (!rows_.empty()) TRY(upload(d_rows_.p, rows_.data(), rows_.size() * 8, s));
-  return DFAMIN_OK;
+  TRY(stage_copy(d_desc_.p, desc_.data(), I * sizeof(InstDesc), s));
+  if (!rows_.empty()) TRY(stage_copy(d_rows_.p, rows_.data(), rows_.size() * 8, s));
+  return queued ? DFAMIN_OK : flush_segs(s);
 }
 
 // Partial transitive closure (Algorithm 5) for the listed instances.  Level
@@ -815,10 +851,9 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       for (uint32_t i : alist)
         if (desc_[i].kp > kMaxLabelLetters) return DFAMIN_E_INTERNAL;
       TRY(ensure(d_dense_, N * 4));
-      TRY(ensure(d_lbl_, I * 256 * 5));
+      // (lmin set to all ones by run_path)
       uint32_t* lmin = d_lbl_.as<uint32_t>();
       uint8_t* rank8 = reinterpret_cast<uint8_t*>(lmin + I * 256);
-      HIP(hipMemsetAsync(lmin, 0xff, I * 256 * 4, s));
       const int litems = scan_items_for(m);
       const uint32_t ltiles = scan_tiles(m, litems);
       double lb = 0;
@@ -1658,9 +1693,10 @@ int Engine::validate(hipStream_t s, std::vector<InstOutcome>& res) {
   TRY(ensure(d_flags_, jobs.size() * 4));
   TRY(ensure(d_wgflags_, (size_t)wgs * 4));
   TRY(ensure_host(h_flags_, jobs.size() * 4));
-  TRY(upload(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), s));
-  TRY(upload(d_joboff_.p, joboff.data(), joboff.size() * 4, s));
-  HIP(hipMemsetAsync(d_flags_.p, 0, jobs.size() * 4, s));
+  TRY(stage_copy(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), s));
+  TRY(stage_copy(d_joboff_.p, joboff.data(), joboff.size() * 4, s));
+  TRY(queue_fill(d_flags_.p, 0, jobs.size() * 4, s));
+  TRY(flush_segs(s));
   {
     double bytes = 0;
     for (auto& x : in_) bytes += 4.0 * x.n * x.k;
@@ -1799,24 +1835,6 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     if (!uni.empty()) TRY(lazy_levels(uni, opts, rest, lazy_));
   }
   const auto t_bufs = now();
-  TRY(upload_layout(s));
-  const auto t_layout = now();
-  // workgroup offsets of the per-instance init jobs
-  std::vector<uint32_t> inst_off(I);
-  uint32_t init_wgs = 0;
-  for (size_t i = 0; i < I; ++i) {
-    inst_off[i] = init_wgs;
-    init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
-  }
-  init_wgs_ = init_wgs;
-  TRY(upload(d_inst_off_.p, inst_off.data(), I * 4, s));
-  TRY(ensure(d_part_, (size_t)init_wgs * 8));
-  HIP(hipMemsetAsync(d_changed_.p, 0, I * 4, s));
-  // joiners' marks of lone slot claimers (each round's resolve step returns
-  // the ones it reads to 0)
-  HIP(hipMemsetAsync(d_notify_.p, 0, N, s));
-  HIP(hipMemsetAsync(d_refine_.p, 0, I * 4, s));
-  HIP(hipMemsetAsync(d_ctrl_.p, 0, sizeof(Ctrl), s));
   // testing: force the table insertion order of every signature round
   // (DFAMIN_CAS_FIRST=b: bit 0 hash-mode states, bit 1 exact-key states)
   cas_forced_ = -1;
@@ -1830,6 +1848,45 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     slots_off_ = (v & 2) != 0;
     direct_off_ = (v & 4) != 0;
   }
+  // The initial partition {F, Q\F} is not needed when the first round goes
+  // by labels (every instance with at most kMaxLabelLetters signature
+  // letters in that round; one-letter AUTO instances read one level), whose
+  // kernels write every block id, the active list and the instance map.
+  labels_planned_ = opts.method == DFAMIN_METHOD_SIGNATURE && !label_off_;
+  for (size_t i = 0; i < I && labels_planned_; ++i)
+    if ((lazy_[i] ? 1u : (uint32_t)inst_rows_[i].size()) > kMaxLabelLetters) labels_planned_ = false;
+  // the first round's key mode (accept bits), so that no descriptor changes
+  // for it unless a doubling instance reads one level
+  for (size_t i = 0; i < I; ++i) {
+    const uint32_t kp0 = lazy_[i] ? 1u : (uint32_t)inst_rows_[i].size();
+    desc_[i].ebits = desc_[i].dsrc = kp0 + 1 <= 31 ? 1u : 0u;
+  }
+  // Descriptors, row pointers, init job offsets and the cleared per-call
+  // state go out in one launch.
+  TRY(upload_layout(s, true));
+  const auto t_layout = now();
+  // workgroup offsets of the per-instance init jobs
+  std::vector<uint32_t> inst_off(I);
+  uint32_t init_wgs = 0;
+  for (size_t i = 0; i < I; ++i) {
+    inst_off[i] = init_wgs;
+    init_wgs += (in_[i].n + kRowTile - 1) / kRowTile;
+  }
+  init_wgs_ = init_wgs;
+  TRY(stage_copy(d_inst_off_.p, inst_off.data(), I * 4, s));
+  TRY(ensure(d_part_, (size_t)init_wgs * 8));
+  TRY(queue_fill(d_changed_.p, 0, I * 4, s));
+  // joiners' marks of lone slot claimers (each round's resolve step returns
+  // the ones it reads to 0)
+  TRY(queue_fill(d_notify_.p, 0, N, s));
+  TRY(queue_fill(d_refine_.p, 0, I * 4, s));
+  TRY(queue_fill(d_ctrl_.p, 0, sizeof(Ctrl), s));
+  if (labels_planned_) {
+    // the first round's least member per label: all ones (none yet)
+    TRY(ensure(d_lbl_, I * 256 * 5));
+    TRY(queue_fill(d_lbl_.p, 0xff, I * 256 * 4, s));
+  }
+  TRY(flush_segs(s));
   if (const char* e = std::getenv("DFAMIN_HASH_BITS")) {
     // testing: weak signature hashes (see Ctrl::hash_mask)
     const int bits = std::atoi(e);
@@ -1839,13 +1896,7 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
     }
   }
 
-  // ---- 4. initial partition {F, Q\F}: not needed when the first round
-  // goes by labels (every instance with at most kMaxLabelLetters signature
-  // letters in that round; one-letter AUTO instances read one level), whose
-  // kernels write every block id, the active list and the instance map
-  labels_planned_ = opts.method == DFAMIN_METHOD_SIGNATURE && !label_off_;
-  for (size_t i = 0; i < I && labels_planned_; ++i)
-    if ((lazy_[i] ? 1u : (uint32_t)inst_rows_[i].size()) > kMaxLabelLetters) labels_planned_ = false;
+  // ---- 4. initial partition {F, Q\F} (unless the first round goes by labels)
   if (!labels_planned_) {
     prof.begin(s, "init_minmax", (double)N / 8.0);
     launch_init_minmax(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs,

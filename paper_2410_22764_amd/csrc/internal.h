@@ -280,7 +280,9 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
 // set.  If not, no block id changes and no state stays.  The notify bytes
 // read are returned to 0.  With dtab (the round's direct count table) a
 // lone claimer's group is shared iff its word counts two or more, and no
-// notify byte is read.
+// notify byte is read; where at most one in 64 states formed a group alone,
+// every state stays active under its label instead (prev_shared is then
+// every group formed).
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,
@@ -307,6 +309,23 @@ void launch_store_u64(uint64_t* p, uint64_t v, hipStream_t s);
 // kernels such a copy costs a few microseconds, where a copy-engine transfer
 // of 32 KB or more adds about 15 us of hand-off in each direction.
 void launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
+// Small copies and fills batched into one launch (launch_mem_segs): src
+// non-null copies `bytes` from src (device memory, or page-locked host memory
+// mapped for the device) to dst, src null sets `bytes` bytes of dst to fill.
+// For host-to-device staging only: a copy to host memory needs
+// launch_copy_bytes, which makes its stores visible to the host.
+constexpr uint32_t kMemSegs = 8;
+struct MemSeg {
+  void* dst;
+  const void* src;
+  uint64_t bytes;
+  uint32_t fill, pad;
+};
+struct MemSegs {
+  MemSeg seg[kMemSegs];
+  uint32_t n;
+};
+void launch_mem_segs(const MemSegs& q, hipStream_t s);
 // Queued rounds of instances refining by doubling (one closure level per
 // round, 2^l <= j+1): per listed instance t (instance list[t]) the device
 // keeps j (mj), the levels built and the highest level read.  Before a

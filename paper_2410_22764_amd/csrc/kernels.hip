@@ -784,11 +784,16 @@ __global__ __launch_bounds__(kBlock) void k_compact(
     // slot labels: the round split iff it formed more groups than before
     const uint32_t formed = wave_sum(gcount[threadIdx.x]);
     const uint32_t shared = wave_sum(gcount[kGroupCounters + threadIdx.x]);
+    // A count table tells a lone claimer from a shared one only by a random
+    // read of its word.  Where groups of one state are rare, every state
+    // stays instead (a group of one stays a group of one, under a label):
+    // the groups kept are then all groups formed.
+    const bool keep_all = dtab && (formed - shared) * 64ull <= m;
     if (threadIdx.x == 0) {
-      s_split = formed > prev_count ? 1u : 0u;
-      if (blockIdx.x == 0 && s_split) {
+      s_split = (formed > prev_count ? 1u : 0u) | (keep_all ? 2u : 0u);
+      if (blockIdx.x == 0 && formed > prev_count) {
         changed_inst[0] = 1u;
-        ctrl->prev_shared = shared;
+        ctrl->prev_shared = keep_all ? formed : shared;
       }
     }
   }
@@ -799,14 +804,15 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   uint32_t fb = 0;
   if (slot_of) {
     // one instance, exact keys (no collision): ids change only if it split
-    if (s_split) {
+    if (s_split & 1u) {
+      const bool keep_all = (s_split & 2u) != 0;
 #pragma unroll 8
       for (int e = 0; e < ITEMS; ++e) {
         const uint32_t j = base + e * kBlock + threadIdx.x;
         if (j < m) {
           const uint32_t g = act[j];
           const uint32_t so = slot_of[j];
-          bool shared = !(so & kSlotClaimedAlone);
+          bool shared = keep_all || !(so & kSlotClaimedAlone);
           if (!shared) {
             if (dtab) {
               shared = dtab[so & ~kSlotClaimedAlone] >= 2u;  // a count table: its word
@@ -896,6 +902,24 @@ __global__ __launch_bounds__(kBlock) void k_copy_units(T* __restrict__ dst, cons
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
   for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < units; i += stride) dst[i] = src[i];
   __threadfence_system();
+}
+
+// Up to kMemSegs copies (src set) and byte fills (src null) in one launch:
+// every workgroup strides over every segment, 16 bytes at a time where the
+// segment allows it.
+__global__ __launch_bounds__(kBlock) void k_mem_segs(MemSegs q) {
+  const uint64_t t0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x, stride = (uint64_t)gridDim.x * kBlock;
+  for (uint32_t k = 0; k < q.n; ++k) {
+    const MemSeg g = q.seg[k];
+    uint8_t* d = static_cast<uint8_t*>(g.dst);
+    const uint8_t* sp = static_cast<const uint8_t*>(g.src);
+    const bool wide = ((reinterpret_cast<uintptr_t>(d) | reinterpret_cast<uintptr_t>(sp)) & 15u) == 0;
+    const uint64_t body = wide ? (g.bytes & ~uint64_t(15)) : 0;
+    const uint32_t f = g.fill * 0x01010101u;
+    for (uint64_t u = t0; u < body / 16; u += stride)
+      reinterpret_cast<uint4*>(d)[u] = sp ? reinterpret_cast<const uint4*>(sp)[u] : make_uint4(f, f, f, f);
+    for (uint64_t b = body + t0; b < g.bytes; b += stride) d[b] = sp ? sp[b] : (uint8_t)g.fill;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_queue_plan(QueueDbl q, InstDesc* __restrict__ desc,
@@ -1690,6 +1714,14 @@ void launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s) 
   else
     hipLaunchKernelGGL(k_copy_units<uint8_t>, dim3(grid), dim3(kBlock), 0, s, static_cast<uint8_t*>(dst),
                        static_cast<const uint8_t*>(src), units);
+}
+
+void launch_mem_segs(const MemSegs& q, hipStream_t s) {
+  if (!q.n) return;
+  uint64_t most = 0;
+  for (uint32_t k = 0; k < q.n; ++k) most = std::max<uint64_t>(most, q.seg[k].bytes);
+  const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((most / 16 + kBlock - 1) / kBlock, 1024));
+  hipLaunchKernelGGL(k_mem_segs, dim3(grid), dim3(kBlock), 0, s, q);
 }
 
 namespace {
