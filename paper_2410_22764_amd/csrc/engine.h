@@ -222,6 +222,10 @@ class Engine {
   bool slots_off_ = false;       // testing: no slot labels
   bool direct_off_ = false;      // testing: slot labels through the hash table only
   bool labels_planned_ = false;  // this call's first signature round goes by labels
+  uint32_t label_bits_ = 1;      // bits of its widest label (kp + 1)
+  std::vector<uint32_t> live_;   // per instance: still refining (after the first round)
+  // a batched call's letter lists, and those of the subset passed to run_path
+  std::vector<std::vector<uint32_t>> vnonid_, sub_nonid_;
   uint32_t init_wgs_ = 0;        // kRowTile-state jobs over all instances (d_inst_off_)
   bool all_single_ = false;      // single instance: the rounds ended with every block a singleton
   // captured leader-election rounds, reused while pointers and sizes match

@@ -813,7 +813,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       }
     }
     if (!exact.empty()) {
-      // dense numbers from the ranks of the previous scan
+      // dense numbers from the ranks of the previous scan (or the first
+      // round's label numbers, one byte each)
       dense_width = eb_max <= 8 ? 1 : (eb_max <= 16 ? 2 : 4);
       const uint32_t ne = (uint32_t)exact.size();
       uint32_t wgs = 0;
@@ -842,40 +843,35 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       }
     }
     // The first round by labels (launch_label): every instance has at most
-    // kMaxLabelLetters signature letters.  One instance keeps every state
-    // active (no compaction); a batch compacts away the instances that did
-    // not split.
+    // kMaxLabelLetters signature letters.  Every state stays active; in the
+    // rare batch where an instance did not split, a compaction then drops
+    // that instance's states.
     const bool label_round = rounds == 0 && labels_planned_ && !alist.empty();
     if (label_round) {
       // planned by run_path, which then left out the initial partition
       for (uint32_t i : alist)
-        if (desc_[i].kp > kMaxLabelLetters) return DFAMIN_E_INTERNAL;
+        if (desc_[i].kp + 1 > label_bits_) return DFAMIN_E_INTERNAL;
       TRY(ensure(d_dense_, N * 4));
       // (lmin set to all ones by run_path)
+      const uint32_t nl = label_bits_ <= 8 ? 256u : 512u, lw = label_bits_ <= 8 ? 1u : 2u;
       uint32_t* lmin = d_lbl_.as<uint32_t>();
-      uint8_t* rank8 = reinterpret_cast<uint8_t*>(lmin + I * 256);
+      void* rank = lmin + I * nl;
       const int litems = scan_items_for(m);
       const uint32_t ltiles = scan_tiles(m, litems);
       double lb = 0;
       // own bit, kp row entries and bitmap bytes, the label written, read and
       // rewritten, the id and the list entry [instance map, keep flag]
       for (size_t i = 0; i < I; ++i)
-        lb += (double)in_[i].n * (0.125 + 5.0 * desc_[i].kp + 11.0 + (batch ? 5.0 : 0.0));
+        lb += (double)in_[i].n * (0.125 + 5.0 * desc_[i].kp + 3.0 * lw + 8.0 + (batch ? 5.0 : 0.0));
       prof.begin(s, "label", lb);
+      // one-byte labels become the dense numbers in place; two-byte ones
+      // are kept in the (here unused) new-id array
       launch_label(d_desc_.as<InstDesc>(), d_inst_off_.as<uint32_t>(), (uint32_t)I, init_wgs_,
-                   d_rows_.as<uint64_t>(), lmin, rank8, d_dense_.as<uint8_t>(), d_counts_.as<uint32_t>(),
-                   d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(), d_block_.as<uint32_t>(),
-                   batch ? d_nb_.as<uint32_t>() : nullptr, d_keep_.as<uint8_t>(),
-                   d_status_.as<unsigned long long>(), ltiles, batch ? 0u : 1u, (uint32_t)m,
-                   d_act_.as<uint32_t>(), batch ? d_inst_of_.as<uint32_t>() : nullptr, s);
+                   d_rows_.as<uint64_t>(), label_bits_, lmin, rank, lw == 1 ? d_dense_.p : d_nb_.p,
+                   d_dense_.as<uint8_t>(), d_counts_.as<uint32_t>(), d_changed_.as<uint32_t>(), d_ctrl_.as<Ctrl>(),
+                   d_block_.as<uint32_t>(), 1u, (uint32_t)m, d_act_.as<uint32_t>(),
+                   batch ? d_inst_of_.as<uint32_t>() : nullptr, s);
       prof.end(s);
-      if (batch) {
-        prof.begin(s, "compact", (double)m * (4 + 4 + 4 + 1 + 4));
-        launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_nb_.as<uint32_t>(),
-                       d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(),
-                       nxt, d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), litems, s);
-        prof.end(s);
-      }
       launch_round_end((uint32_t)I, d_changed_.as<uint32_t>(), d_refine_.as<uint32_t>(), nullptr,
                        d_ctrl_.as<Ctrl>(), s);
       HIP(hipGetLastError());
@@ -893,14 +889,39 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       }
       if (trace) t_issue += us(tp0, now());
       ++rounds;
+      const size_t before = alist.size();
       settle(h_refine);
       dense_from_labels = true;
       if (I == 1) all_single_ = cnt[0] >= in_[0].n;
-      if (batch) {
+      if (!c.any_changed || alist.empty()) break;
+      if (alist.size() < before) {
+        // Some instance split nothing (or only into single states): its
+        // states leave the list, kept by a compaction whose per-instance
+        // flags are the instances still refining.
+        std::vector<uint32_t>& live = live_;
+        live.assign(I, 0);
+        for (uint32_t i : alist) live[i] = 1;
+        TRY(stage_copy(d_changed_.p, live.data(), I * 4, s));
+        TRY(queue_fill(d_keep_.p, 1, m, s));
+        TRY(flush_segs(s));
+        launch_prep_scan(d_status_.as<unsigned long long>(), ltiles, d_ctrl_.as<Ctrl>(), s);
+        prof.begin(s, "compact", (double)m * (4 + 4 + 4 + 1 + 4));
+        launch_compact(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_block_.as<uint32_t>(),
+                       d_keep_.as<uint8_t>(), d_changed_.as<uint32_t>(), nullptr, d_block_.as<uint32_t>(), nxt,
+                       d_ctrl_.as<Ctrl>(), d_status_.as<unsigned long long>(), litems, s);
+        prof.end(s);
+        TRY(queue_fill(d_changed_.p, 0, I * 4, s));
+        TRY(flush_segs(s));
+        HIP(hipGetLastError());
+        TRY(readback(h_rb_, d_rb_.p, sizeof(Ctrl), s));
+        HIP(stream_wait(s));
+        stage_flip();
+        prof.collect();
+        const Ctrl c2 = *h_rb_.as<Ctrl>();
+        if (c2.fault) return DFAMIN_E_INTERNAL;
         std::swap(cur, nxt);
-        m = c.m_next;
+        m = c2.m_next;
       }
-      if (!c.any_changed) break;
       continue;
     }
     // Table: twice the number of groups this round can form, at most m.  An
@@ -1587,21 +1608,22 @@ int Engine::run_all(const std::vector<InstInput>& in, const dfamin_opts& opts, h
   const uint64_t max_rounds = opts.max_rounds ? opts.max_rounds : (uint64_t)nmax + 1;
   res.assign(I, InstOutcome{});
   std::vector<uint32_t> handoff;
+  // (the letter lists are members that keep their capacity from call to
+  // call: a batch of thousands of instances then allocates none of them)
   auto subset = [&](const std::vector<uint32_t>& idx, std::vector<InstInput>& sub,
                     std::vector<std::vector<uint32_t>>& sub_nonid, const std::vector<std::vector<uint32_t>>& all) {
     sub.clear();
-    sub_nonid.clear();
-    for (uint32_t i : idx) {
-      sub.push_back(in[i]);
-      sub_nonid.push_back(all[i]);
+    if (sub_nonid.size() < idx.size()) sub_nonid.resize(idx.size());
+    for (size_t t = 0; t < idx.size(); ++t) {
+      sub.push_back(in[idx[t]]);
+      sub_nonid[t].assign(all[idx[t]].begin(), all[idx[t]].end());
     }
   };
   auto run_subset = [&](const std::vector<uint32_t>& idx, const std::vector<std::vector<uint32_t>>& all) {
     std::vector<InstInput> sub;
-    std::vector<std::vector<uint32_t>> sub_nonid;
-    subset(idx, sub, sub_nonid, all);
+    subset(idx, sub, sub_nonid_, all);
     std::vector<InstOutcome> sub_res;
-    const int rc = run_path(sub, opts, s, sub_res, &sub_nonid);
+    const int rc = run_path(sub, opts, s, sub_res, &sub_nonid_);
     if (rc == DFAMIN_OK)
       for (size_t t = 0; t < idx.size(); ++t) res[idx[t]] = sub_res[t];
     return rc;
@@ -1615,11 +1637,20 @@ int Engine::run_all(const std::vector<InstInput>& in, const dfamin_opts& opts, h
     if (handoff.empty()) return DFAMIN_OK;
     return run_path(in, opts, s, res);
   }
+  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto us_since = [&](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - a).count();
+  };
   in_ = in;
   stage_idle();
   stage_cur_ = 0;
   TRY(validate(s, res));
-  const std::vector<std::vector<uint32_t>> nonid_all = nonid_;
+  const double t_valid = us_since(t0);
+  // this call's letter lists, kept apart from nonid_, which the subsets' runs
+  // overwrite (the swap hands nonid_ the previous call's lists to reuse)
+  vnonid_.swap(nonid_);
+  const std::vector<std::vector<uint32_t>>& nonid_all = vnonid_;
   // With larger instances in the call, the fused kernels run on their own
   // stream beside the round engine's rounds (whose host syncs leave the GPU
   // idle now and then), after this call's validation.
@@ -1636,9 +1667,15 @@ int Engine::run_all(const std::vector<InstInput>& in, const dfamin_opts& opts, h
     HIP(hipStreamWaitEvent(fused_stream_, fused_ready_, 0));
     fs = fused_stream_;
   }
+  const double t_pre = us_since(t0);
   int frc = fused_issue(in, small, opts, max_rounds, fs);
   if (frc == DFAMIN_OK && fs != s) frc = check_hip(hipEventRecord(fused_done_, fs));
+  const double t_fused = us_since(t0);
   if (frc == DFAMIN_OK && !big.empty()) frc = run_subset(big, nonid_all);
+  if (trace)
+    std::fprintf(stderr, "[dfamin] batch of %zu (%zu fused): host us to validation %.0f, to fused issue %.0f, "
+                 "fused issued %.0f, round engine done %.0f\n", I, small.size(), t_valid, t_pre, t_fused,
+                 us_since(t0));
   if (frc != DFAMIN_OK) {
     if (fs != s && !ctx_->device_lost) (void)hipStreamSynchronize(fs);  // nothing of the call left queued
     return frc;
@@ -1667,6 +1704,12 @@ int Engine::run(const std::vector<InstInput>& in, const dfamin_opts& opts, hipSt
 int Engine::validate(hipStream_t s, std::vector<InstOutcome>& res) {
   const size_t I = in_.size();
   Profiler& prof = ctx_->prof;
+  const bool trace = std::getenv("DFAMIN_TRACE") != nullptr;
+  const auto v0 = std::chrono::steady_clock::now();
+  auto us_since = [&](std::chrono::steady_clock::time_point a) {
+    return std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - a).count();
+  };
+  double t_jobs = 0, t_issue = 0, t_wait = 0;
   // (the job vectors are members, so a call of the same shape allocates nothing)
   size_t njobs = 0;
   for (auto& x : in_) njobs += x.k;
@@ -1693,6 +1736,7 @@ int Engine::validate(hipStream_t s, std::vector<InstOutcome>& res) {
   TRY(ensure(d_flags_, jobs.size() * 4));
   TRY(ensure(d_wgflags_, (size_t)wgs * 4));
   TRY(ensure_host(h_flags_, jobs.size() * 4));
+  t_jobs = us_since(v0);
   TRY(stage_copy(d_jobs_.p, jobs.data(), jobs.size() * sizeof(RowJob), s));
   TRY(stage_copy(d_joboff_.p, joboff.data(), joboff.size() * 4, s));
   TRY(queue_fill(d_flags_.p, 0, jobs.size() * 4, s));
@@ -1707,11 +1751,13 @@ int Engine::validate(hipStream_t s, std::vector<InstOutcome>& res) {
     HIP(hipGetLastError());
   }
   TRY(readback(h_flags_, d_flags_.p, jobs.size() * 4, s));
+  t_issue = us_since(v0);
   HIP(stream_wait(s));
+  t_wait = us_since(v0);
   stage_idle();
   prof.collect();
   bool any_bad = false;
-  nonid_.resize(I);
+  if (nonid_.size() < I) nonid_.resize(I);  // (longer lists are left as they are)
   {
     // jobs are ordered (instance, letter): job j of instance i is letter j - first(i)
     const uint32_t* f = h_flags_.as<uint32_t>();
@@ -1729,6 +1775,9 @@ int Engine::validate(hipStream_t s, std::vector<InstOutcome>& res) {
       }
     }
   }
+  if (trace)
+    std::fprintf(stderr, "[dfamin] validation of %zu rows: host us jobs %.0f, issued %.0f, waited %.0f, done %.0f\n",
+                 jobs.size(), t_jobs, t_issue, t_wait, us_since(v0));
   return any_bad ? DFAMIN_E_BAD_DFA : DFAMIN_OK;
 }
 
@@ -1757,7 +1806,10 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
 
   // ---- 1. validation + identity letters (unless the call has done it)
   if (nonid) {
-    nonid_ = *nonid;
+    // element by element: the lists keep their capacity (nonid_ may stay
+    // longer than this call's instances)
+    if (nonid_.size() < I) nonid_.resize(I);
+    for (size_t i = 0; i < I; ++i) nonid_[i].assign((*nonid)[i].begin(), (*nonid)[i].end());
   } else {
     TRY(validate(s, res));
   }
@@ -1853,8 +1905,12 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   // letters in that round; one-letter AUTO instances read one level), whose
   // kernels write every block id, the active list and the instance map.
   labels_planned_ = opts.method == DFAMIN_METHOD_SIGNATURE && !label_off_;
-  for (size_t i = 0; i < I && labels_planned_; ++i)
-    if ((lazy_[i] ? 1u : (uint32_t)inst_rows_[i].size()) > kMaxLabelLetters) labels_planned_ = false;
+  label_bits_ = 1;
+  for (size_t i = 0; i < I && labels_planned_; ++i) {
+    const uint32_t kp0 = lazy_[i] ? 1u : (uint32_t)inst_rows_[i].size();
+    if (kp0 > kMaxLabelLetters) labels_planned_ = false;
+    label_bits_ = std::max(label_bits_, kp0 + 1);
+  }
   // the first round's key mode (accept bits), so that no descriptor changes
   // for it unless a doubling instance reads one level
   for (size_t i = 0; i < I; ++i) {
@@ -1882,9 +1938,11 @@ int Engine::run_path(const std::vector<InstInput>& in, const dfamin_opts& opts, 
   TRY(queue_fill(d_refine_.p, 0, I * 4, s));
   TRY(queue_fill(d_ctrl_.p, 0, sizeof(Ctrl), s));
   if (labels_planned_) {
-    // the first round's least member per label: all ones (none yet)
-    TRY(ensure(d_lbl_, I * 256 * 5));
-    TRY(queue_fill(d_lbl_.p, 0xff, I * 256 * 4, s));
+    // the first round's least member per label: all ones (none yet); then
+    // the labels' numbers, one or two bytes each
+    const size_t nl = label_bits_ <= 8 ? 256 : 512;
+    TRY(ensure(d_lbl_, I * nl * (label_bits_ <= 8 ? 5 : 6)));
+    TRY(queue_fill(d_lbl_.p, 0xff, I * nl * 4, s));
   }
   TRY(flush_segs(s));
   if (const char* e = std::getenv("DFAMIN_HASH_BITS")) {

@@ -385,24 +385,25 @@ void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_
                        void* dense, int dense_width, hipStream_t s);
 // The first signature round from {F, Q\F} by labels (instances of at most
 // kMaxLabelLetters signature letters): the label of q is its accept bit and
-// those of its successors, an exact key below 256.  Per instance (jobs of
-// kRowTile states, job_wg_off as for the init jobs): lmin (256 words per
+// those of its successors, an exact key of label_bits <= kMaxLabelLetters+1
+// bits.  NL = 256 labels per instance for label_bits <= 8, else 512; labels
+// and their numbers are then one byte, else two.  Per instance (jobs of
+// kRowTile states, job_wg_off as for the init jobs): lmin (NL words per
 // instance, all ones before the call) receives each label's least member,
-// rank8 (256 bytes per instance) the labels' numbers in order, counts[i] the
-// number of labels present, changed_inst[i] = 1 where that exceeds the
-// number of blocks of {F, Q\F}.  label (one byte per state) ends holding
-// dense block numbers and block[g] the least-member ids; with nb given, the
-// ids go to nb and keep[g] = 1 for a compaction that follows (whose scan
-// status words and tile counter are cleared).  act receives every state in
-// order and inst_of (nullable) each state's instance: the initial
-// partition need not be computed first.  The round flags of ctrl are
-// cleared, and with set_m m_next is set to m.
-constexpr uint32_t kMaxLabelLetters = 7;
+// rank (NL per instance) the labels' numbers in order, counts[i] the number
+// of labels present, changed_inst[i] = 1 where that exceeds the number of
+// blocks of {F, Q\F}.  label (one per state, scratch) holds the labels;
+// then block[g] = the least-member id, dense[g] = the label's number in one
+// byte (every instance whose next round groups on exact keys has at most 32
+// blocks; dense may be label itself when labels are one byte), act[g] = g
+// and inst_of[g] = i (nullable): the initial partition need not be
+// computed first.  The round flags of ctrl are cleared, and with set_m
+// m_next is set to m (every state stays active).
+constexpr uint32_t kMaxLabelLetters = 8;
 void launch_label(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst, uint32_t total_wgs,
-                  const uint64_t* rows, uint32_t* lmin, uint8_t* rank8, uint8_t* label, uint32_t* counts,
-                  uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block, uint32_t* nb, uint8_t* keep,
-                  unsigned long long* scan_status, uint32_t ntiles, uint32_t set_m, uint32_t m,
-                  uint32_t* act, uint32_t* inst_of, hipStream_t s);
+                  const uint64_t* rows, uint32_t label_bits, uint32_t* lmin, void* rank, void* label,
+                  uint8_t* dense, uint32_t* counts, uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block,
+                  uint32_t set_m, uint32_t m, uint32_t* act, uint32_t* inst_of, hipStream_t s);
 // One instance whose blocks are all singletons: out[q] = q and its results
 // (n blocks, initial block q0).
 void launch_identity_out(const InstDesc* desc, uint32_t n, const uint32_t* refine_cnt, ResultDev* res,

@@ -1454,22 +1454,23 @@ __global__ __launch_bounds__(kBlock) void k_results_jobs(const InstDesc* __restr
 // signature of q is the accept bit of q and of each successor, and with at
 // most kMaxLabelLetters signature letters that bit string (own bit in bit
 // 0, letter t in bit t+1) is itself the exact key and a block label below
-// 256.  k_label writes the labels and the least member of every label
-// (lmin, 256 words per instance, all ones where absent); k_label_rank numbers
-// the labels present (rank8: the dense block numbers of the next round),
+// NL (256 with up to 7 letters, stored in a byte; 512 with 8, in two bytes,
+// type LT).  k_label writes the labels and the least member of every label
+// (lmin, NL words per instance, all ones where absent); k_label_rank numbers
+// the labels present (rank: the dense block numbers of the next round),
 // counts them and flags the instances that split; k_label_apply turns labels
 // into least-member ids and dense numbers.  Each workgroup covers kRowTile
 // states of one instance.
 // Algorithmic bytes per state: 1/8 (own bit) + kp * (4 + 1) (row entry, the
-// successor's bitmap byte) + 1 (label).
+// successor's bitmap byte) + sizeof(LT) (label).
+template <int NL, typename LT>
 __global__ __launch_bounds__(kBlock) void k_label(const InstDesc* __restrict__ desc,
                                                   const uint32_t* __restrict__ job_wg_off, uint32_t ninst,
                                                   const uint64_t* __restrict__ rows,
-                                                  uint32_t* __restrict__ lmin, uint8_t* __restrict__ label) {
-  static_assert(kBlock == 256, "one thread per label");
+                                                  uint32_t* __restrict__ lmin, LT* __restrict__ label) {
   __shared__ uint32_t s_job;
-  __shared__ uint32_t s_min[256];
-  s_min[threadIdx.x] = 0xffffffffu;
+  __shared__ uint32_t s_min[NL];
+  for (uint32_t l = threadIdx.x; l < (uint32_t)NL; l += kBlock) s_min[l] = 0xffffffffu;
   const uint32_t i = find_job(job_wg_off, ninst, &s_job);
   const InstDesc D = desc[i];
   const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
@@ -1502,44 +1503,47 @@ __global__ __launch_bounds__(kBlock) void k_label(const InstDesc* __restrict__ d
   for (int e = 0; e < 4; ++e) {
     const uint32_t q = base + e * kBlock + threadIdx.x;
     if (q >= D.n) continue;
-    label[D.state_off + q] = (uint8_t)lab[e];
+    label[D.state_off + q] = (LT)lab[e];
     atomicMin(&s_min[lab[e]], D.state_off + q);
   }
   __syncthreads();
-  const uint32_t v = s_min[threadIdx.x];
-  if (v != 0xffffffffu) {
+  for (uint32_t l = threadIdx.x; l < (uint32_t)NL; l += kBlock) {
+    const uint32_t v = s_min[l];
+    if (v == 0xffffffffu) continue;
     // Workgroups of one instance run roughly in state order, so the word
     // mostly holds a smaller member already.  A plain read can only be
     // stale upwards (the word only decreases), which at worst costs an
     // atomic that changes nothing.
-    uint32_t* p = &lmin[(size_t)i * 256 + threadIdx.x];
+    uint32_t* p = &lmin[(size_t)i * NL + l];
     if (*p > v) atomicMin(p, v);
   }
 }
 
-// One workgroup per instance, one thread per label.  Also clears the round
-// flags of the control block (no table is cleared in this round) and, with
-// set_m, sets m_next to m (every state stays active: no compaction).
-__global__ __launch_bounds__(kBlock) void k_label_rank(const uint32_t* __restrict__ lmin,
-                                                       uint8_t* __restrict__ rank8,
-                                                       uint32_t* __restrict__ counts,
-                                                       uint32_t* __restrict__ changed_inst,
-                                                       Ctrl* __restrict__ ctrl, uint32_t set_m, uint32_t m) {
-  __shared__ uint32_t s_cnt[kWaves], s_par;
+// One workgroup of NL threads per instance, one thread per label.  Also
+// clears the round flags of the control block (no table is cleared in this
+// round) and, with set_m, sets m_next to m (every state stays active: no
+// compaction).
+template <int NL, typename LT>
+__global__ __launch_bounds__(NL) void k_label_rank(const uint32_t* __restrict__ lmin, LT* __restrict__ rank,
+                                                   uint32_t* __restrict__ counts,
+                                                   uint32_t* __restrict__ changed_inst,
+                                                   Ctrl* __restrict__ ctrl, uint32_t set_m, uint32_t m) {
+  constexpr int kW = NL / 64;
+  __shared__ uint32_t s_cnt[kW], s_par;
   const uint32_t i = blockIdx.x, L = threadIdx.x, lane = L & 63u, w = L >> 6;
   if (L == 0) s_par = 0;
-  const bool present = lmin[(size_t)i * 256 + L] != 0xffffffffu;
+  const bool present = lmin[(size_t)i * NL + L] != 0xffffffffu;
   const unsigned long long b = __ballot(present);
   if (lane == 0) s_cnt[w] = (uint32_t)__popcll(b);
   __syncthreads();
   if (present) atomicOr(&s_par, 1u << (L & 1u));  // blocks of P_0 present: accept bit 0 and / or 1
   uint32_t before = (uint32_t)__popcll(b & ((1ull << lane) - 1ull)), total = 0;
 #pragma unroll
-  for (int v = 0; v < kWaves; ++v) {
+  for (int v = 0; v < kW; ++v) {
     if (v < (int)w) before += s_cnt[v];
     total += s_cnt[v];
   }
-  rank8[(size_t)i * 256 + L] = (uint8_t)before;
+  rank[(size_t)i * NL + L] = (LT)before;
   __syncthreads();
   if (L == 0) {
     counts[i] = total;
@@ -1552,33 +1556,28 @@ __global__ __launch_bounds__(kBlock) void k_label_rank(const uint32_t* __restric
   }
 }
 
-// label[g] -> dense number rank8[label] (in place) and the label's least
-// member, written to block[g] or, for a compaction that follows, to nb[g]
-// with keep[g] = 1; act[g] = g (every state in order: list position and
-// state id agree) and inst_of[g] = i where given.  With nb, also clears the
-// scan status words and the tile counter of that compaction.
-// Algorithmic bytes per state: 1 (label) + 1 (dense) + 4 (id) + 4 (act)
-// [+4 inst_of, +1 keep].
+// label[g] -> the label's least member in block[g], the label's number in
+// dense[g] (one byte: an instance whose next round groups on exact keys
+// has at most 32 blocks, as (kp+1) * ceil(log2 B) <= 31 with B <= 2^(kp+1)
+// gives ceil(log2 B) <= 5; for the others the byte is never read), act[g] =
+// g (every state in order: list position and state id agree) and
+// inst_of[g] = i where given.  With one-byte labels, dense may be label
+// itself (each thread reads its state's label before it writes there).
+// Algorithmic bytes per state: sizeof(LT) (label) + 1 (dense) + 4 (id) + 4
+// (act) [+4 inst_of].
+template <int NL, typename LT>
 __global__ __launch_bounds__(kBlock) void k_label_apply(const InstDesc* __restrict__ desc,
                                                         const uint32_t* __restrict__ job_wg_off,
                                                         uint32_t ninst, const uint32_t* __restrict__ lmin,
-                                                        const uint8_t* __restrict__ rank8,
-                                                        uint8_t* __restrict__ label,
-                                                        uint32_t* __restrict__ block, uint32_t* __restrict__ nb,
-                                                        uint8_t* __restrict__ keep, Ctrl* __restrict__ ctrl,
-                                                        unsigned long long* __restrict__ scan_status,
-                                                        uint32_t ntiles, uint32_t* __restrict__ act,
+                                                        const LT* __restrict__ rank, const LT* label,
+                                                        uint8_t* dense, uint32_t* __restrict__ block,
+                                                        uint32_t* __restrict__ act,
                                                         uint32_t* __restrict__ inst_of) {
   __shared__ uint32_t s_job;
-  if (nb) {
-    const uint32_t j = blockIdx.x * kBlock + threadIdx.x;
-    for (uint32_t t = j; t < ntiles; t += gridDim.x * kBlock) store_status(&scan_status[t], 0ull);
-    if (j == 0) atomicExch(&ctrl->tile_counter, 0u);
-  }
   const uint32_t i = find_job(job_wg_off, ninst, &s_job);
   const InstDesc D = desc[i];
-  const uint32_t* __restrict__ lm = lmin + (size_t)i * 256;
-  const uint8_t* __restrict__ rk = rank8 + (size_t)i * 256;
+  const uint32_t* __restrict__ lm = lmin + (size_t)i * NL;
+  const LT* __restrict__ rk = rank + (size_t)i * NL;
   const uint32_t base = (blockIdx.x - job_wg_off[i]) * kRowTile;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
@@ -1586,15 +1585,10 @@ __global__ __launch_bounds__(kBlock) void k_label_apply(const InstDesc* __restri
     if (q >= D.n) continue;
     const uint32_t g = D.state_off + q;
     const uint32_t L = label[g];
-    label[g] = rk[L];
+    dense[g] = (uint8_t)rk[L];
+    block[g] = lm[L];
     act[g] = g;
     if (inst_of) inst_of[g] = i;
-    if (nb) {
-      nb[g] = lm[L];
-      keep[g] = 1;
-    } else {
-      block[g] = lm[L];
-    }
   }
 }
 
@@ -1917,17 +1911,32 @@ void launch_dense_jobs(const InstDesc* desc, const uint32_t* slot, const uint32_
                        dense);
 }
 
+namespace {
+template <int NL, typename LT>
+void launch_label_t(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst, uint32_t total_wgs,
+                    const uint64_t* rows, uint32_t* lmin, void* rank, void* label, uint8_t* dense,
+                    uint32_t* counts, uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block, uint32_t set_m,
+                    uint32_t m, uint32_t* act, uint32_t* inst_of, hipStream_t s) {
+  hipLaunchKernelGGL((k_label<NL, LT>), dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, rows, lmin,
+                     static_cast<LT*>(label));
+  hipLaunchKernelGGL((k_label_rank<NL, LT>), dim3(ninst), dim3(NL), 0, s, lmin, static_cast<LT*>(rank), counts,
+                     changed_inst, ctrl, set_m, m);
+  hipLaunchKernelGGL((k_label_apply<NL, LT>), dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, lmin,
+                     static_cast<const LT*>(rank), static_cast<const LT*>(label), dense, block, act, inst_of);
+}
+}  // namespace
+
 void launch_label(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst, uint32_t total_wgs,
-                  const uint64_t* rows, uint32_t* lmin, uint8_t* rank8, uint8_t* label, uint32_t* counts,
-                  uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block, uint32_t* nb, uint8_t* keep,
-                  unsigned long long* scan_status, uint32_t ntiles, uint32_t set_m, uint32_t m,
-                  uint32_t* act, uint32_t* inst_of, hipStream_t s) {
+                  const uint64_t* rows, uint32_t label_bits, uint32_t* lmin, void* rank, void* label,
+                  uint8_t* dense, uint32_t* counts, uint32_t* changed_inst, Ctrl* ctrl, uint32_t* block,
+                  uint32_t set_m, uint32_t m, uint32_t* act, uint32_t* inst_of, hipStream_t s) {
   if (!total_wgs || !ninst) return;
-  hipLaunchKernelGGL(k_label, dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, rows, lmin, label);
-  hipLaunchKernelGGL(k_label_rank, dim3(ninst), dim3(kBlock), 0, s, lmin, rank8, counts, changed_inst, ctrl,
-                     set_m, m);
-  hipLaunchKernelGGL(k_label_apply, dim3(total_wgs), dim3(kBlock), 0, s, desc, job_wg_off, ninst, lmin, rank8,
-                     label, block, nb, keep, ctrl, scan_status, ntiles, act, inst_of);
+  if (label_bits <= 8)
+    launch_label_t<256, uint8_t>(desc, job_wg_off, ninst, total_wgs, rows, lmin, rank, label, dense, counts,
+                                 changed_inst, ctrl, block, set_m, m, act, inst_of, s);
+  else
+    launch_label_t<512, uint16_t>(desc, job_wg_off, ninst, total_wgs, rows, lmin, rank, label, dense, counts,
+                                  changed_inst, ctrl, block, set_m, m, act, inst_of, s);
 }
 
 void launch_identity_out(const InstDesc* desc, uint32_t n, const uint32_t* refine_cnt, ResultDev* res,

@@ -436,9 +436,10 @@ def test_table_insertion_orders_agree(ctx, monkeypatch, order):
 
 
 def test_first_round_labels_and_table_agree(ctx, monkeypatch):
-    """From {F, Q\\F}, with at most 7 signature letters, the first round
+    """From {F, Q\\F}, with at most 8 signature letters, the first round
     labels every state by its own accept bit and those of its successors
-    (an exact key below 256) instead of grouping through the hash table.
+    (an exact key below 256, or 512 with 8 letters, stored in two bytes)
+    instead of grouping through the hash table.
     One instance's exact-key round that a hash round follows leaves slot
     labels for the states of shared groups instead of least members, with
     no resolve step, and both rounds decide whether they split by counting
@@ -447,9 +448,11 @@ def test_first_round_labels_and_table_agree(ctx, monkeypatch):
     1: slot labels, bit 2: direct tables).  Every setting gives the oracle's partition and the
     same round counts and closure levels, alone and batched.  The batch
     holds instances whose first round splits nothing (F empty, F = Q, no
-    non-identity letter), which leave it after that round, 1- and 7-letter
-    instances (labels of 2 and 8 bits) and an 8-letter one that keeps the
-    whole batch on the table."""
+    non-identity letter), which leave it after that round, and 1- and
+    7-letter instances (labels of 2 and 8 bits); it runs as it is, with an
+    8-letter instance (9-bit labels for the whole batch, whose 7-letter
+    instance then reads two-byte dense numbers in its exact second round)
+    and with a 9-letter one (the whole batch through the table)."""
     from paper_2410_22764_amd import dfamin
     empty = W.random_dfa(40000, 3, 11)
     empty.accept = W.pack_accept(np.zeros(empty.n, bool))
@@ -457,9 +460,13 @@ def test_first_round_labels_and_table_agree(ctx, monkeypatch):
     full.accept = W.pack_accept(np.ones(full.n, bool))
     ident = W.from_rows(np.stack([np.arange(20000, dtype=np.uint32)] * 2),
                         np.arange(20000) % 3 == 0, name="identity-letters")
+    # (8,192 and 12,000 states over 3 letters: a second round in a count
+    # table where most groups have one state, so the compaction reads the
+    # counts of lone claimers; 65,536 over 4: keys too wide for a count table)
     cases = [W.random_dfa(20000, 3, 7), W.random_dfa(70000, 7, 3), W.random_dfa(5000, 1, 2),
              W.permuted_chain_dfa(30000, 1, 3), W.chain_dfa(20000, 2), W.fib_dfa(14), empty, full, ident,
-             W.random_dfa(1, 1, 1)]
+             W.random_dfa(1, 1, 1), W.random_dfa(8192, 3, 17), W.random_dfa(12000, 3, 18),
+             W.random_dfa(65536, 4, 19), W.random_dfa(40000, 8, 23)]
     fields = ("num_blocks", "initial_block", "refine_rounds", "closure_levels", "closure_letters")
     for closure in ("off", "auto"):
         labelled = {}
@@ -481,8 +488,8 @@ def test_first_round_labels_and_table_agree(ctx, monkeypatch):
                 assert np.array_equal(out, oracle.hopcroft(d.n, d.k, d.delta, d.accept)[0]), (knob, d.name)
                 assert all(r[f] == labelled[d.name][f] for f in fields), (knob, d.name, r, labelled[d.name])
         monkeypatch.delenv("DFAMIN_NO_LABELS")
-    batch = [c for c in cases if not c.name.startswith("chain")]
-    for extra in ([], [W.random_dfa(30000, 8, 5)]):
+    batch = [c for c in cases if not c.name.startswith("chain") and c.k != 8]
+    for extra in ([], [W.random_dfa(30000, 8, 5)], [W.random_dfa(30000, 9, 5)]):
         print(f"[case] first round by labels, batch of {len(batch) + len(extra)}", flush=True)
         outs, res = dfamin.dfamin_minimize_batch(ctx, batch + extra, "off")
         for d, o, r in zip(batch + extra, outs, res):
