@@ -716,6 +716,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
   };
   // the dense numbers of the coming round were written by the first round's labels
   bool dense_from_labels = false;
+  // key bits of a count table cleared behind the last round's copy (0: none)
+  uint32_t dtab_ready = 0;
   all_single_ = false;
   // slot labels (launch_compact) for one instance, unless rounds are queued
   // (their resolve steps compare ids) or a testing knob turns them off; and
@@ -877,7 +879,24 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       HIP(hipGetLastError());
       // control block, refine counters and every instance's label count
       TRY(readback(h_rb_, d_rb_.p, sizeof(Ctrl) + 8 * I, s));
-      HIP(stream_wait(s));
+      // One instance's next round may group in a count table of at most
+      // (kp+1)^2 key bits: it is cleared behind the copy, while the host
+      // waits and plans (wasted only if this round was the last).
+      dtab_ready = 0;
+      const bool lover = !prof.enabled();
+      if (lover) {
+        if (!ev_rb_) HIP(hipEventCreateWithFlags(&ev_rb_, hipEventDisableTiming));
+        HIP(hipEventRecord(ev_rb_, s));
+        const uint32_t bits = (desc_[0].kp + 1u) * (desc_[0].kp + 1u);
+        if (!batch && slots_ok && !direct_off_ && !fixed() && bits <= kDirectMaxBits && bits >= 1 &&
+            (1ull << bits) <= 8ull * m) {
+          TRY(ensure(d_dtab_, 4ull << bits));
+          launch_clear_table(d_dtab_.as<Slot>(), 1ull << (bits - 1), d_ctrl_.as<Ctrl>(), s, 0, gcount);
+          HIP(hipGetLastError());
+          dtab_ready = bits;
+        }
+      }
+      HIP(lover ? event_wait(ev_rb_) : stream_wait(s));
       stage_flip();
       prof.collect();
       const Ctrl c = *h_rb_.as<Ctrl>();
@@ -1128,10 +1147,12 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       // (the group counters are cleared with the count table: a hash table
       // cleared ahead would no longer come with cleared counters)
       spec_clear = 0;
-      TRY(ensure(d_dtab_, 4ull << dwidth));
-      prof.begin(s, "clear_table", 4.0 * (double)(1ull << dwidth));
-      launch_clear_table(d_dtab_.as<Slot>(), 1ull << (dwidth - 1), d_ctrl_.as<Ctrl>(), s, 0, gcount);
-      prof.end(s);
+      if (dwidth > dtab_ready) {  // else cleared behind the last round's copy
+        TRY(ensure(d_dtab_, 4ull << dwidth));
+        prof.begin(s, "clear_table", 4.0 * (double)(1ull << dwidth));
+        launch_clear_table(d_dtab_.as<Slot>(), 1ull << (dwidth - 1), d_ctrl_.as<Ctrl>(), s, 0, gcount);
+        prof.end(s);
+      }
       prof.begin(s, "signature", md * sig_bytes());
       launch_signature(batch, cur, (uint32_t)m, d_inst_of_.as<uint32_t>(), d_desc_.as<InstDesc>(),
                        d_rows_.as<uint64_t>(), d_block_.as<uint32_t>(), d_dense_.p, dense_width,
@@ -1154,6 +1175,7 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     } else {
       spec_clear = 0;
     }
+    dtab_ready = 0;  // the count table cleared ahead serves this round only
     // (through the hash table, lone claimers must be marked: no tuning run)
     const bool slot_round = slot_cand && (direct || (!tuned_now && tbits <= 31));
     if (slot_round) {
@@ -1244,7 +1266,15 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
         TRY(queue_levels(todo, s));
         todo.clear();
       }
-      if (tsize <= kClearAheadSlots) {
+      if (slot_round) {
+        // a hash round follows if this one split: its table (at most twice
+        // this round's active states) is cleared now, while the host plans
+        const uint64_t next = 1ull << std::max<uint32_t>(9, ceil_log2_u64(2 * m));
+        TRY(ensure(d_table_, next * sizeof(Slot)));
+        launch_clear_table(d_table_.as<Slot>(), next, d_ctrl_.as<Ctrl>(), s, 0, gcount);
+        HIP(hipGetLastError());
+        spec_clear = next;
+      } else if (tsize <= kClearAheadSlots) {
         launch_clear_table(d_table_.as<Slot>(), tsize, d_ctrl_.as<Ctrl>(), s, 0, gcount);
         HIP(hipGetLastError());
         spec_clear = tsize;
@@ -1284,7 +1314,8 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
     // one instance, and this round split blocks and kept no state (every
     // block is a singleton), or counted n blocks
     if (I == 1) all_single_ = (c.any_changed && c.m_next == 0) || (cnt_ok[0] && cnt[0] >= in_[0].n);
-    std::swap(cur, nxt);
+    // (a slot round that kept every state may have left its list in place)
+    if (!(slot_round && c.m_next == m)) std::swap(cur, nxt);
     m = c.m_next;
     t_post += us(tp3, now());
     if (!c.any_changed) break;

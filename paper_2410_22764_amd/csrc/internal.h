@@ -282,7 +282,8 @@ void launch_resolve(bool batch, const uint32_t* act, uint32_t m, const uint32_t*
 // lone claimer's group is shared iff its word counts two or more, and no
 // notify byte is read; where at most one in 64 states formed a group alone,
 // every state stays active under its label instead (prev_shared is then
-// every group formed).
+// every group formed), and act_next is not written: m_next = m, and the
+// caller keeps act as the list of the next round.
 void launch_compact(bool batch, const uint32_t* act, uint32_t m, const uint32_t* inst_of,
                     const uint32_t* nb, const uint8_t* keep, uint32_t* changed_inst,
                     const uint32_t* dead, uint32_t* block, uint32_t* act_next, Ctrl* ctrl,

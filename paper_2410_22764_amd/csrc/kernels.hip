@@ -802,6 +802,20 @@ __global__ __launch_bounds__(kBlock) void k_compact(
   const bool coll = s_coll != 0;
   const uint32_t base = tile * (kBlock * ITEMS);
   uint32_t fb = 0;
+  if (slot_of && (s_split & 3u) == 3u) {
+    // every state stays, under its label: the list is left as it is (the
+    // caller keeps using it) and only the labels are written
+#pragma unroll 8
+    for (int e = 0; e < ITEMS; ++e) {
+      const uint32_t j = base + e * kBlock + threadIdx.x;
+      if (j < m) {
+        const uint32_t g = act[j];
+        block[g] = kSlotLabel | (slot_of[j] & ~kSlotClaimedAlone);
+      }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicExch(&ctrl->m_next, m);
+    return;
+  }
   if (slot_of) {
     // one instance, exact keys (no collision): ids change only if it split
     if (s_split & 1u) {
