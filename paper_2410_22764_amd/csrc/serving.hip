@@ -646,13 +646,25 @@ struct Serving::Impl {
       std::vector<uint32_t> depth;
       int rc = build_closure_levels(specs, sc, stream, rows, depth);
       if (rc != DFAMIN_OK) return rc;
+      // The signature records for the new letter count come first: where
+      // the budget has no room for them, the resident keeps refining on its
+      // plain letters (sound: any subset of closure letters is) and its
+      // level storage goes back, instead of failing every request.
+      const size_t sz = (size_t)r->req->n * (rows[0].size() + 1) * 4;
+      void* sig = sz <= r->sz_sig ? r->d_sig : (pool.live() + sz <= pool.budget() ? pool.alloc(sz) : nullptr);
+      if (!sig) {
+        for (auto& cb : r->closure_bufs) pool.free(cb.first, cb.second);
+        r->closure_bufs.clear();
+        continue;
+      }
+      if (sig != r->d_sig) {
+        pool.free(r->d_sig, r->sz_sig);
+        r->d_sig = sig;
+        r->sz_sig = sz;
+      }
       r->rows = rows[0];
       r->levels = depth[0];
       r->closure = true;
-      pool.free(r->d_sig, r->sz_sig);
-      r->sz_sig = (size_t)r->req->n * (r->rows.size() + 1) * 4;
-      r->d_sig = pool.alloc(r->sz_sig);
-      if (!r->d_sig) return DFAMIN_E_NOMEM;
       desc[r->slot].sig = reinterpret_cast<uint64_t>(r->d_sig);
     }
     return DFAMIN_OK;
@@ -1063,7 +1075,8 @@ struct Serving::Impl {
     if (!auto_closure.empty()) {
       int rc = build_closures(auto_closure);
       if (rc != DFAMIN_OK) return rc;
-      for (Resident* r : auto_closure) r->dbl = r->nonid.size() == 1;
+      // (one that kept its plain letters for want of room refines plainly)
+      for (Resident* r : auto_closure) r->dbl = r->closure && r->nonid.size() == 1;
       desc_dirty = true;
     }
     if (desc_dirty) {

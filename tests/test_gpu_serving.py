@@ -198,3 +198,39 @@ def test_doubling_requests_report_as_alone(ctx):
         for f in ("num_blocks", "initial_block", "refine_rounds", "rounds_executed", "closure_levels",
                   "closure_letters"):
             assert res[f] == ra[f], (d.name, f, res, ra)
+
+
+def _double_step_chain(n, seed):
+    """A chain on which both letters move forward (one or two states): two
+    non-identity letters, about n/2 plain rounds, so AUTO gives it the
+    closure after its first rounds."""
+    ids = np.arange(n, dtype=np.uint32)
+    rows = np.stack([np.minimum(ids + 1, n - 1), np.minimum(ids + 2, n - 1)])
+    acc = np.zeros(n, bool)
+    acc[n - 1] = True
+    d = W.from_rows(rows, acc, 0, f"double-step chain(n={n})")
+    return W.permute_dfa(d, W.random_permutation(n, seed), f"double-step chain(n={n},seed={seed})")
+
+
+def test_small_budget_deep_auto_requests():
+    """A context whose HBM budget leaves the serving loop a few MB: deep
+    requests with two non-identity letters under AUTO all come due for the
+    closure at once, and a unary chain refines by doubling beside them.
+    Level storage runs short (a closure then keeps the levels it has), and a
+    request whose signature records for the new letter count do not fit
+    keeps refining on its plain letters: every request still ends with the
+    oracle's partition, none fails."""
+    from paper_2410_22764_amd import dfamin
+    c = dfamin.dfamin_create(0, hbm_budget_bytes=8 << 20)
+    try:
+        ds = [_double_step_chain(6000, 31 + i) for i in range(10)]
+        ds.append(W.permuted_chain_dfa(6000, 2, 41))
+        print(f"[case] serving {len(ds)} deep requests under an 8 MB budget", flush=True)
+        tickets = [dfamin.dfamin_submit(c, d, "auto") for d in ds]
+        for d, t in zip(ds, tickets):
+            rc, out, res = dfamin.dfamin_wait(c, t, d.n, timeout_us=60_000_000)
+            assert rc == dfamin.DFAMIN_OK, (d.name, rc)
+            want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            assert res["num_blocks"] == nb and np.array_equal(out, want) and res["initial_block"] == want[d.q0]
+    finally:
+        c.close()
