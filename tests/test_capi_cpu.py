@@ -116,3 +116,20 @@ def test_noalloc_size_limit_matches_header():
     assert m and int(m.group(1)) << int(m.group(2)) == dfamin.NOALLOC_SCRATCH_BYTES
     assert "n * (66 + 16 * (k + 1)) + 2^20" in text
     assert dfamin.noalloc_fits(579_000, 2) and not dfamin.noalloc_fits(579_500, 2)
+
+
+def test_exact_keys_after_a_label_round_fit_one_byte():
+    """After the first round by labels, the next round's dense numbers are
+    written one byte wide.  That is sound because a round groups on exact
+    keys only when (k'+1) * ceil(log2 B) <= 31, and after the label round
+    B <= 2^(k'+1) with k' >= 0 signature letters (the engine's rule, here
+    for every k' and every B that rule can meet, with the same at-least-one
+    bit as the engine): such a round never has more than 32 blocks."""
+    def ceil_log2(x):
+        return max(1, (x - 1).bit_length())
+    worst = 0
+    for kp in range(0, 9):  # up to 8 signature letters: labels of kp+1 <= 9 bits
+        for blocks in range(1, 2 ** (kp + 1) + 1):
+            if (kp + 1) * ceil_log2(blocks) <= 31:
+                worst = max(worst, blocks)
+    assert worst == 32 and worst <= 256
