@@ -1297,9 +1297,11 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       cnt_ok[scan[j]] = 1;
     }
     if (prof.enabled() && std::getenv("DFAMIN_TRACE"))
-      std::fprintf(stderr, "[dfamin] round %llu: m=%llu table=2^%u next=%u changed=%u collision=%u exact=%zu\n",
+      std::fprintf(stderr,
+                   "[dfamin] round %llu: m=%llu table=2^%u next=%u changed=%u collision=%u exact=%zu slot=%d "
+                   "direct=%d\n",
                    (unsigned long long)rounds + 1, (unsigned long long)m, tbits, c.m_next, c.any_changed,
-                   c.collision, exact.size());
+                   c.collision, exact.size(), (int)slot_round, (int)direct);
     if (c.collision) {
       // the partition is unchanged, so the counts just taken still hold
       if (++retries > (int)kMaxSaltRetries) return DFAMIN_E_INTERNAL;
