@@ -861,10 +861,10 @@ int Engine::signature_rounds(const dfamin_opts& opts, uint64_t max_rounds, hipSt
       const int litems = scan_items_for(m);
       const uint32_t ltiles = scan_tiles(m, litems);
       double lb = 0;
-      // own bit, kp row entries and bitmap bytes, the label written, read and
-      // rewritten, the id and the list entry [instance map, keep flag]
+      // own bit, kp row entries and bitmap bytes, the label written and read,
+      // the dense byte, the id and the list entry [instance map]
       for (size_t i = 0; i < I; ++i)
-        lb += (double)in_[i].n * (0.125 + 5.0 * desc_[i].kp + 3.0 * lw + 8.0 + (batch ? 5.0 : 0.0));
+        lb += (double)in_[i].n * (0.125 + 5.0 * desc_[i].kp + 2.0 * lw + 1.0 + 8.0 + (batch ? 4.0 : 0.0));
       prof.begin(s, "label", lb);
       // one-byte labels become the dense numbers in place; two-byte ones
       // are kept in the (here unused) new-id array
