@@ -359,11 +359,13 @@ void launch_naive_round(bool batch, uint32_t N, uint32_t ninst, const uint32_t* 
                         uint32_t* next_leader, uint8_t* differs, uint32_t* changed_inst, uint32_t* refine_cnt,
                         Ctrl* ctrl, hipStream_t s);
 // Instances joining a running set: like launch_init_block, with instance
-// ids slot[j] for job j and their states appended to act at act_off[j].
+// ids slot[j] for job j and their states appended to act at act_off[j];
+// zero_a/b/c[slot[j]] (per-slot counters) are set to 0.
 void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
                       uint32_t njobs, uint32_t total_wgs, const uint32_t* act_off,
                       const uint32_t* minF, const uint32_t* minN, uint32_t* inst_of,
-                      uint32_t* block, uint32_t* act, hipStream_t s);
+                      uint32_t* block, uint32_t* act, uint32_t* zero_a, uint32_t* zero_b, uint32_t* zero_c,
+                      hipStream_t s);
 void launch_init_minmax_slots(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
                               uint32_t njobs, uint32_t total_wgs, unsigned long long* wg_part,
                               uint32_t* minF, uint32_t* minN, hipStream_t s);

@@ -1327,11 +1327,19 @@ __global__ __launch_bounds__(kBlock) void k_init_join(const InstDesc* __restrict
                                                       const uint32_t* __restrict__ minN,
                                                       uint32_t* __restrict__ inst_of,
                                                       uint32_t* __restrict__ block,
-                                                      uint32_t* __restrict__ act) {
+                                                      uint32_t* __restrict__ act,
+                                                      uint32_t* __restrict__ zero_a,
+                                                      uint32_t* __restrict__ zero_b,
+                                                      uint32_t* __restrict__ zero_c) {
   __shared__ uint32_t s_job;
   const uint32_t j = find_job(job_wg_off, njobs, &s_job);
   const uint32_t i = slot[j];
   const InstDesc D = desc[i];
+  if (blockIdx.x == job_wg_off[j] && threadIdx.x == 0) {  // the slot's counters start at 0
+    zero_a[i] = 0u;
+    zero_b[i] = 0u;
+    zero_c[i] = 0u;
+  }
   const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(D.accept);
   const uint32_t base = (blockIdx.x - job_wg_off[j]) * kRowTile;
   const uint32_t f = D.state_off + minF[i], nf = D.state_off + minN[i];
@@ -1872,10 +1880,11 @@ void launch_round_end(uint32_t ninst, uint32_t* changed_inst, uint32_t* refine_c
 void launch_init_join(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,
                       uint32_t njobs, uint32_t total_wgs, const uint32_t* act_off,
                       const uint32_t* minF, const uint32_t* minN, uint32_t* inst_of,
-                      uint32_t* block, uint32_t* act, hipStream_t s) {
+                      uint32_t* block, uint32_t* act, uint32_t* zero_a, uint32_t* zero_b, uint32_t* zero_c,
+                      hipStream_t s) {
   if (!total_wgs) return;
   hipLaunchKernelGGL(k_init_join, dim3(total_wgs), dim3(kBlock), 0, s, desc, slot, job_wg_off, njobs,
-                     act_off, minF, minN, inst_of, block, act);
+                     act_off, minF, minN, inst_of, block, act, zero_a, zero_b, zero_c);
 }
 
 void launch_init_minmax_slots(const InstDesc* desc, const uint32_t* slot, const uint32_t* job_wg_off,

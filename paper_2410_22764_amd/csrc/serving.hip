@@ -341,7 +341,8 @@ struct Serving::Impl {
   uint64_t table_cap = 0;
   // scratch that grows
   DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux, s_fjobs, s_fres;
-  HostBuf h_flags, h_ctrl, h_last, h_results, h_fres;
+  HostBuf h_flags, h_ctrl, h_results, h_fres;  // h_ctrl: a Ctrl, then the per-slot flags of d_last
+  uint32_t* h_last() { return reinterpret_cast<uint32_t*>(static_cast<char*>(h_ctrl.p) + sizeof(Ctrl)); }
 
   void shutdown() {
     {
@@ -400,14 +401,15 @@ struct Serving::Impl {
       if (r) release_resident(r);
     slots.clear();
     void** ps[] = {&d_block, &d_inst_of, &d_act, &d_act2, &d_slot_of, &d_nb, &d_keep, &d_rank,
-                   &d_status, &d_table, &d_desc, &d_rows, &d_changed, &d_last, &d_refine, &d_dead,
+                   &d_status, &d_table, &d_desc, &d_rows, &d_changed, &d_refine, &d_dead,
                    &d_minF, &d_minN, &d_ctrl, &d_results, &d_totals};
     for (void** p : ps)
       if (*p) { (void)hipFree(*p); *p = nullptr; }
+    d_last = nullptr;  // part of d_ctrl's allocation
     DevBuf* db[] = {&s_jobs, &s_off, &s_flags, &s_wg, &s_part, &s_slot, &s_aux, &s_fjobs, &s_fres};
     for (DevBuf* b : db)
       if (b->p) { (void)hipFree(b->p); b->p = nullptr; b->cap = 0; }
-    HostBuf* hb[] = {&h_flags, &h_ctrl, &h_last, &h_results, &h_fres};
+    HostBuf* hb[] = {&h_flags, &h_ctrl, &h_results, &h_fres};
     for (HostBuf* b : hb)
       if (b->p) { (void)hipHostFree(b->p); b->p = nullptr; b->cap = 0; }
     pool.release_all();
@@ -439,23 +441,25 @@ struct Serving::Impl {
     table_cap = 1ull << std::max<uint32_t>(9, ceil_log2_u64(2 * cap));
     d_table = dmalloc(table_cap * sizeof(Slot));
     d_desc = dmalloc(kSlots * sizeof(InstDesc));
-    d_changed = dmalloc(kSlots * 4); d_last = dmalloc(kSlots * 4);
+    d_changed = dmalloc(kSlots * 4);
     d_refine = dmalloc(kSlots * 4); d_dead = dmalloc(kSlots * 4);
     d_minF = dmalloc(kSlots * 4); d_minN = dmalloc(kSlots * 4);
-    d_ctrl = dmalloc(sizeof(Ctrl)); d_results = dmalloc(kSlots * sizeof(ResultDev));
+    // the round's control words and per-slot "still refining" flags sit
+    // together, so one copy reads both back
+    d_ctrl = dmalloc(sizeof(Ctrl) + kSlots * 4); d_results = dmalloc(kSlots * sizeof(ResultDev));
     d_totals = dmalloc(kSlots * 4);
     void* all[] = {d_block, d_inst_of, d_act, d_act2, d_slot_of, d_nb, d_keep, d_rank, d_status,
-                   d_table, d_desc, d_changed, d_last, d_refine, d_dead, d_minF, d_minN, d_ctrl,
+                   d_table, d_desc, d_changed, d_refine, d_dead, d_minF, d_minN, d_ctrl,
                    d_results, d_totals};
     for (void* p : all)
       if (!p) return DFAMIN_E_NOMEM;
+    d_last = static_cast<char*>(d_ctrl) + sizeof(Ctrl);
     if (hipMemsetAsync(d_changed, 0, kSlots * 4, stream) != hipSuccess ||
         hipMemsetAsync(d_refine, 0, kSlots * 4, stream) != hipSuccess ||
         hipMemsetAsync(d_dead, 0, kSlots * 4, stream) != hipSuccess ||
         hipMemsetAsync(d_ctrl, 0, sizeof(Ctrl), stream) != hipSuccess)
       return DFAMIN_E_DEVICE;
-    if (!grow_host(h_ctrl, sizeof(Ctrl)) || !grow_host(h_last, kSlots * 4) ||
-        !grow_host(h_results, kSlots * sizeof(ResultDev)))
+    if (!grow_host(h_ctrl, sizeof(Ctrl) + kSlots * 4) || !grow_host(h_results, kSlots * sizeof(ResultDev)))
       return DFAMIN_E_NOMEM;
     arena.reset(cap);
     slots.assign(kSlots, nullptr);
@@ -606,10 +610,20 @@ struct Serving::Impl {
         hipMemcpyAsync(d_rows, rows_host.data(), rows_host.size() * 8, hipMemcpyHostToDevice, stream) !=
             hipSuccess)
       return DFAMIN_E_DEVICE;
-    if (hipMemcpyAsync(d_desc, desc.data(), kSlots * sizeof(InstDesc), hipMemcpyHostToDevice, stream) !=
-        hipSuccess)
+    // slots are taken lowest first: the occupied ones lie below slot_hi()
+    const uint32_t hi = slot_hi();
+    if (hi && hipMemcpyAsync(d_desc, desc.data(), hi * sizeof(InstDesc), hipMemcpyHostToDevice, stream) !=
+                  hipSuccess)
       return DFAMIN_E_DEVICE;
     return DFAMIN_OK;
+  }
+
+  // One past the highest occupied slot.
+  uint32_t slot_hi() const {
+    uint32_t hi = 0;
+    for (uint32_t s = 0; s < (uint32_t)slots.size(); ++s)
+      if (slots[s]) hi = s + 1;
+    return hi;
   }
 
   ClosureScratch scratch() {
@@ -881,25 +895,19 @@ struct Serving::Impl {
     int rc = upload_layout();
     if (rc != DFAMIN_OK) return rc;
     // reset per-slot counters and build the initial partition
-    std::vector<uint32_t> slot_ids, wgoff, actoff;
-    uint32_t iw = 0, am = m;
-    for (Resident* r : js) {
-      slot_ids.push_back(r->slot);
-      wgoff.push_back(iw);
-      actoff.push_back(am);
-      iw += (r->req->n + kRowTile - 1) / kRowTile;
-      am += r->req->n;
-      if (hipMemsetAsync(static_cast<uint32_t*>(d_changed) + r->slot, 0, 4, stream) != hipSuccess ||
-          hipMemsetAsync(static_cast<uint32_t*>(d_refine) + r->slot, 0, 4, stream) != hipSuccess ||
-          hipMemsetAsync(static_cast<uint32_t*>(d_dead) + r->slot, 0, 4, stream) != hipSuccess)
-        return DFAMIN_E_DEVICE;
-    }
     const size_t nj = js.size();
+    std::vector<uint32_t> jl(3 * nj);  // slot ids, workgroup offsets, act offsets
+    uint32_t iw = 0, am = m;
+    for (size_t j = 0; j < nj; ++j) {
+      jl[j] = js[j]->slot;
+      jl[nj + j] = iw;
+      jl[2 * nj + j] = am;
+      iw += (js[j]->req->n + kRowTile - 1) / kRowTile;
+      am += js[j]->req->n;
+    }
     if (!grow(s_slot, nj * 4 * 3) || !grow(s_part, (size_t)iw * 8)) return DFAMIN_E_NOMEM;
     uint32_t* d_sl = s_slot.as<uint32_t>();
-    if (hipMemcpyAsync(d_sl, slot_ids.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(d_sl + nj, wgoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-        hipMemcpyAsync(d_sl + 2 * nj, actoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+    if (hipMemcpyAsync(d_sl, jl.data(), nj * 4 * 3, hipMemcpyHostToDevice, stream) != hipSuccess)
       return DFAMIN_E_DEVICE;
     launch_init_minmax_slots(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, iw,
                              s_part.as<unsigned long long>(), static_cast<uint32_t*>(d_minF),
@@ -907,7 +915,8 @@ struct Serving::Impl {
     launch_init_join(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, iw, d_sl + 2 * nj,
                      static_cast<uint32_t*>(d_minF), static_cast<uint32_t*>(d_minN),
                      static_cast<uint32_t*>(d_inst_of), static_cast<uint32_t*>(d_block),
-                     static_cast<uint32_t*>(d_act), stream);
+                     static_cast<uint32_t*>(d_act), static_cast<uint32_t*>(d_changed),
+                     static_cast<uint32_t*>(d_refine), static_cast<uint32_t*>(d_dead), stream);
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     // host vectors must outlive the asynchronous copies
     if (stream_wait(stream) != hipSuccess) return DFAMIN_E_DEVICE;
@@ -1030,8 +1039,8 @@ struct Serving::Impl {
         launch_round_end(kSlots, static_cast<uint32_t*>(d_changed), static_cast<uint32_t*>(d_refine),
                          static_cast<uint32_t*>(d_last), static_cast<Ctrl*>(d_ctrl), stream);
         if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
-        if (hipMemcpyAsync(h_ctrl.p, d_ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-            hipMemcpyAsync(h_last.p, d_last, kSlots * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        if (hipMemcpyAsync(h_ctrl.p, d_ctrl, sizeof(Ctrl) + 4ull * slot_hi(), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
             stream_wait(stream) != hipSuccess)
           return DFAMIN_E_DEVICE;
         const Ctrl c = *h_ctrl.as<Ctrl>();
@@ -1046,10 +1055,10 @@ struct Serving::Impl {
         break;
       }
     } else {
-      std::memset(h_last.p, 0, kSlots * 4);
+      std::memset(h_last(), 0, kSlots * 4);
     }
     // who is done, who needs the closure, whose next round hashes
-    const uint32_t* last = h_last.as<uint32_t>();
+    const uint32_t* last = h_last();
     std::vector<Resident*> done, auto_closure;
     bool desc_dirty = false;
     for (uint32_t s = 0; s < kSlots; ++s) {
