@@ -398,6 +398,15 @@ def serving_run(ctx, seed, count, pool_size, load, threads=256, submitters=16):
     span = float(arrivals[-1])
     wall = max(done) - start
     trans = sum(pool[int(o)].transitions for o in order)
+    # every request crosses the host link: delta and bitmap in, one id per state out
+    bin_ = sum(4 * d.n * d.k + d.accept.nbytes for d in pool) / len(pool)
+    bout = sum(4 * d.n for d in pool) / len(pool)
+    h2d, d2h = pinned_copy_rates()
+    link = {"in_GBps_at_saturation": round(sat * bin_ / 1e9, 2), "out_GBps_at_saturation": round(sat * bout / 1e9, 2),
+            "pinned_h2d_GBps": round(h2d, 2), "pinned_d2h_GBps": round(d2h, 2),
+            "in_frac": round(sat * bin_ / 1e9 / h2d, 3),
+            "note": "mean request input and output bytes of the pool times the saturation rate, against one "
+                    "256 MiB page-locked copy in each direction"}
     return {"requests": count, "pool": pool_size, "offered_rate_per_s": round(rate, 2),
             "offered_rate_realised_per_s": round(count / span, 2),
             "saturation_dfas_per_s": round(sat, 2), "load": load, "dfas_per_s": round(count / wall, 2),
@@ -409,7 +418,28 @@ def serving_run(ctx, seed, count, pool_size, load, threads=256, submitters=16):
             "submit_lag_ms": {"p50": round(1e3 * float(np.percentile(lag, 50)), 3),
                               "p99": round(1e3 * float(np.percentile(lag, 99)), 3)},
             "client": f"arrivals scheduled by one thread, submitted by a pool of {threads} worker threads; "
-                      f"saturation from {submitters} submitting threads, closed loop over the pool"}
+                      f"saturation from {submitters} submitting threads, closed loop over the pool",
+            "host_link": link}
+
+
+def pinned_copy_rates(mib=256, reps=5):
+    """GB/s of one page-locked host buffer copied to the device and back."""
+    import torch
+    h = torch.empty(mib << 20, dtype=torch.uint8, pin_memory=True)
+    d = torch.empty(mib << 20, dtype=torch.uint8, device="cuda")
+    rates = []
+    for src, dst in ((h, d), (d, h)):
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src, non_blocking=True)
+        e1.record()
+        torch.cuda.synchronize()
+        rates.append(reps * (mib << 20) / (e0.elapsed_time(e1) * 1e-3) / 1e9)
+    del h, d
+    return rates[0], rates[1]
 
 
 def main():

@@ -931,23 +931,21 @@ struct Serving::Impl {
       if (!r->dead) live.push_back(r);
     if (!live.empty()) {
       const size_t nj = live.size();
-      std::vector<uint32_t> slot_ids, tileoff, wgoff;
+      std::vector<uint32_t> jl(3 * nj);  // slot ids, scan tile offsets, workgroup offsets
       uint32_t tiles = 0, wgs = 0;
       uint64_t states = 0;
       for (Resident* r : live) states += r->req->n;
       const int items = scan_items_for(states);
-      for (Resident* r : live) {
-        slot_ids.push_back(r->slot);
-        tileoff.push_back(tiles);
-        wgoff.push_back(wgs);
-        tiles += scan_tiles(r->req->n, items);
-        wgs += (r->req->n + kRowTile - 1) / kRowTile;
+      for (size_t j = 0; j < nj; ++j) {
+        jl[j] = live[j]->slot;
+        jl[nj + j] = tiles;
+        jl[2 * nj + j] = wgs;
+        tiles += scan_tiles(live[j]->req->n, items);
+        wgs += (live[j]->req->n + kRowTile - 1) / kRowTile;
       }
       if (!grow(s_aux, nj * 4 * 3)) return DFAMIN_E_NOMEM;
       uint32_t* d_sl = s_aux.as<uint32_t>();
-      if (hipMemcpyAsync(d_sl, slot_ids.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-          hipMemcpyAsync(d_sl + nj, tileoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-          hipMemcpyAsync(d_sl + 2 * nj, wgoff.data(), nj * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
+      if (hipMemcpyAsync(d_sl, jl.data(), nj * 4 * 3, hipMemcpyHostToDevice, stream) != hipSuccess)
         return DFAMIN_E_DEVICE;
       launch_prep_scan(static_cast<unsigned long long*>(d_status), tiles, static_cast<Ctrl*>(d_ctrl), stream);
       launch_scan_jobs(static_cast<InstDesc*>(d_desc), d_sl, d_sl + nj, (uint32_t)nj, tiles,
