@@ -219,7 +219,9 @@ def config_legs(ctx, reps=30):
     """The small single-instance configurations, each timed over `reps`
     device-resident calls: the random DFA of 16,384 states (seeds 1..5) and
     the 2^20-state chain (closure AUTO, the default, and ON), with the oracle
-    on the same input beside each."""
+    on the same input beside each; then the rows of the paper's Table 2
+    (Fib_20, Fib_30, B_23, B_26) under AUTO, the oracle beside the two Fib
+    rows only (on B_m it would take minutes)."""
     import numpy as np
     import torch
     import oracle
@@ -227,7 +229,7 @@ def config_legs(ctx, reps=30):
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
 
-    def leg(d, closure, reps):
+    def leg(d, closure, reps, with_oracle=True):
         delta = torch.from_numpy(d.delta.view(np.int32)).to(dev)
         accept = torch.from_numpy(d.accept).to(dev)
         out = torch.empty(d.n, dtype=torch.int32, device=dev)
@@ -239,9 +241,11 @@ def config_legs(ctx, reps=30):
         t = time_device_steps(step, reps)
         t["value_p50"] = d.n * d.k / (t["ms_p50"] * 1e-3)
         t["result"] = result_summary(res)
-        t0 = time.perf_counter()
-        oracle.hopcroft(d.n, d.k, d.delta, d.accept)
-        t["cpu_oracle_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
+        del delta, accept, out
+        if with_oracle:
+            t0 = time.perf_counter()
+            oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+            t["cpu_oracle_ms"] = round(1e3 * (time.perf_counter() - t0), 3)
         return t
 
     print("[bench] configs: plain_single seeds 1..5, deep_chain", file=sys.stderr, flush=True)
@@ -249,7 +253,7 @@ def config_legs(ctx, reps=30):
     for seed in range(1, 6):
         single[str(seed)] = leg(W.random_dfa(16384, 2, seed), "auto", reps)
     chain = W.chain_dfa(1 << 20, 2)
-    return {
+    out = {
         "plain_single": {"workload": "random DFA, n=16384, |Sigma|=2, closure auto, seeds 1..5",
                          "transitions": 32768, "seeds": single,
                          "ms_p50_median_over_seeds": round(statistics.median(
@@ -260,6 +264,16 @@ def config_legs(ctx, reps=30):
                               transitions=2 << 20, **leg(chain, "on", max(20, reps // 2))),
         "cpu_oracle_note": "cpu_oracle_ms: Hopcroft (C, 1 thread) on the same input, once",
     }
+    print("[bench] configs: Table 2 rows", file=sys.stderr, flush=True)
+    for name, r, with_oracle in (("fib20", reps, True), ("fib30", 20, True), ("bitsplitter23", 5, False),
+                                 ("bitsplitter26", 3, False)):
+        spec = WORKLOADS[name]
+        d = make_input(spec, 0)
+        out[name] = dict(workload=spec["desc"] + ", closure auto", transitions=d.n * d.k, paper=spec["paper"],
+                         **leg(d, spec["closure"], r, with_oracle))
+        del d
+        torch.cuda.empty_cache()
+    return out
 
 
 def upload_batch(dfas, dev):
