@@ -253,7 +253,7 @@ class Engine {
   DevBuf d_qdbl_;   // per-instance doubling state of queued rounds
   HostBuf h_qdbl_;
   // fused kernels: jobs in class order, their results, and where each sits
-  DevBuf d_fjobs_, d_fres_;
+  DevBuf d_fjobs_;
   HostBuf h_fjobs_, h_fres_;
   std::vector<uint32_t> fused_pos_;  // per entry of `which`: index in the job array
   // A batch's fused kernels run on their own stream beside the round

@@ -140,7 +140,7 @@ Engine::~Engine() {
                     &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
+                    &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
   // device buffers of the fixed-region mode belong to the region
   if (!fixed()) {
     for (DevBuf* b : bufs)
@@ -160,7 +160,7 @@ uint64_t Engine::device_bytes() const {
                           &d_keep_, &d_rank_, &d_sig_, &d_table_, &d_status_, &d_changed_, &d_rb_,
                           &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                           &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
-                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_fres_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
+                          &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_fjobs_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
   uint64_t t = 0;
   for (const DevBuf* b : bufs) t += b->cap;
   for (const DevBuf& b : closure_bufs_) t += b.cap;
@@ -253,7 +253,7 @@ void Engine::reset_fixed_region() {
                     &d_results_, &d_wgflags_, &d_part_, &d_dense_,
                     &d_djobs_, &d_visit_, &d_bfs_rows_, &d_min_delta_, &d_min_acc_,
                     &d_lvl_, &d_lvl_wg_, &d_lvl_flags_, &d_qdbl_, &d_ctrl_, &d_refine_, &d_counts_,
-                    &d_fjobs_, &d_fres_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
+                    &d_fjobs_, &d_notify_, &d_lbl_, &d_gcount_, &d_dtab_};
   for (DevBuf* b : bufs) *b = DevBuf{};
   closure_bufs_.clear();
   fixed_off_ = 0;
@@ -1535,8 +1535,7 @@ uint32_t Engine::fused_limit(const dfamin_opts& opts) const {
 int Engine::fused_issue(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,
                         const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s) {
   const size_t F = which.size();
-  TRY(ensure(d_fjobs_, F * sizeof(FusedJob)));
-  TRY(ensure(d_fres_, F * sizeof(FusedRes)));
+  if (F > 1) TRY(ensure(d_fjobs_, F * sizeof(FusedJob)));
   TRY(ensure_host(h_fjobs_, F * sizeof(FusedJob)));
   TRY(ensure_host(h_fres_, F * sizeof(FusedRes)));
   // jobs grouped by size class, largest class first
@@ -1569,16 +1568,23 @@ int Engine::fused_issue(const std::vector<InstInput>& in, const std::vector<uint
     }
   }
   start[3] = at;
-  launch_copy_bytes(d_fjobs_.p, h_fjobs_.dp, F * sizeof(FusedJob), s);
+  // The kernels write their results straight into the mapped page-locked
+  // buffer the host reads after its wait; one job travels as a kernel
+  // argument, so a single small instance costs one launch and no copies.
+  FusedRes* res = static_cast<FusedRes*>(h_fres_.dp);
+  if (F > 1) launch_copy_bytes(d_fjobs_.p, h_fjobs_.dp, F * sizeof(FusedJob), s);
   Profiler& prof = ctx_->prof;
   prof.begin(s, "fused", bytes);
-  for (int cls = 2; cls >= 0; --cls) {
-    const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
-    launch_fused(d_fjobs_.as<FusedJob>() + b, d_fres_.as<FusedRes>() + b, e - b, cls, s);
+  if (F == 1) {
+    launch_fused(nullptr, res, 1, fused_class(hj[0].n), s, &hj[0]);
+  } else {
+    for (int cls = 2; cls >= 0; --cls) {
+      const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
+      launch_fused(d_fjobs_.as<FusedJob>() + b, res + b, e - b, cls, s);
+    }
   }
   prof.end(s);
-  HIP(hipGetLastError());
-  return readback(h_fres_, d_fres_.p, F * sizeof(FusedRes), s);
+  return check_hip(hipGetLastError());
 }
 
 int Engine::fused_collect(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,

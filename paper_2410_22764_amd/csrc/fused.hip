@@ -88,7 +88,7 @@ constexpr uint16_t kBlkMask = 0x3FFFu;
 
 template <int MAXN, int NT>
 __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs, FusedRes* __restrict__ res,
-                                              uint32_t njobs) {
+                                              uint32_t njobs, FusedJob one) {
   static_assert(MAXN % NT == 0 && MAXN <= (1 << 14) && (MAXN / NT) % kChunk == 0, "fused tile: ids fit 14 bits");
   static_assert(((3u * MAXN) / 2u - 64u) % kBucket == 0, "table of whole buckets");
   constexpr int ITEMS = MAXN / NT;
@@ -103,7 +103,7 @@ __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs,
                                    // 4/5 leaders (alternate rounds), 6 fault, 32.. wave totals
   const uint32_t j = blockIdx.x;
   if (j >= njobs) return;
-  const FusedJob J = jobs[j];
+  const FusedJob J = jobs ? jobs[j] : one;  // one job may come as an argument
   const uint32_t n = J.n, k = J.k, tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
   const uint32_t* __restrict__ delta = reinterpret_cast<const uint32_t*>(J.delta);
   const uint8_t* __restrict__ acc = reinterpret_cast<const uint8_t*>(J.accept);
@@ -502,12 +502,20 @@ __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs,
 
 }  // namespace
 
-void launch_fused(const FusedJob* jobs, FusedRes* res, uint32_t njobs, int cls, hipStream_t s) {
+void launch_fused(const FusedJob* jobs, FusedRes* res, uint32_t njobs, int cls, hipStream_t s,
+                  const FusedJob* one) {
   if (!njobs) return;
+  const FusedJob arg = one ? *one : FusedJob{};
+  if (one) {
+    jobs = nullptr;
+    njobs = 1;
+  }
   switch (cls) {
-    case 0: hipLaunchKernelGGL((k_fused<2048, 256>), dim3(njobs), dim3(256), 0, s, jobs, res, njobs); break;
-    case 1: hipLaunchKernelGGL((k_fused<8192, 512>), dim3(njobs), dim3(512), 0, s, jobs, res, njobs); break;
-    default: hipLaunchKernelGGL((k_fused<16384, 1024>), dim3(njobs), dim3(1024), 0, s, jobs, res, njobs); break;
+    case 0: hipLaunchKernelGGL((k_fused<2048, 256>), dim3(njobs), dim3(256), 0, s, jobs, res, njobs, arg); break;
+    case 1: hipLaunchKernelGGL((k_fused<8192, 512>), dim3(njobs), dim3(512), 0, s, jobs, res, njobs, arg); break;
+    default:
+      hipLaunchKernelGGL((k_fused<16384, 1024>), dim3(njobs), dim3(1024), 0, s, jobs, res, njobs, arg);
+      break;
   }
 }
 

@@ -198,7 +198,10 @@ constexpr uint32_t kFusedMaxLetters = 32;
 // size class of a fused instance: 0 up to 2,048 states (256 threads),
 // 1 up to 8,192 (512 threads), 2 up to 16,384 (1,024 threads, 160 KB of LDS)
 inline int fused_class(uint32_t n) { return n <= 2048 ? 0 : (n <= 8192 ? 1 : 2); }
-void launch_fused(const FusedJob* jobs, FusedRes* res, uint32_t njobs, int cls, hipStream_t s);
+// one (nullable): a single job passed by value (jobs is then ignored and
+// njobs taken as 1).  res may be mapped page-locked host memory.
+void launch_fused(const FusedJob* jobs, FusedRes* res, uint32_t njobs, int cls, hipStream_t s,
+                  const FusedJob* one = nullptr);
 
 // Row-check flag bits.
 constexpr uint32_t kFlagBad = 1u;      // entry >= n
