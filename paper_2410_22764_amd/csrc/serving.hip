@@ -340,8 +340,9 @@ struct Serving::Impl {
   size_t rows_cap = 0;
   uint64_t table_cap = 0;
   // scratch that grows
-  DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux, s_fjobs, s_fres;
+  DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux, s_fjobs;
   HostBuf h_flags, h_ctrl, h_results, h_fres;  // h_ctrl: a Ctrl, then the per-slot flags of d_last
+  std::vector<char> job_stage;                 // host side of upload_jobs
   uint32_t* h_last() { return reinterpret_cast<uint32_t*>(static_cast<char*>(h_ctrl.p) + sizeof(Ctrl)); }
 
   void shutdown() {
@@ -382,17 +383,41 @@ struct Serving::Impl {
     b.cap = b.p ? want : 0;
     return b.p != nullptr;
   }
+  // Page-locked, coherent and mapped: kernels may write results straight
+  // into it (b.dp), with no device cache holding them back.
   bool grow_host(HostBuf& b, size_t bytes) {
     if (b.cap >= bytes) return true;
     if (b.p) (void)hipHostFree(b.p);
+    b.p = b.dp = nullptr;
+    b.cap = 0;
     size_t want = bytes + bytes / 4 + 64;
-    if (hipHostMalloc(&b.p, want, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc(&b.p, want, hipHostMallocCoherent) != hipSuccess) {
       b.p = nullptr;
-      b.cap = 0;
+      (void)hipGetLastError();
+      return false;
+    }
+    if (hipHostGetDevicePointer(&b.dp, b.p, 0) != hipSuccess || !b.dp) {
+      (void)hipHostFree(b.p);
+      b.p = b.dp = nullptr;
+      (void)hipGetLastError();
       return false;
     }
     b.cap = want;
     return true;
+  }
+
+  // A job list and its workgroup offsets in one upload into s_jobs; the
+  // offsets follow the jobs (returned in *off).
+  int upload_jobs(const std::vector<RowJob>& jobs, const std::vector<uint32_t>& joboff, uint32_t** off) {
+    const size_t jb = jobs.size() * sizeof(RowJob), ob = joboff.size() * 4;
+    if (!grow(s_jobs, jb + ob)) return DFAMIN_E_NOMEM;
+    job_stage.resize(jb + ob);
+    std::memcpy(job_stage.data(), jobs.data(), jb);
+    std::memcpy(job_stage.data() + jb, joboff.data(), ob);
+    if (hipMemcpyAsync(s_jobs.p, job_stage.data(), jb + ob, hipMemcpyHostToDevice, stream) != hipSuccess)
+      return DFAMIN_E_DEVICE;
+    *off = reinterpret_cast<uint32_t*>(static_cast<char*>(s_jobs.p) + jb);
+    return DFAMIN_OK;
   }
   void free_device() {
     if (ustream) (void)hipStreamSynchronize(ustream);  // uploads still reading host staging
@@ -406,7 +431,7 @@ struct Serving::Impl {
     for (void** p : ps)
       if (*p) { (void)hipFree(*p); *p = nullptr; }
     d_last = nullptr;  // part of d_ctrl's allocation
-    DevBuf* db[] = {&s_jobs, &s_off, &s_flags, &s_wg, &s_part, &s_slot, &s_aux, &s_fjobs, &s_fres};
+    DevBuf* db[] = {&s_jobs, &s_off, &s_flags, &s_wg, &s_part, &s_slot, &s_aux, &s_fjobs};
     for (DevBuf* b : db)
       if (b->p) { (void)hipFree(b->p); b->p = nullptr; b->cap = 0; }
     HostBuf* hb[] = {&h_flags, &h_ctrl, &h_results, &h_fres};
@@ -534,16 +559,13 @@ struct Serving::Impl {
     }
     begin[S] = (uint32_t)jobs.size();
     todo.clear();
-    if (!grow(s_jobs, jobs.size() * sizeof(RowJob)) || !grow(s_off, joboff.size() * 4) ||
-        !grow(s_flags, jobs.size() * 4) || !grow(s_wg, (size_t)maxw * 4))
-      return DFAMIN_E_NOMEM;
-    if (hipMemcpyAsync(s_jobs.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(s_off.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
-      return DFAMIN_E_DEVICE;
+    if (!grow(s_flags, jobs.size() * 4) || !grow(s_wg, (size_t)maxw * 4)) return DFAMIN_E_NOMEM;
+    uint32_t* d_off = nullptr;
+    const int urc = upload_jobs(jobs, joboff, &d_off);
+    if (urc != DFAMIN_OK) return urc;
     for (uint32_t st = 0; st < S; ++st)
       if (begin[st + 1] > begin[st])
-        launch_closure_level(s_jobs.as<RowJob>() + begin[st], s_off.as<uint32_t>() + begin[st],
+        launch_closure_level(s_jobs.as<RowJob>() + begin[st], d_off + begin[st],
                              begin[st + 1] - begin[st], wgs[st], s_wg.as<uint32_t>(),
                              s_flags.as<uint32_t>() + begin[st], stream);
     return hipGetLastError() == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
@@ -746,8 +768,7 @@ struct Serving::Impl {
       }
     }
     start[3] = at;
-    if (!grow(s_fjobs, F * sizeof(FusedJob)) || !grow(s_fres, F * sizeof(FusedRes)) ||
-        !grow_host(h_fres, F * sizeof(FusedRes)))
+    if ((F > 1 && !grow(s_fjobs, F * sizeof(FusedJob))) || !grow_host(h_fres, F * sizeof(FusedRes)))
       return DFAMIN_E_NOMEM;
     for (Resident* r : fs) {
       if (r->uploaded) continue;
@@ -758,11 +779,19 @@ struct Serving::Impl {
         return DFAMIN_E_DEVICE;
       r->uploaded = true;
     }
-    if (hipMemcpyAsync(s_fjobs.p, jobs.data(), F * sizeof(FusedJob), hipMemcpyHostToDevice, stream) != hipSuccess)
-      return DFAMIN_E_DEVICE;
-    for (int cls = 2; cls >= 0; --cls) {
-      const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
-      launch_fused(s_fjobs.as<FusedJob>() + b, s_fres.as<FusedRes>() + b, e - b, cls, stream);
+    // results go straight to the mapped host buffer; one job travels as a
+    // kernel argument
+    FusedRes* res = static_cast<FusedRes*>(h_fres.dp);
+    if (F == 1) {
+      launch_fused(nullptr, res, 1, fused_class(jobs[0].n), stream, &jobs[0]);
+    } else {
+      if (hipMemcpyAsync(s_fjobs.p, jobs.data(), F * sizeof(FusedJob), hipMemcpyHostToDevice, stream) !=
+          hipSuccess)
+        return DFAMIN_E_DEVICE;
+      for (int cls = 2; cls >= 0; --cls) {
+        const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
+        launch_fused(s_fjobs.as<FusedJob>() + b, res + b, e - b, cls, stream);
+      }
     }
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     // every output comes back with the results (a bad or handed-back one is
@@ -773,9 +802,7 @@ struct Serving::Impl {
           hipSuccess)
         return DFAMIN_E_DEVICE;
     }
-    if (hipMemcpyAsync(h_fres.p, s_fres.p, F * sizeof(FusedRes), hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        stream_wait(stream) != hipSuccess)
-      return DFAMIN_E_DEVICE;
+    if (stream_wait(stream) != hipSuccess) return DFAMIN_E_DEVICE;
     const FusedRes* fr = h_fres.as<FusedRes>();
     for (size_t w = 0; w < F; ++w) {
       Resident* r = fs[w];
@@ -833,20 +860,14 @@ struct Serving::Impl {
         wgs += (J.n + kLongTile - 1) / kLongTile;
         jobs.push_back(J);
       }
-    if (!grow(s_jobs, jobs.size() * sizeof(RowJob)) || !grow(s_off, joboff.size() * 4) ||
-        !grow(s_flags, jobs.size() * 4) || !grow(s_wg, (size_t)wgs * 4) ||
-        !grow_host(h_flags, jobs.size() * 4))
-      return DFAMIN_E_NOMEM;
-    if (hipMemcpyAsync(s_jobs.p, jobs.data(), jobs.size() * sizeof(RowJob), hipMemcpyHostToDevice, stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(s_off.p, joboff.data(), joboff.size() * 4, hipMemcpyHostToDevice, stream) != hipSuccess)
-      return DFAMIN_E_DEVICE;
-    launch_row_check(s_jobs.as<RowJob>(), s_off.as<uint32_t>(), (uint32_t)jobs.size(), wgs,
-                     s_wg.as<uint32_t>(), s_flags.as<uint32_t>(), stream);
-    if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
-    if (hipMemcpyAsync(h_flags.p, s_flags.p, jobs.size() * 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        stream_wait(stream) != hipSuccess)
-      return DFAMIN_E_DEVICE;
+    if (!grow(s_wg, (size_t)wgs * 4) || !grow_host(h_flags, jobs.size() * 4)) return DFAMIN_E_NOMEM;
+    uint32_t* d_off = nullptr;
+    const int urc = upload_jobs(jobs, joboff, &d_off);
+    if (urc != DFAMIN_OK) return urc;
+    // the per-row flags go straight to the mapped host buffer
+    launch_row_check(s_jobs.as<RowJob>(), d_off, (uint32_t)jobs.size(), wgs, s_wg.as<uint32_t>(),
+                     static_cast<uint32_t*>(h_flags.dp), stream);
+    if (hipGetLastError() != hipSuccess || stream_wait(stream) != hipSuccess) return DFAMIN_E_DEVICE;
     for (Resident* r : js) r->req->in.release();  // the inputs are on the device now
     const uint32_t* f = h_flags.as<uint32_t>();
     std::vector<Resident*> ok, need_closure;
