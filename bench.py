@@ -475,6 +475,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain and end-to-end legs")
     ap.add_argument("--requests", type=int, default=2000, help="serving: measured requests")
     ap.add_argument("--pool", type=int, default=256, help="serving: distinct pre-generated requests")
+    ap.add_argument("--submitters", type=int, default=16,
+                    help="serving: submitting threads of the closed-loop saturation pass")
     ap.add_argument("--load", type=float, default=0.7, help="serving: offered load / saturation")
     ap.add_argument("--serving-requests", type=int, default=2000,
                     help="requests of the serving leg in the default run (0: none)")
@@ -507,7 +509,7 @@ def main():
 
     if args.workload == "serving":
         ctx = dfamin.dfamin_create(0)
-        res = serving_run(ctx, args.seed, args.requests, args.pool, args.load)
+        res = serving_run(ctx, args.seed, args.requests, args.pool, args.load, submitters=args.submitters)
         ctx.close()
         line = {"metric": METRIC, "value": res["transitions_per_s"], "unit": "transitions/s", "n_gpus": 1,
                 "steps": args.requests, "warmup": 0, "ms_per_step": None, "higher_is_better": True,
@@ -645,7 +647,8 @@ def main():
     serving = None
     if args.serving_requests and args.workload == "plain_large":
         sctx = dfamin.dfamin_create(0)
-        serving = serving_run(sctx, args.seed, args.serving_requests, args.serving_pool, args.load)
+        serving = serving_run(sctx, args.seed, args.serving_requests, args.serving_pool, args.load,
+                              submitters=args.submitters)
         serving["workload"] = ("serving: Poisson stream, n log-uniform in [2^8, 2^22], |Sigma| in 2..16, "
                                "20% permuted chains, closure auto")
         sctx.close()

@@ -343,6 +343,7 @@ struct Serving::Impl {
   DevBuf s_jobs, s_off, s_flags, s_wg, s_part, s_slot, s_aux, s_fjobs;
   HostBuf h_flags, h_ctrl, h_results, h_fres;  // h_ctrl: a Ctrl, then the per-slot flags of d_last
   std::vector<char> job_stage;                 // host side of upload_jobs
+  std::vector<uint32_t> join_list;             // host side of a join's job list
   uint32_t* h_last() { return reinterpret_cast<uint32_t*>(static_cast<char*>(h_ctrl.p) + sizeof(Ctrl)); }
 
   void shutdown() {
@@ -917,7 +918,8 @@ struct Serving::Impl {
     if (rc != DFAMIN_OK) return rc;
     // reset per-slot counters and build the initial partition
     const size_t nj = js.size();
-    std::vector<uint32_t> jl(3 * nj);  // slot ids, workgroup offsets, act offsets
+    std::vector<uint32_t>& jl = join_list;  // slot ids, workgroup offsets, act offsets
+    jl.resize(3 * nj);
     uint32_t iw = 0, am = m;
     for (size_t j = 0; j < nj; ++j) {
       jl[j] = js[j]->slot;
@@ -939,8 +941,8 @@ struct Serving::Impl {
                      static_cast<uint32_t*>(d_act), static_cast<uint32_t*>(d_changed),
                      static_cast<uint32_t*>(d_refine), static_cast<uint32_t*>(d_dead), stream);
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
-    // host vectors must outlive the asynchronous copies
-    if (stream_wait(stream) != hipSuccess) return DFAMIN_E_DEVICE;
+    // no wait: the copies' host sources are members that live until the
+    // next join, and everything after this runs behind it on the stream
     m = am;
     return DFAMIN_OK;
   }
