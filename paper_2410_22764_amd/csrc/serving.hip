@@ -344,6 +344,15 @@ struct Serving::Impl {
   HostBuf h_flags, h_ctrl, h_results, h_fres;  // h_ctrl: a Ctrl, then the per-slot flags of d_last
   std::vector<char> job_stage;                 // host side of upload_jobs
   std::vector<uint32_t> join_list;             // host side of a join's job list
+  struct FusedBatch {
+    std::vector<Resident*> fs;
+    std::vector<uint32_t> pos;   // per entry of fs: index in jobs (class order)
+    std::vector<FusedJob> jobs;  // host side of the job list
+    bool live = false;           // in flight on fstream
+  } fb;
+  std::vector<Resident*> fpend;  // small requests waiting for the next batch
+  hipStream_t fstream = nullptr;
+  hipEvent_t fev = nullptr;
   uint32_t* h_last() { return reinterpret_cast<uint32_t*>(static_cast<char*>(h_ctrl.p) + sizeof(Ctrl)); }
 
   void shutdown() {
@@ -422,7 +431,11 @@ struct Serving::Impl {
   }
   void free_device() {
     if (ustream) (void)hipStreamSynchronize(ustream);  // uploads still reading host staging
+    if (fstream) (void)hipStreamSynchronize(fstream);  // a fused batch still running
     staged.clear();
+    fpend.clear();
+    fb.fs.clear();
+    fb.live = false;
     for (Resident* r : slots)
       if (r) release_resident(r);
     slots.clear();
@@ -443,12 +456,16 @@ struct Serving::Impl {
     free_events.clear();
     if (stream) { (void)hipStreamDestroy(stream); stream = nullptr; }
     if (ustream) { (void)hipStreamDestroy(ustream); ustream = nullptr; }
+    if (fstream) { (void)hipStreamDestroy(fstream); fstream = nullptr; }
+    if (fev) { (void)hipEventDestroy(fev); fev = nullptr; }
   }
 
   int init_device() {
     if (hipSetDevice(ctx->device) != hipSuccess) return DFAMIN_E_DEVICE;
     if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) return DFAMIN_E_DEVICE;
     if (hipStreamCreateWithFlags(&ustream, hipStreamNonBlocking) != hipSuccess) return DFAMIN_E_DEVICE;
+    if (hipStreamCreateWithFlags(&fstream, hipStreamNonBlocking) != hipSuccess) return DFAMIN_E_DEVICE;
+    if (hipEventCreateWithFlags(&fev, hipEventDisableTiming) != hipSuccess) return DFAMIN_E_DEVICE;
     // arena sized from the budget: ~37 bytes per state of fixed buffers,
     // 16 per state of hash table, the rest for request buffers
     cap = kDefaultArenaStates;
@@ -740,19 +757,27 @@ struct Serving::Impl {
            (q.opts.closure == DFAMIN_CLOSURE_AUTO || q.opts.closure == DFAMIN_CLOSURE_OFF) &&
            q.opts.method == DFAMIN_METHOD_SIGNATURE;
   }
-  int join_fused(std::vector<Resident*>& fs, std::vector<Resident*>& handed_back) {
-    const size_t F = fs.size();
-    std::vector<FusedJob> jobs(F);
-    std::vector<uint32_t> pos(F);
+  // Small requests run as batches of the fused kernel on a stream of their
+  // own (fstream), one batch at a time, beside the resident set's rounds:
+  // fpend collects them, launch_fused_batch issues a batch (kernels, their
+  // outputs' copies back, an event), collect_fused publishes it once the
+  // event has completed.  The batch's results land in h_fres (mapped host
+  // memory) and its job list in s_fjobs, both held by the batch in flight.
+  int launch_fused_batch() {
+    fb.fs.swap(fpend);
+    fpend.clear();
+    const size_t F = fb.fs.size();
+    std::vector<FusedJob>& jobs = fb.jobs;
+    jobs.assign(F, FusedJob{});
+    fb.pos.assign(F, 0);
     uint32_t at = 0, start[4] = {0, 0, 0, 0};
     for (int cls = 2; cls >= 0; --cls) {
       start[cls] = at;
       for (size_t w = 0; w < F; ++w) {
-        Resident* r = fs[w];
+        Resident* r = fb.fs[w];
         const Request& q = *r->req;
         if (fused_class(q.n) != cls) continue;
         FusedJob& J = jobs[at];
-        J = FusedJob{};
         J.delta = reinterpret_cast<uint64_t>(r->d_delta);
         J.accept = reinterpret_cast<uint64_t>(r->d_accept);
         J.out = reinterpret_cast<uint64_t>(r->d_out);
@@ -765,49 +790,55 @@ struct Serving::Impl {
         J.levels = L;
         J.auto_rounds = q.opts.auto_rounds ? q.opts.auto_rounds : kDefaultAutoRounds;
         J.max_rounds = q.opts.max_rounds ? q.opts.max_rounds : q.n + 1u;
-        pos[w] = at++;
+        fb.pos[w] = at++;
       }
     }
     start[3] = at;
     if ((F > 1 && !grow(s_fjobs, F * sizeof(FusedJob))) || !grow_host(h_fres, F * sizeof(FusedRes)))
       return DFAMIN_E_NOMEM;
-    for (Resident* r : fs) {
+    for (Resident* r : fb.fs) {
       if (r->uploaded) continue;
-      if (hipMemcpyAsync(r->d_delta, r->req->delta(), r->sz_delta, hipMemcpyHostToDevice, stream) !=
+      if (hipMemcpyAsync(r->d_delta, r->req->delta(), r->sz_delta, hipMemcpyHostToDevice, fstream) !=
               hipSuccess ||
           hipMemcpyAsync(r->d_accept, r->req->accept(), r->req->accept_bytes(), hipMemcpyHostToDevice,
-                         stream) != hipSuccess)
+                         fstream) != hipSuccess)
         return DFAMIN_E_DEVICE;
       r->uploaded = true;
     }
-    // results go straight to the mapped host buffer; one job travels as a
-    // kernel argument
+    // one job travels as a kernel argument
     FusedRes* res = static_cast<FusedRes*>(h_fres.dp);
     if (F == 1) {
-      launch_fused(nullptr, res, 1, fused_class(jobs[0].n), stream, &jobs[0]);
+      launch_fused(nullptr, res, 1, fused_class(jobs[0].n), fstream, &jobs[0]);
     } else {
-      if (hipMemcpyAsync(s_fjobs.p, jobs.data(), F * sizeof(FusedJob), hipMemcpyHostToDevice, stream) !=
+      if (hipMemcpyAsync(s_fjobs.p, jobs.data(), F * sizeof(FusedJob), hipMemcpyHostToDevice, fstream) !=
           hipSuccess)
         return DFAMIN_E_DEVICE;
       for (int cls = 2; cls >= 0; --cls) {
         const uint32_t b = start[cls], e = cls == 0 ? start[3] : start[cls - 1];
-        launch_fused(s_fjobs.as<FusedJob>() + b, res + b, e - b, cls, stream);
+        launch_fused(s_fjobs.as<FusedJob>() + b, res + b, e - b, cls, fstream);
       }
     }
     if (hipGetLastError() != hipSuccess) return DFAMIN_E_DEVICE;
     // every output comes back with the results (a bad or handed-back one is
     // simply not published)
-    for (Resident* r : fs) {
+    for (Resident* r : fb.fs) {
       if (!r->req->out.make(pinned, 4ull * r->req->n)) return DFAMIN_E_NOMEM;
-      if (hipMemcpyAsync(r->req->out.data(), r->d_out, 4ull * r->req->n, hipMemcpyDeviceToHost, stream) !=
+      if (hipMemcpyAsync(r->req->out.data(), r->d_out, 4ull * r->req->n, hipMemcpyDeviceToHost, fstream) !=
           hipSuccess)
         return DFAMIN_E_DEVICE;
     }
-    if (stream_wait(stream) != hipSuccess) return DFAMIN_E_DEVICE;
+    if (hipEventRecord(fev, fstream) != hipSuccess) return DFAMIN_E_DEVICE;
+    fb.live = true;
+    return DFAMIN_OK;
+  }
+
+  // Publish the batch in flight (its event has completed); requests the
+  // kernel handed back go to handed_back, to join the resident set.
+  int collect_fused(std::vector<Resident*>& handed_back) {
     const FusedRes* fr = h_fres.as<FusedRes>();
-    for (size_t w = 0; w < F; ++w) {
-      Resident* r = fs[w];
-      const FusedRes& f = fr[pos[w]];
+    for (size_t w = 0; w < fb.fs.size(); ++w) {
+      Resident* r = fb.fs[w];
+      const FusedRes& f = fr[fb.pos[w]];
       if (f.status == kFusedHandOff) {
         handed_back.push_back(r);
         continue;
@@ -832,6 +863,8 @@ struct Serving::Impl {
       release_resident(r);
       finish(req, cancelled && st == DFAMIN_OK ? DFAMIN_E_CANCELLED : st);
     }
+    fb.fs.clear();
+    fb.live = false;
     return DFAMIN_OK;
   }
 
@@ -1131,7 +1164,11 @@ struct Serving::Impl {
 
   void fail_all(int rc) {
     if (ustream) (void)hipStreamSynchronize(ustream);  // uploads still reading host staging
+    if (fstream) (void)hipStreamSynchronize(fstream);  // a fused batch still running
     staged.clear();
+    fpend.clear();
+    fb.fs.clear();
+    fb.live = false;
     std::vector<std::shared_ptr<Request>> rs;
     {
       std::lock_guard<std::mutex> g(mu);
@@ -1237,11 +1274,18 @@ struct Serving::Impl {
       }
       const auto t0 = std::chrono::steady_clock::now();
       if (!joining.empty()) {
-        std::vector<Resident*> fs, rest;
-        for (Resident* r : joining) (fusable(*r->req) ? fs : rest).push_back(r);
-        if (!fs.empty()) rc = join_fused(fs, rest);
+        std::vector<Resident*> rest;
+        for (Resident* r : joining) (fusable(*r->req) ? fpend : rest).push_back(r);
         joining.swap(rest);
       }
+      if (rc == DFAMIN_OK && fb.live) {
+        // with nothing else to run, wait for the batch in flight
+        const bool idle = !any_joined() && joining.empty() && staged.empty();
+        const hipError_t e = idle ? hipEventSynchronize(fev) : hipEventQuery(fev);
+        if (e == hipSuccess) rc = collect_fused(joining);
+        else if (e != hipErrorNotReady) rc = DFAMIN_E_DEVICE;
+      }
+      if (rc == DFAMIN_OK && !fb.live && !fpend.empty()) rc = launch_fused_batch();
       if (rc == DFAMIN_OK && !joining.empty()) rc = join(joining);
       const auto t1 = std::chrono::steady_clock::now();
       if (rc == DFAMIN_OK && any_joined()) rc = round();
