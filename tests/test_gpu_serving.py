@@ -234,3 +234,51 @@ def test_small_budget_deep_auto_requests():
             assert res["num_blocks"] == nb and np.array_equal(out, want) and res["initial_block"] == want[d.q0]
     finally:
         c.close()
+
+
+def test_small_request_batches_beside_rounds(ctx):
+    """Small requests run as fused batches on their own stream while the
+    resident set refines: a burst of them around a long request, every
+    fourth cancelled right after its submit, one invalid and one that the
+    fused kernel hands back (two non-identity letters, still splitting after
+    the AUTO rounds), which then joins the resident set and takes closure
+    letters.  Each result is the oracle's, a cancelled request reports
+    success or cancellation, the invalid one E_BAD_DFA."""
+    from paper_2410_22764_amd import dfamin
+    print("[case] serving: small-request batches beside a long request", flush=True)
+    long = W.chain_dfa(3000, 1)
+    tl = dfamin.dfamin_submit(ctx, long, {"closure": "off"})  # one round per state
+    small = [W.random_dfa(200 + 300 * i, 2 + i % 5, 100 + i) for i in range(48)]
+    n = 3000
+    ids = np.arange(n)
+    rows = np.stack([np.minimum(ids + 1, n - 1), np.minimum(ids + 2, n - 1)])
+    acc = np.zeros(n, bool)
+    acc[-1] = True
+    deep = W.from_rows(rows, acc, 0, "two-letter chain")
+    bad = W.random_dfa(500, 2, 7)
+    bad.delta = bad.delta.copy()
+    bad.delta[10] = 500
+    tickets, cancelled = [], set()
+    for i, d in enumerate(small):
+        t = dfamin.dfamin_submit(ctx, d, {"closure": "auto"})
+        tickets.append(t)
+        if i % 4 == 1:
+            assert dfamin.dfamin_cancel(ctx, t) == dfamin.DFAMIN_OK
+            cancelled.add(i)
+    td = dfamin.dfamin_submit(ctx, deep, {"closure": "auto"})
+    tb = dfamin.dfamin_submit(ctx, bad, {"closure": "auto"})
+    for i, (d, t) in enumerate(zip(small, tickets)):
+        rc, out, res = dfamin.dfamin_wait(ctx, t, d.n, timeout_us=30_000_000)
+        if i in cancelled and rc == dfamin.DFAMIN_E_CANCELLED:
+            continue
+        assert rc == dfamin.DFAMIN_OK, (i, rc)
+        want, nb = oracle.hopcroft(d.n, d.k, d.delta, d.accept)
+        assert res["num_blocks"] == nb and np.array_equal(out, want), i
+    rc, out, res = dfamin.dfamin_wait(ctx, td, deep.n, timeout_us=30_000_000)
+    want, nb = oracle.hopcroft(deep.n, deep.k, deep.delta, deep.accept)
+    assert rc == dfamin.DFAMIN_OK and res["num_blocks"] == nb and np.array_equal(out, want)
+    assert res["closure_levels"] > 0  # handed back by the fused kernel, closure built by the loop
+    rc, _, _ = dfamin.dfamin_wait(ctx, tb, bad.n, timeout_us=30_000_000)
+    assert rc == dfamin.DFAMIN_E_BAD_DFA
+    rc, out, res = dfamin.dfamin_wait(ctx, tl, long.n, timeout_us=60_000_000)
+    assert rc == dfamin.DFAMIN_OK and np.array_equal(out, np.arange(long.n))
