@@ -122,8 +122,8 @@ class Engine {
   int validate(hipStream_t s, std::vector<InstOutcome>& res);
   // Largest instance the fused kernels take under these options (0: none).
   uint32_t fused_limit(const dfamin_opts& opts) const;
-  // Queues the fused kernels for the instances `which` of `in` and the copy
-  // of their results to h_fres_ (read after the stream has drained).
+  // Queues the fused kernels for the instances `which` of `in`; they write
+  // their results into h_fres_ (mapped, read after the stream has drained).
   int fused_issue(const std::vector<InstInput>& in, const std::vector<uint32_t>& which,
                   const dfamin_opts& opts, uint64_t max_rounds, hipStream_t s);
   // Results of fused_issue's instances: res entries of the finished ones,
