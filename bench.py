@@ -124,6 +124,39 @@ def copy_peak_gbps(reps=5, mib=1024):
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
+def random_access_rates(reps=5):
+    """Random accesses per second on this GPU, from torch's own kernels:
+    4-byte gathers at 2^26 random indices of a 64 MiB table, and 8-byte
+    atomic adds at 2^24 random indices of a 256 MiB table.  These are the
+    two accesses a signature launch makes per state at random (the
+    successors' block ids; one table update per group)."""
+    import torch
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    n = 1 << 24
+    src = torch.arange(n, dtype=torch.int32, device=dev)
+    idx = torch.randint(0, n, (4 * n,), device=dev, generator=g)
+    out = torch.index_select(src, 0, idx)
+    table = torch.zeros(1 << 25, dtype=torch.int64, device=dev)
+    aidx = torch.randint(0, 1 << 25, (n,), device=dev, generator=g)
+    ones = torch.ones(n, dtype=torch.int64, device=dev)
+    table.index_add_(0, aidx, ones)
+    rates = []
+    for work, count in ((lambda: torch.index_select(src, 0, idx, out=out), 4 * n),
+                        (lambda: table.index_add_(0, aidx, ones), n)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            work()
+        b.record()
+        b.synchronize()
+        rates.append(count * reps / (a.elapsed_time(b) * 1e-3))
+    del src, idx, out, table, aidx, ones
+    torch.cuda.empty_cache()
+    return rates[0], rates[1]
+
+
 def host_info():
     """The host the CPU baselines ran on."""
     model = None
@@ -621,6 +654,22 @@ def main():
                                         "bytes between L2 and the memory fabric, memory-side cache hits included")
         if not args.no_batch:
             roofline["copy_GBps"] = round(copy_peak_gbps(), 1)
+        if not args.no_batch and args.workload == "plain_large" and top["name"] == "signature":
+            # each of C1's two signature launches runs over all n states,
+            # gathering k block ids at random and updating one table word per
+            # group (nearly every group is a single state)
+            gps, aps = random_access_rates()
+            n, k = spec["n"], spec["k"]
+            tg, ta = k * n / gps, n / aps
+            roofline["random_access"] = {
+                "gathers_per_s": round(gps), "atomics_per_s": round(aps),
+                "per_launch": {"gathers": k * n, "atomics": n},
+                "floor_ms": {"overlapped": round(1e3 * max(tg, ta), 3), "serial": round(1e3 * (tg + ta), 3)},
+                "avg_launch_ms": round(per_launch_ms, 3),
+                "frac_of_floor": round(1e3 * max(tg, ta) / per_launch_ms, 3),
+                "note": "rates from torch's index_select (4-byte gathers, 64 MiB table) and index_add_ "
+                        "(8-byte atomics, 256 MiB table) on this GPU; floor = the launch's random "
+                        "accesses at those rates"}
     batched = None
     configs = None
     if not args.no_batch and args.workload == "plain_large":
