@@ -479,7 +479,7 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   RowJob* hj = reinterpret_cast<RowJob*>(lvl_host_.data());
   uint32_t* ho = reinterpret_cast<uint32_t*>(hj + J);
   std::vector<uint32_t> begin(S + 1, 0), wgs(S, 0);
-  uint32_t c = 0, maxw = 0;
+  uint32_t c = 0;
   double alg = 0;
   for (uint32_t st = 0; st < S; ++st) {
     begin[st] = c;
@@ -499,11 +499,8 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
       ++c;
     }
     wgs[st] = w;
-    maxw = std::max(maxw, w);
   }
   begin[S] = c;
-  TRY(ensure(d_lvl_wg_, (size_t)maxw * 4));
-  TRY(ensure(d_lvl_flags_, J * 4));
   TRY(upload(d_lvl_.p, lvl_host_.data(), bytes, s));
   RowJob* dj = d_lvl_.as<RowJob>();
   uint32_t* dof = reinterpret_cast<uint32_t*>(dj + J);
@@ -511,8 +508,10 @@ int Engine::queue_levels(const std::vector<LevelTodo>& todo, hipStream_t s) {
   prof.begin(s, "closure", alg);
   for (uint32_t st = 0; st < S; ++st)
     if (begin[st + 1] > begin[st])
-      launch_closure_level(dj + begin[st], dof + begin[st], begin[st + 1] - begin[st], wgs[st],
-                           d_lvl_wg_.as<uint32_t>(), d_lvl_flags_.as<uint32_t>() + begin[st], s);
+      // (a level read by a doubling round is not tested for being equal to
+      // its predecessor or the identity: no flags)
+      launch_closure_level(dj + begin[st], dof + begin[st], begin[st + 1] - begin[st], wgs[st], nullptr,
+                           nullptr, s);
   prof.end(s);
   HIP(hipGetLastError());
   return DFAMIN_OK;

@@ -215,6 +215,7 @@ constexpr uint32_t kFlagDiffers = 4u;  // closure level differs from the previou
 // into one word per job (flags); no contended atomics.
 void launch_row_check(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
                       uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s);
+// (flags null: no flags are computed, and wg_flags is not used)
 void launch_closure_level(const RowJob* jobs, const uint32_t* job_wg_off, uint32_t njobs,
                           uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s);
 // Least accepting / non-accepting state per instance: per-workgroup partial

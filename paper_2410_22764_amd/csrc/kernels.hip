@@ -301,8 +301,10 @@ __global__ __launch_bounds__(kBlock) void k_closure_level(const RowJob* __restri
       if (s2 != q) bits |= kFlagNonId;
     }
   }
-  const uint32_t w = block_or(bits, &s_or);
-  if (threadIdx.x == 0) wg_flags[wg] = w;
+  if (wg_flags) {  // the same for the whole grid
+    const uint32_t w = block_or(bits, &s_or);
+    if (threadIdx.x == 0) wg_flags[wg] = w;
+  }
 }
 
 // flags[j] = OR of the workgroup flags of job j (one workgroup per job).
@@ -1657,9 +1659,10 @@ void launch_closure_level(const RowJob* jobs, const uint32_t* job_wg_off, uint32
                           uint32_t total_wgs, uint32_t* wg_flags, uint32_t* flags, hipStream_t s) {
   if (!total_wgs) return;
   hipLaunchKernelGGL(k_closure_level, dim3(total_wgs), dim3(kBlock), 0, s, jobs, job_wg_off, njobs,
-                     wg_flags);
-  hipLaunchKernelGGL(k_flags_reduce, dim3(njobs), dim3(kBlock), 0, s, job_wg_off, njobs, total_wgs,
-                     wg_flags, flags);
+                     flags ? wg_flags : nullptr);
+  if (flags)
+    hipLaunchKernelGGL(k_flags_reduce, dim3(njobs), dim3(kBlock), 0, s, job_wg_off, njobs, total_wgs,
+                       wg_flags, flags);
 }
 
 void launch_init_minmax(const InstDesc* desc, const uint32_t* job_wg_off, uint32_t ninst,

@@ -557,7 +557,6 @@ struct Serving::Impl {
     for (const LevelTodo& t : todo) S = std::max(S, t.step + 1);
     std::vector<RowJob> jobs;
     std::vector<uint32_t> joboff, begin(S + 1, 0), wgs(S, 0);
-    uint32_t maxw = 0;
     for (uint32_t st = 0; st < S; ++st) {
       begin[st] = (uint32_t)jobs.size();
       uint32_t w = 0;
@@ -573,19 +572,16 @@ struct Serving::Impl {
         jobs.push_back(J);
       }
       wgs[st] = w;
-      maxw = std::max(maxw, w);
-    }
+      }
     begin[S] = (uint32_t)jobs.size();
     todo.clear();
-    if (!grow(s_flags, jobs.size() * 4) || !grow(s_wg, (size_t)maxw * 4)) return DFAMIN_E_NOMEM;
     uint32_t* d_off = nullptr;
     const int urc = upload_jobs(jobs, joboff, &d_off);
     if (urc != DFAMIN_OK) return urc;
     for (uint32_t st = 0; st < S; ++st)
-      if (begin[st + 1] > begin[st])
+      if (begin[st + 1] > begin[st])  // (levels read as built are not tested: no flags)
         launch_closure_level(s_jobs.as<RowJob>() + begin[st], d_off + begin[st],
-                             begin[st + 1] - begin[st], wgs[st], s_wg.as<uint32_t>(),
-                             s_flags.as<uint32_t>() + begin[st], stream);
+                             begin[st + 1] - begin[st], wgs[st], nullptr, nullptr, stream);
     return hipGetLastError() == hipSuccess ? DFAMIN_OK : DFAMIN_E_DEVICE;
   }
 
