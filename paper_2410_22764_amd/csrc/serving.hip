@@ -362,6 +362,9 @@ struct Serving::Impl {
     }
     cv_work.notify_all();
     if (worker.joinable()) worker.join();
+    // a fused batch may still be copying outputs into requests' buffers:
+    // let it finish before their waiters wake
+    if (fstream) (void)hipStreamSynchronize(fstream);
     if (std::getenv("DFAMIN_TRACE"))
       std::fprintf(stderr, "[dfamin] serving: %llu iterations, %llu joined; join %.0f us, rounds %.0f us\n",
                    (unsigned long long)iters, (unsigned long long)joined, t_join, t_round);
