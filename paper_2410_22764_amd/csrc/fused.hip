@@ -90,6 +90,7 @@ template <int MAXN, int NT>
 __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs, FusedRes* __restrict__ res,
                                               uint32_t njobs, FusedJob one) {
   static_assert(MAXN % NT == 0 && MAXN <= (1 << 14) && (MAXN / NT) % kChunk == 0, "fused tile: ids fit 14 bits");
+  static_assert(MAXN / NT <= 32, "accept bits of a thread's states fit one word");
   static_assert(((3u * MAXN) / 2u - 64u) % kBucket == 0, "table of whole buckets");
   constexpr int ITEMS = MAXN / NT;
   constexpr uint32_t NW = NT / 64;
@@ -117,23 +118,46 @@ __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs,
   }
   __syncthreads();
 
-  // ---- validation (every entry < n) and identity letters (Section 2)
+  // ---- validation (every entry < n) and identity letters (Section 2).
+  // Thread tid owns states tid + i*NT, i < ITEMS (n <= MAXN); its loads of
+  // one row go out together, so each row costs one memory latency.
+  uint32_t fbits = 0;  // accept bit of owned state i in bit i
   {
     uint32_t bad = 0, nonid = 0;
     for (uint32_t a = 0; a < k; ++a) {
       const uint32_t* __restrict__ row = delta + (size_t)a * n;
+      uint32_t v[ITEMS];
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t q = tid + (uint32_t)i * NT;
+        v[i] = q < n ? row[q] : q;
+      }
       uint32_t d = 0;
-      for (uint32_t q = tid; q < n; q += NT) {
-        const uint32_t v = row[q];
-        bad |= (uint32_t)(v >= n);
-        d |= (uint32_t)(v != q);
+#pragma unroll
+      for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t q = tid + (uint32_t)i * NT;
+        bad |= (uint32_t)(q < n && v[i] >= n);
+        d |= (uint32_t)(v[i] != q);
       }
       if (d) nonid |= 1u << a;
     }
+    uint8_t ab[ITEMS];
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t q = tid + (uint32_t)i * NT;
+      ab[i] = q < n ? acc[q >> 3] : 0u;
+    }
     uint32_t mf = kNone, mn = kNone;
-    for (uint32_t q = tid; q < n; q += NT) {
-      if ((acc[q >> 3] >> (q & 7)) & 1u) mf = min(mf, q);
-      else mn = min(mn, q);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const uint32_t q = tid + (uint32_t)i * NT;
+      if (q >= n) continue;
+      if ((ab[i] >> (q & 7)) & 1u) {
+        mf = min(mf, q);
+        fbits |= 1u << i;
+      } else {
+        mn = min(mn, q);
+      }
     }
     bad = wave_or(bad);
     nonid = wave_or(nonid);
@@ -165,12 +189,15 @@ __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs,
   const uint32_t l1 = m1 ? (uint32_t)__ffs(m1) - 1u : 0u;
   // ---- initial partition {F, Q\F}; ids are least members (Section 3.2)
   uint32_t count = (minF < n ? 1u : 0u) + (minN < n ? 1u : 0u);
-  for (uint32_t q = tid; q < n; q += NT) {
-    const bool f = (acc[q >> 3] >> (q & 7)) & 1u;
+#pragma unroll
+  for (int i = 0; i < ITEMS; ++i) {
+    const uint32_t q = tid + (uint32_t)i * NT;
+    if (q >= n) continue;
+    const bool f = (fbits >> i) & 1u;
     blk[q] = (uint16_t)(f ? minF : minN);
     // a doubling instance keeps its closure level in lvl[]; any other
     // starts with its accept bit there, the exact label of its class
-    lvl[q] = dbl ? (uint16_t)delta[(size_t)(__ffs(mask) - 1) * n + q] : (uint16_t)f;
+    lvl[q] = dbl ? (uint16_t)delta[(size_t)l0 * n + q] : (uint16_t)f;
   }
   // > n slots, so an empty one always exists
   const uint32_t S = min(SMAX, max(64u, (n + n / 2u + kBucket - 1u) & ~(kBucket - 1u)));
@@ -260,13 +287,36 @@ __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs,
     // a direct round keeps each state's key behind the table, 16 bits each
     uint16_t* const keyat = reinterpret_cast<uint16_t*>(slot + T);
     if (direct) {
+      // with one or two signature letters the successors of kChunk states
+      // of the thread are loaded together, as in the hash rounds
+      const bool pre = knon <= 2u;
 #pragma unroll 1
-      for (int i = 0; i < ITEMS; ++i) {
-        const uint32_t q = tid + (uint32_t)i * NT;
+      for (int c0 = 0; c0 < ITEMS; c0 += kChunk) {
+      uint32_t pf[kChunk];
+      if (pre) {
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+          const uint32_t q = tid + (uint32_t)(c0 + i) * NT;
+          pf[i] = 0;
+          if (q < n && knon > 0u) {
+            pf[i] = delta[(size_t)l0 * n + q];
+            if (knon > 1u) pf[i] |= delta[(size_t)l1 * n + q] << 16;
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i) {
+        const uint32_t q = tid + (uint32_t)(c0 + i) * NT;
         if (q >= n || (blk[q] & kSingle)) continue;
-        uint32_t key = lvl[q], at = lw;
-        for (uint32_t mm = mask; mm; mm &= mm - 1u, at += lw)
-          key |= (uint32_t)lvl[delta[(size_t)(__ffs(mm) - 1) * n + q]] << at;
+        uint32_t key = lvl[q];
+        if (pre) {
+          if (knon > 0u) key |= (uint32_t)lvl[pf[i] & 0xFFFFu] << lw;
+          if (knon > 1u) key |= (uint32_t)lvl[pf[i] >> 16] << (2u * lw);
+        } else {
+          uint32_t at = lw;
+          for (uint32_t mm = mask; mm; mm &= mm - 1u, at += lw)
+            key |= (uint32_t)lvl[delta[(size_t)(__ffs(mm) - 1) * n + q]] << at;
+        }
         keyat[q] = (uint16_t)key;
         const uint32_t want = (q + 1u) << 1;
         uint32_t v = slot[key];
@@ -276,6 +326,7 @@ __global__ void __launch_bounds__(NT) k_fused(const FusedJob* __restrict__ jobs,
         }
         if (((v >> 1) & kIdMask) - 1u > q) atomicMin(&slot[key], want | kShared);
         else if (!(v & kShared)) atomicOr(&slot[key], kShared);
+      }
       }
     } else {
     // (a plain instance keeps each state's slot in lvl[], which only
